@@ -258,7 +258,11 @@ int orc_costs(int32_t n, const int64_t *off, const int32_t *col, const int32_t *
  *   Later tasks (Eq. (2)): with C the cost target reached so far (C = H after
  *     the initial tasks), the next target is C + max(ceil((total - C) / W),
  *     min_chunk); the task ends at the first x with F(x) >= that target; this
- *     repeats until the target reaches total, and the last task ends at n.
+ *     repeats until the target reaches total, and that last task ends at n.
+ *     When no later task is needed, one final task ends at n.  The remaining
+ *     cost is measured from the last target, not from the node boundary it
+ *     fell on (they differ by less than one position's cost); this makes
+ *     every boundary an independent search.
  * Boundaries are written to bnd[0..ntasks] (bnd[0] = 0, bnd[ntasks] = n);
  * tasks may be empty when one position's cost spans several targets (the
  * atomic task of Section V-A cannot be split).  Returns ORC_EINVAL when cap
@@ -294,6 +298,7 @@ int orc_schedule(int32_t n, const int64_t *f, int32_t W, int64_t min_chunk, int3
     t[k++] = 0;
     for (int32_t i = 0; i < W; ++i) t[k++] = (int32_t)first_reaching(F, n, ((int64_t)(i + 1) * H + W - 1) / W);
     int64_t C = H;
+    int ended = 0;
     while (C < total) {
         int64_t step = (total - C + W - 1) / W;
         if (step < min_chunk) step = min_chunk;
@@ -308,9 +313,14 @@ int orc_schedule(int32_t n, const int64_t *f, int32_t W, int64_t min_chunk, int3
             }
             t = g;
         }
-        t[k++] = C >= total ? n : (int32_t)first_reaching(F, n, C);
+        if (C >= total) {
+            t[k++] = n; /* the target that reaches the total ends the last task at n */
+            ended = 1;
+        } else {
+            t[k++] = (int32_t)first_reaching(F, n, C);
+        }
     }
-    if (t[k - 1] != n) {
+    if (!ended) {
         if (k == tcap) {
             int32_t *g = (int32_t *)realloc(t, (size_t)(tcap + 1) * sizeof(int32_t));
             if (!g) {
@@ -320,7 +330,7 @@ int orc_schedule(int32_t n, const int64_t *f, int32_t W, int64_t min_chunk, int3
             }
             t = g;
         }
-        t[k++] = n; /* trailing zero-cost positions join a final task */
+        t[k++] = n; /* no later task: one final task ends at n */
     }
     *ntasks = k - 1;
     int rc = ORC_OK;
