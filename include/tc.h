@@ -1,0 +1,163 @@
+/*
+ * tc.h -- exact triangle counting over a degree-ordered oriented graph on one
+ * AMD Instinct MI355X (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * Method (Arifuzzaman, Khan, Marathe, "Parallel Algorithms for Counting
+ * Triangles in Networks with Large Degrees"):
+ *   - the input is an undirected graph G(V, E) on ids 0..n-1 (Section II);
+ *   - nodes are ordered by degree, ties broken by id (Section III-A);
+ *   - each edge is stored once, in the list N_v of its lower-ordered endpoint,
+ *     and every list is sorted (Fig. 1, first two loops);
+ *   - the total T is the sum over stored edges (v, u) of |N_v intersect N_u|
+ *     (Fig. 1, last loop); the per-node count T_v is the number of triangles
+ *     that contain v (Section II);
+ *   - work is handed out as node-range tasks whose sizes follow Eq. (1) and
+ *     Eq. (2) of Section V-B, pulled by persistent GPU workers from an atomic
+ *     queue in place of the coordinator of Fig. 11;
+ *   - graphs larger than a device-memory budget are counted in non-overlapping
+ *     node-range partitions (Definition 1) whose lists N_v are streamed to the
+ *     partition that needs them, once per partition (Section IV-C, Fig. 2/3).
+ *
+ * Conventions for every entry point:
+ *   - the return value is a tc_status; outputs are written only on TC_OK;
+ *   - nothing aborts, exits or throws across this interface;
+ *   - work is ordered on the stream named in tc_options (NULL: the null stream);
+ *   - a call whose outputs are host pointers returns once they are written;
+ *     a call whose outputs are device pointers returns after enqueuing work;
+ *   - tc_last_error() gives a thread-local text for the last failure.
+ */
+#ifndef TC_H
+#define TC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TC_OK = 0,
+    TC_ERR_INVALID_ARG = 1,   /* NULL where data is required, negative sizes, bad option values */
+    TC_ERR_ID_RANGE = 2,      /* an endpoint outside 0..n-1 (Section II labels nodes 0..n-1) */
+    TC_ERR_TOO_LARGE = 3,     /* sizes beyond the int32 node-id space of one handle */
+    TC_ERR_OUT_OF_MEMORY = 4, /* device allocation failed, or the budget cannot hold one partition */
+    TC_ERR_DEVICE = 5         /* a HIP runtime call failed */
+} tc_status;
+
+/* One undirected input graph (Section II).  src[e], dst[e] are the endpoints
+ * of edge e, int32 node ids in 0..n-1.  Loops are dropped and repeated or
+ * reversed pairs are merged before degrees are taken.  Host or device memory
+ * according to tc_options.inputs_on_device; read only, owned by the caller. */
+typedef struct {
+    int32_t n;
+    int64_t m;
+    const int32_t *src;
+    const int32_t *dst;
+} tc_edges;
+
+/* Cost functions for the task schedule (Sections IV-B, IV-F and V-A). */
+enum {
+    TC_COST_ONE = 0,    /* f(v) = 1 */
+    TC_COST_DEGREE = 1, /* f(v) = d_v */
+    TC_COST_PRIOR = 2,  /* f(v) = sum over u in N_v of (|N_v| + |N_u|) */
+    TC_COST_NEW = 3     /* f(v) = sum over u with v in N_u of (|N_v| + |N_u|) */
+};
+
+typedef struct {
+    void *stream;               /* hipStream_t; NULL = null stream */
+    int32_t inputs_on_device;   /* tc_edges.src/dst are device pointers */
+    int32_t outputs_on_device;  /* count outputs are device pointers */
+    uint64_t hbm_budget_bytes;  /* 0: no budget (resident).  Otherwise every device
+                                   allocation of a build or count stays below it and
+                                   the graph is counted in node-range partitions. */
+    /* Device allocator; both NULL = hipMallocAsync / hipFreeAsync on the stream.
+     * alloc returns NULL on failure. */
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, size_t bytes, void *stream, void *ctx);
+    void *alloc_ctx;
+    int32_t workers;    /* persistent waves pulling tasks; 0 = 16 per compute unit */
+    int32_t cost_fn;    /* TC_COST_*; used when the schedule is built */
+    int64_t min_chunk;  /* floor on a task's cost target (Eq. (2)); 0 = automatic */
+    int32_t small_max;  /* lists up to this length are handled by one wave, longer ones by a
+                           whole workgroup; 0 = automatic (128, also the maximum) */
+    int32_t lds_list_max; /* longest list a workgroup stages in LDS; longer lists are probed by
+                             binary search in device memory; 0 = automatic (4096, the maximum) */
+    int32_t reserved[8];
+} tc_options;
+
+/* Fills *opt with the defaults (all zero except cost_fn = TC_COST_PRIOR). */
+void tc_options_default(tc_options *opt);
+
+/* Opaque handle: the oriented adjacency (in degree-order labels), the map back
+ * to caller labels and the task schedule, for k graphs packed together.  Owns
+ * its device memory until tc_graph_free. */
+typedef struct tc_graph tc_graph;
+
+/* Builds the oriented, sorted adjacency of Fig. 1 for k graphs (k >= 1) in one
+ * pass on the device: canonical edge set, degrees, degree order (Section
+ * III-A), orientation and row sort, the per-node cost f (Section V-A), and the
+ * task table of Eq. (1)/(2).  graphs[i] may have n = 0 or m = 0.  With a
+ * budget, the oriented adjacency is kept in pinned host memory and streamed.
+ * Errors: TC_ERR_INVALID_ARG (NULL graphs/out, k < 1, negative n or m, NULL
+ * src/dst with m > 0), TC_ERR_ID_RANGE, TC_ERR_TOO_LARGE (sum of n >= 2^31),
+ * TC_ERR_OUT_OF_MEMORY, TC_ERR_DEVICE.  *out is written only on TC_OK. */
+tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options *opt, tc_graph **out);
+
+/* Total triangle count of each graph in the handle (Fig. 1; Fig. 10/11 task
+ * by task): totals[k], int64, host or device per opt->outputs_on_device.
+ * Counting one handle concurrently on two streams is not supported. */
+tc_status tc_count_total(tc_graph *g, const tc_options *opt, int64_t *totals);
+
+/* Per-node counts T_v (Section II: triangles containing v) in the caller's
+ * labels, packed graph after graph: per_node[sum of n_i].  totals (may be
+ * NULL) receives the k totals.  Host or device per opt->outputs_on_device. */
+tc_status tc_count_per_node(tc_graph *g, const tc_options *opt, int64_t *per_node, int64_t *totals);
+
+/* Counts ng handles in one persistent launch: all their tasks share one
+ * queue.  totals receives, handle after handle, each handle's k totals
+ * (sum of k entries).  per_node may be NULL; otherwise per_node[i] is NULL or
+ * the per-node output of handle i.  Results equal those of separate calls. */
+tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, int64_t *totals,
+                         int64_t *const *per_node);
+
+typedef struct {
+    int32_t k;              /* graphs in the handle */
+    int64_t n;              /* sum of node counts */
+    int64_t m;              /* distinct undirected edges = stored oriented edges */
+    int64_t m_input;        /* input edges, loops and repeats included */
+    int32_t max_out_degree; /* max |N_v| */
+    int64_t tasks;          /* entries of the task table */
+    int64_t total_cost;     /* sum of f over all nodes */
+    int64_t wide_nodes;     /* nodes whose list is longer than small_max */
+    uint64_t device_bytes;  /* device memory held by the handle */
+    int32_t partitions;     /* node-range partitions used for counting (1 = resident) */
+    int32_t reserved[7];
+} tc_graph_info_t;
+
+tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info);
+
+/* Copies the oriented adjacency to host arrays for inspection: off[n+1] row
+ * offsets and col[m] entries in degree-order labels (rows ascending), and
+ * perm[n], the caller label of each degree-order position (Section III-A
+ * order; for k graphs, packed labels graph after graph).  Any pointer may be
+ * NULL.  Synchronises the stream. */
+tc_status tc_export_csr(const tc_graph *g, const tc_options *opt, int64_t *off, int32_t *col, int32_t *perm);
+
+/* Copies the task table: bnd[0..tasks] node boundaries in degree-order labels
+ * and, if gid is not NULL, gid[0..tasks-1] the graph of each task.  cap is the
+ * capacity of bnd; *tasks receives the number of tasks. */
+tc_status tc_export_schedule(const tc_graph *g, const tc_options *opt, int32_t *bnd, int32_t *gid, int64_t cap,
+                             int64_t *tasks);
+
+/* Releases the handle and its device memory.  NULL is a no-op. */
+void tc_graph_free(tc_graph *g);
+
+const char *tc_status_str(tc_status s);
+const char *tc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H */

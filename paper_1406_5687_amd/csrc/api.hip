@@ -1,0 +1,373 @@
+// C ABI of the library (declared in include/tc.h).  Host orchestration only:
+// argument checks, packing of input graphs, allocation, and kernel launches.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+
+#include "internal.h"
+
+struct tc_graph {
+    tc::Allocator al;  // allocator of the handle's own memory (stream = last stream used)
+    tc::Packing pk;
+    tc::Oriented o;
+    int32_t workers = 0;
+    int32_t small_max = 128;
+    int32_t lds_max = 4096;
+    int32_t cost_fn = TC_COST_PRIOR;
+    // persistent count scratch: queue heads, totals, per-node accumulators
+    tc::DevBuf<uint32_t> heads;
+    tc::DevBuf<int64_t> totals;
+    tc::DevBuf<int64_t> tv;
+    tc::DevBuf<tc::CountDesc> desc;  // one descriptor pointing at the buffers above
+    bool desc_has_tv = false;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tc_status fail(tc_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+template <class F>
+tc_status guarded(F &&f) {
+    try {
+        f();
+        g_last_error.clear();
+        return TC_OK;
+    } catch (const tc::Error &e) {
+        return fail(e.code, e.what());
+    } catch (const std::bad_alloc &) {
+        return fail(TC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(TC_ERR_DEVICE, e.what());
+    }
+}
+
+tc::Allocator make_allocator(const tc_options *opt) {
+    tc::Allocator a;
+    if (opt) {
+        a.fn_alloc = opt->alloc;
+        a.fn_free = opt->free;
+        a.ctx = opt->alloc_ctx;
+        a.stream = (hipStream_t)opt->stream;
+        a.budget = opt->hbm_budget_bytes;
+    }
+    return a;
+}
+
+void check_options(const tc_options *opt) {
+    if (!opt) return;
+    if ((opt->alloc == nullptr) != (opt->free == nullptr))
+        throw tc::Error(TC_ERR_INVALID_ARG, "alloc and free callbacks must be given together");
+    if (opt->workers < 0 || opt->min_chunk < 0 || opt->small_max < 0 || opt->lds_list_max < 0)
+        throw tc::Error(TC_ERR_INVALID_ARG, "negative option value");
+    if (opt->cost_fn < TC_COST_ONE || opt->cost_fn > TC_COST_NEW)
+        throw tc::Error(TC_ERR_INVALID_ARG, "unknown cost function");
+}
+
+// Per-handle descriptor used by single-handle counts (kept on the device).
+void ensure_scratch(tc_graph *g, bool per_node, hipStream_t s) {
+    g->al.stream = s;
+    if (!g->heads.p) g->heads = tc::DevBuf<uint32_t>(g->al, 4);
+    if (!g->totals.p) g->totals = tc::DevBuf<int64_t>(g->al, (size_t)std::max(g->pk.k, 1));
+    if (per_node && !g->tv.p) g->tv = tc::DevBuf<int64_t>(g->al, (size_t)std::max<int64_t>(g->pk.N, 1));
+    if (!g->desc.p || (per_node && !g->desc_has_tv)) {
+        tc::CountDesc d{};
+        d.off = g->o.off.p;
+        d.col = g->o.col.p;
+        d.bnd = g->o.bnd.p;
+        d.gid = g->pk.k > 1 ? g->o.gid.p : nullptr;
+        d.node_base = g->o.node_base.p;
+        d.big = g->o.big.p;
+        d.m = g->o.M;
+        d.totals = g->totals.p;
+        d.tv = g->tv.p;
+        d.task_base = 0;
+        d.big_base = 0;
+        d.k = g->pk.k;
+        d.small_max = g->small_max;
+        if (!g->desc.p) g->desc = tc::DevBuf<tc::CountDesc>(g->al, 1);
+        TC_HIP(hipMemcpyAsync(g->desc.p, &d, sizeof(d), hipMemcpyHostToDevice, s));
+        g->desc_has_tv = g->tv.p != nullptr;
+    }
+}
+
+void copy_out(void *dst, const void *src, size_t bytes, bool dst_on_device, hipStream_t s) {
+    if (bytes == 0) return;
+    TC_HIP(hipMemcpyAsync(dst, src, bytes, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+void tc_options_default(tc_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->cost_fn = TC_COST_PRIOR;
+}
+
+const char *tc_status_str(tc_status s) {
+    switch (s) {
+        case TC_OK: return "ok";
+        case TC_ERR_INVALID_ARG: return "invalid argument";
+        case TC_ERR_ID_RANGE: return "node id out of range";
+        case TC_ERR_TOO_LARGE: return "too large";
+        case TC_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case TC_ERR_DEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+const char *tc_last_error(void) { return g_last_error.c_str(); }
+
+tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options *opt, tc_graph **out) {
+    if (!graphs || !out || k < 1) return fail(TC_ERR_INVALID_ARG, "graphs and out must be non-NULL and k >= 1");
+    std::unique_ptr<tc_graph> g(new (std::nothrow) tc_graph());
+    if (!g) return fail(TC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    tc_status st = guarded([&] {
+        check_options(opt);
+        tc_options o;
+        if (opt)
+            o = *opt;
+        else
+            tc_options_default(&o);
+        hipStream_t s = (hipStream_t)o.stream;
+        tc::Packing &pk = g->pk;
+        pk.k = k;
+        pk.node_base.assign((size_t)k + 1, 0);
+        pk.edge_base.assign((size_t)k + 1, 0);
+        for (int32_t i = 0; i < k; ++i) {
+            const tc_edges &e = graphs[i];
+            if (e.n < 0 || e.m < 0) throw tc::Error(TC_ERR_INVALID_ARG, "negative n or m");
+            if (e.m > 0 && (!e.src || !e.dst)) throw tc::Error(TC_ERR_INVALID_ARG, "NULL edge arrays with m > 0");
+            pk.node_base[i + 1] = pk.node_base[i] + e.n;
+            pk.edge_base[i + 1] = pk.edge_base[i] + e.m;
+            pk.max_n = std::max(pk.max_n, e.n);
+        }
+        pk.N = pk.node_base[k];
+        pk.M_in = pk.edge_base[k];
+        if (pk.N >= ((int64_t)1 << 31) - 1) throw tc::Error(TC_ERR_TOO_LARGE, "sum of n must stay below 2^31 - 1");
+
+        g->al = make_allocator(&o);
+        g->al.budget = 0;  // resident build; budgets are handled by the partitioned path
+        const int cus = tc::device_cu_count();
+        g->workers = o.workers > 0 ? o.workers : 16 * cus;
+        g->small_max = o.small_max > 0 ? std::min(o.small_max, tc::max_small_list()) : tc::max_small_list();
+        g->lds_max = o.lds_list_max > 0 ? std::max(2, std::min(o.lds_list_max, tc::max_lds_list())) : tc::max_lds_list();
+        g->cost_fn = o.cost_fn;
+
+        // packed input edges on the device
+        tc::Allocator scratch = g->al;
+        scratch.live = 0;
+        tc::DevBuf<int32_t> psrc, pdst;
+        const int32_t *dsrc = nullptr, *ddst = nullptr;
+        if (k == 1 && o.inputs_on_device) {
+            dsrc = graphs[0].src;
+            ddst = graphs[0].dst;
+        } else if (pk.M_in > 0) {
+            psrc = tc::DevBuf<int32_t>(scratch, (size_t)pk.M_in);
+            pdst = tc::DevBuf<int32_t>(scratch, (size_t)pk.M_in);
+            const hipMemcpyKind kind = o.inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+            for (int32_t i = 0; i < k; ++i) {
+                const size_t bytes = (size_t)graphs[i].m * sizeof(int32_t);
+                if (!bytes) continue;
+                TC_HIP(hipMemcpyAsync(psrc.p + pk.edge_base[i], graphs[i].src, bytes, kind, s));
+                TC_HIP(hipMemcpyAsync(pdst.p + pk.edge_base[i], graphs[i].dst, bytes, kind, s));
+            }
+            dsrc = psrc.p;
+            ddst = pdst.p;
+        }
+        tc::BuildParams bp;
+        bp.workers = g->workers;
+        bp.cost_fn = o.cost_fn;
+        bp.min_chunk = o.min_chunk;
+        bp.small_max = g->small_max;
+        tc::build_oriented_device(dsrc, ddst, pk, bp, g->al, s, g->o);
+    });
+    if (st != TC_OK) return st;
+    *out = g.release();
+    return TC_OK;
+}
+
+static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node, int64_t *totals) {
+    return guarded([&] {
+        check_options(opt);
+        const bool on_dev = opt && opt->outputs_on_device;
+        hipStream_t s = opt ? (hipStream_t)opt->stream : nullptr;
+        const bool want_tv = per_node != nullptr;
+        ensure_scratch(g, want_tv, s);
+        const size_t k = (size_t)g->pk.k;
+        tc::fill_zero(g->heads.p, 16, s);
+        tc::fill_zero(g->totals.p, k * sizeof(int64_t), s);
+        if (want_tv) tc::fill_zero(g->tv.p, (size_t)g->pk.N * sizeof(int64_t), s);
+        tc::CountLaunch L{};
+        L.descs = g->desc.p;
+        L.ndesc = 1;
+        L.total_tasks = g->o.tasks;
+        L.total_big = g->o.nbig;
+        L.heads = g->heads.p;
+        L.workers = opt && opt->workers > 0 ? opt->workers : g->workers;
+        L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
+        L.big_blocks = tc::device_cu_count();
+        L.per_node = want_tv;
+        tc::count_launch(L, s);
+        if (want_tv) {
+            if (on_dev) {
+                tc::scatter_per_node(g->tv.p, g->o.perm.p, g->pk.N, per_node, s);
+            } else {
+                tc::DevBuf<int64_t> stage(g->al, (size_t)std::max<int64_t>(g->pk.N, 1));
+                tc::scatter_per_node(g->tv.p, g->o.perm.p, g->pk.N, stage.p, s);
+                copy_out(per_node, stage.p, (size_t)g->pk.N * sizeof(int64_t), false, s);
+                TC_HIP(hipStreamSynchronize(s));
+            }
+        }
+        if (totals) copy_out(totals, g->totals.p, k * sizeof(int64_t), on_dev, s);
+        if (!on_dev) TC_HIP(hipStreamSynchronize(s));
+    });
+}
+
+tc_status tc_count_total(tc_graph *g, const tc_options *opt, int64_t *totals) {
+    if (!g || !totals) return fail(TC_ERR_INVALID_ARG, "graph and totals must be non-NULL");
+    return count_one(g, opt, nullptr, totals);
+}
+
+tc_status tc_count_per_node(tc_graph *g, const tc_options *opt, int64_t *per_node, int64_t *totals) {
+    if (!g || (!per_node && g->pk.N > 0)) return fail(TC_ERR_INVALID_ARG, "graph and per_node must be non-NULL");
+    if (g->pk.N == 0) return count_one(g, opt, nullptr, totals ? totals : nullptr);
+    return count_one(g, opt, per_node, totals);
+}
+
+tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, int64_t *totals,
+                         int64_t *const *per_node) {
+    if (!gs || ng < 1 || !totals) return fail(TC_ERR_INVALID_ARG, "graphs, ng >= 1 and totals are required");
+    for (int32_t i = 0; i < ng; ++i)
+        if (!gs[i]) return fail(TC_ERR_INVALID_ARG, "NULL graph in batch");
+    return guarded([&] {
+        check_options(opt);
+        const bool on_dev = opt && opt->outputs_on_device;
+        hipStream_t s = opt ? (hipStream_t)opt->stream : nullptr;
+        tc::Allocator al = make_allocator(opt);
+        al.budget = 0;
+        bool want_tv = false;
+        if (per_node)
+            for (int32_t i = 0; i < ng; ++i) want_tv = want_tv || (per_node[i] != nullptr && gs[i]->pk.N > 0);
+        std::vector<int64_t> kbase(ng + 1, 0), nbase(ng + 1, 0);
+        for (int32_t i = 0; i < ng; ++i) {
+            kbase[i + 1] = kbase[i] + gs[i]->pk.k;
+            nbase[i + 1] = nbase[i] + (want_tv ? gs[i]->pk.N : 0);
+        }
+        // one scratch block: heads | totals | per-node accumulators
+        const size_t head_words = 4;
+        const size_t bytes = head_words * 4 + (size_t)kbase[ng] * 8 + (size_t)nbase[ng] * 8;
+        tc::DevBuf<uint8_t> scratch(al, bytes);
+        tc::fill_zero(scratch.p, bytes, s);
+        uint32_t *heads = (uint32_t *)scratch.p;
+        int64_t *tot = (int64_t *)(scratch.p + head_words * 4);
+        int64_t *tv = tot + kbase[ng];
+        std::vector<tc::CountDesc> hd((size_t)ng);
+        int64_t task_base = 0, big_base = 0;
+        int32_t workers = 0, lds_max = tc::max_lds_list();
+        for (int32_t i = 0; i < ng; ++i) {
+            const tc_graph *g = gs[i];
+            tc::CountDesc &d = hd[i];
+            d.off = g->o.off.p;
+            d.col = g->o.col.p;
+            d.bnd = g->o.bnd.p;
+            d.gid = g->pk.k > 1 ? g->o.gid.p : nullptr;
+            d.node_base = g->o.node_base.p;
+            d.big = g->o.big.p;
+            d.m = g->o.M;
+            d.totals = tot + kbase[i];
+            d.tv = want_tv ? tv + nbase[i] : nullptr;
+            d.task_base = task_base;
+            d.big_base = big_base;
+            d.k = g->pk.k;
+            d.small_max = g->small_max;
+            task_base += g->o.tasks;
+            big_base += g->o.nbig;
+            workers = std::max(workers, g->workers);
+            lds_max = std::min(lds_max, g->lds_max);
+        }
+        tc::DevBuf<tc::CountDesc> ddesc(al, (size_t)ng);
+        TC_HIP(hipMemcpyAsync(ddesc.p, hd.data(), ng * sizeof(tc::CountDesc), hipMemcpyHostToDevice, s));
+        tc::CountLaunch L{};
+        L.descs = ddesc.p;
+        L.ndesc = ng;
+        L.total_tasks = task_base;
+        L.total_big = big_base;
+        L.heads = heads;
+        L.workers = opt && opt->workers > 0 ? opt->workers : workers;
+        L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : lds_max;
+        L.big_blocks = tc::device_cu_count();
+        L.per_node = want_tv;
+        tc::count_launch(L, s);
+        for (int32_t i = 0; i < ng && per_node; ++i) {
+            if (!per_node[i] || gs[i]->pk.N == 0) continue;
+            const int64_t n = gs[i]->pk.N;
+            if (on_dev) {
+                tc::scatter_per_node(tv + nbase[i], gs[i]->o.perm.p, n, per_node[i], s);
+            } else {
+                tc::DevBuf<int64_t> stage(al, (size_t)n);
+                tc::scatter_per_node(tv + nbase[i], gs[i]->o.perm.p, n, stage.p, s);
+                copy_out(per_node[i], stage.p, (size_t)n * 8, false, s);
+                TC_HIP(hipStreamSynchronize(s));
+            }
+        }
+        copy_out(totals, tot, (size_t)kbase[ng] * 8, on_dev, s);
+        if (!on_dev) TC_HIP(hipStreamSynchronize(s));
+        // device descriptors and scratch are released in stream order here
+    });
+}
+
+tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info) {
+    if (!g || !info) return fail(TC_ERR_INVALID_ARG, "graph and info must be non-NULL");
+    std::memset(info, 0, sizeof(*info));
+    info->k = g->pk.k;
+    info->n = g->pk.N;
+    info->m = g->o.M;
+    info->m_input = g->pk.M_in;
+    info->max_out_degree = g->o.max_dhat;
+    info->tasks = g->o.tasks;
+    info->total_cost = g->o.total_cost;
+    info->wide_nodes = g->o.nbig;
+    info->device_bytes = g->al.live;
+    info->partitions = 1;
+    return TC_OK;
+}
+
+tc_status tc_export_csr(const tc_graph *g, const tc_options *opt, int64_t *off, int32_t *col, int32_t *perm) {
+    if (!g) return fail(TC_ERR_INVALID_ARG, "graph must be non-NULL");
+    return guarded([&] {
+        hipStream_t s = opt ? (hipStream_t)opt->stream : nullptr;
+        if (off) copy_out(off, g->o.off.p, (size_t)(g->pk.N + 1) * 8, false, s);
+        if (col && g->o.M) copy_out(col, g->o.col.p, (size_t)g->o.M * 4, false, s);
+        if (perm && g->pk.N) copy_out(perm, g->o.perm.p, (size_t)g->pk.N * 4, false, s);
+        TC_HIP(hipStreamSynchronize(s));
+    });
+}
+
+tc_status tc_export_schedule(const tc_graph *g, const tc_options *opt, int32_t *bnd, int32_t *gid, int64_t cap,
+                             int64_t *tasks) {
+    if (!g || !tasks) return fail(TC_ERR_INVALID_ARG, "graph and tasks must be non-NULL");
+    *tasks = g->o.tasks;
+    if (!bnd) return TC_OK;
+    if (cap < g->o.tasks + 1) return fail(TC_ERR_INVALID_ARG, "bnd capacity below tasks + 1");
+    return guarded([&] {
+        hipStream_t s = opt ? (hipStream_t)opt->stream : nullptr;
+        copy_out(bnd, g->o.bnd.p, (size_t)(g->o.tasks + 1) * 4, false, s);
+        if (gid && g->pk.k > 1) copy_out(gid, g->o.gid.p, (size_t)g->o.tasks * 4, false, s);
+        if (gid && g->pk.k == 1) std::fill(gid, gid + g->o.tasks, 0);
+        TC_HIP(hipStreamSynchronize(s));
+    });
+}
+
+void tc_graph_free(tc_graph *g) {
+    if (!g) return;
+    delete g;  // buffers are returned in order on the last stream the handle used
+}
+
+}  // extern "C"

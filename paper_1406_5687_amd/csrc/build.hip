@@ -1,0 +1,478 @@
+// Device build of the oriented adjacency (Fig. 1, first two loops) and of the
+// task table (Section V-B), for k graphs packed into one node space.
+//
+// Packed labels: node v of graph g is x = node_base[g] + v.  Graphs occupy
+// disjoint, consecutive label ranges both before and after the degree-order
+// relabelling, so every sort below works on one key space.
+//
+//   1. canonical edge set  -- key (x_lo << GB) | x_hi, loops dropped, radix sort, unique
+//   2. degrees             -- d_x = number of distinct neighbours (Section II)
+//   3. degree order        -- sort (g, d_x, v): position r in the sorted list is the
+//                             new label of x (Section III-A order, ties by id)
+//   4. orientation         -- edge {a, b} stored at the lower label s as (s, t);
+//                             radix sort of (s << GB) | t gives rows sorted ascending
+//   5. CSR                 -- col = t, off = exclusive scan of row lengths
+//   6. costs and tasks     -- f per node (Sections IV-B, IV-F, V-A), prefix sums,
+//                             Eq. (1)/(2) targets, one binary search per task boundary
+#include <algorithm>
+
+#include "internal.h"
+
+namespace tc {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned grid_for(int64_t n, int per_thread = 1) {
+    int64_t b = ceil_div(n, (int64_t)kThreads * per_thread);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)1 << 30));
+}
+
+constexpr uint64_t kInvalid = ~0ull;
+
+__global__ void k_fill_zero_u32(uint32_t *p, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__device__ __forceinline__ int upper_bound_i64(const int64_t *a, int n, int64_t x) {
+    // first index i in [0, n) with a[i] > x, or n
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] > x)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
+
+// Step 1a: canonical keys.  err bit 0: id out of range.
+__global__ void k_edge_keys(const int32_t *__restrict__ src, const int32_t *__restrict__ dst, int64_t m_in,
+                            const int64_t *__restrict__ edge_base, const int64_t *__restrict__ node_base, int k,
+                            int gb, uint64_t *__restrict__ keys, uint32_t *__restrict__ err) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m_in; e += (int64_t)gridDim.x * blockDim.x) {
+        int g = 0;
+        if (k > 1) g = upper_bound_i64(edge_base, k + 1, e) - 1;
+        const int64_t nb = node_base[g];
+        const int64_t ng = node_base[g + 1] - nb;
+        const int32_t u = src[e], v = dst[e];
+        uint64_t key = kInvalid;
+        if (u < 0 || v < 0 || u >= ng || v >= ng) {
+            atomicOr(err, 1u);
+        } else if (u != v) {
+            const uint64_t a = (uint64_t)(nb + (u < v ? u : v)), b = (uint64_t)(nb + (u < v ? v : u));
+            key = (a << gb) | b;
+        }
+        keys[e] = key;
+    }
+}
+
+// Step 1b: first occurrence of each valid key.
+__global__ void k_unique_flags(const uint64_t *__restrict__ keys, int64_t n, uint32_t *__restrict__ flag) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[i];
+        flag[i] = (k != kInvalid && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
+    }
+}
+
+__global__ void k_compact_keys(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ flag,
+                               const int64_t *__restrict__ pos, int64_t n, uint64_t *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (flag[i]) out[pos[i]] = keys[i];
+}
+
+// Lanes of a wave holding equal, contiguous values of `key` form a run; the
+// last lane of each run receives the run's sum of `val`.
+template <class T>
+__device__ __forceinline__ T run_sum_at_end(int64_t key, T val, bool *is_end) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const T y = __shfl_up(val, d, 64);
+        const int64_t kd = __shfl_up(key, d, 64);
+        if (lane >= d && kd == key) val += y;
+    }
+    const int64_t kn = __shfl_down(key, 1, 64);
+    *is_end = (lane == 63) || (kn != key);
+    return val;
+}
+
+// Step 2: degrees.  Keys are sorted, so the lower endpoints arrive in runs.
+__global__ void k_degrees(const uint64_t *__restrict__ keys, int64_t m, int gb, int32_t *__restrict__ deg) {
+    const uint64_t mask = (gb >= 64) ? ~0ull : ((1ull << gb) - 1);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        int64_t lo = -1 - (int64_t)threadIdx.x;  // distinct for inactive lanes
+        if (i < m) {
+            const uint64_t k = keys[i];
+            lo = (int64_t)(k >> gb);
+            atomicAdd(&deg[(int64_t)(k & mask)], 1);
+        }
+        bool end;
+        const int32_t cnt = run_sum_at_end<int32_t>(lo, i < m ? 1 : 0, &end);
+        if (i < m && end) atomicAdd(&deg[lo], cnt);
+    }
+}
+
+// Step 3a: degree-order keys (g, d, v).
+__global__ void k_rank_keys(const int32_t *__restrict__ deg, int64_t N, const int64_t *__restrict__ node_base, int k,
+                            int db, int vb, uint64_t *__restrict__ keys) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
+        int g = 0;
+        if (k > 1) g = upper_bound_i64(node_base, k + 1, x) - 1;
+        const uint64_t v = (uint64_t)(x - node_base[g]);
+        keys[x] = ((uint64_t)g << (db + vb)) | ((uint64_t)deg[x] << vb) | v;
+    }
+}
+
+// Step 3b: position r of the sorted list is the new label of x.
+__global__ void k_rank_from_sorted(const uint64_t *__restrict__ keys, int64_t N, const int64_t *__restrict__ node_base,
+                                   int db, int vb, int32_t *__restrict__ perm, int32_t *__restrict__ rank) {
+    const uint64_t vmask = (1ull << vb) - 1;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = keys[r];
+        const int g = (int)(key >> (db + vb));
+        const int64_t x = node_base[g] + (int64_t)(key & vmask);
+        perm[r] = (int32_t)x;
+        rank[x] = (int32_t)r;
+    }
+}
+
+// Step 4: oriented keys (s << gb) | t with s the lower new label.
+__global__ void k_orient_keys(const uint64_t *__restrict__ ukeys, int64_t m, int gb, const int32_t *__restrict__ rank,
+                              uint64_t *__restrict__ okeys) {
+    const uint64_t mask = (1ull << gb) - 1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = ukeys[i];
+        const uint32_t ra = (uint32_t)rank[k >> gb], rb = (uint32_t)rank[k & mask];
+        const uint64_t s = ra < rb ? ra : rb, t = ra < rb ? rb : ra;
+        okeys[i] = (s << gb) | t;
+    }
+}
+
+// Step 5: column entries and row lengths (rows arrive in runs).
+__global__ void k_csr_rows(const uint64_t *__restrict__ okeys, int64_t m, int gb, int32_t *__restrict__ col,
+                           int32_t *__restrict__ rowlen) {
+    const uint64_t mask = (1ull << gb) - 1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        int64_t s = -1 - (int64_t)threadIdx.x;
+        if (i < m) {
+            const uint64_t k = okeys[i];
+            s = (int64_t)(k >> gb);
+            col[i] = (int32_t)(k & mask);
+        }
+        bool end;
+        const int32_t cnt = run_sum_at_end<int32_t>(s, i < m ? 1 : 0, &end);
+        if (i < m && end) atomicAdd(&rowlen[s], cnt);
+    }
+}
+
+// Step 6a: per-node cost f (degree-order labels) over stored pairs (s, t).
+//   kind PRIOR: f[s] += dhat_s + dhat_t;   kind NEW: f[t] += dhat_t + dhat_s.
+__global__ void k_edge_costs(const int64_t *__restrict__ off, const int32_t *__restrict__ col, const uint64_t *okeys,
+                             int64_t m, int gb, int kind, int64_t *__restrict__ f) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        int64_t s = -1 - (int64_t)threadIdx.x;
+        int64_t c = 0;
+        int32_t t = 0;
+        if (i < m) {
+            s = (int64_t)(okeys[i] >> gb);
+            t = col[i];
+            c = (off[s + 1] - off[s]) + (off[(int64_t)t + 1] - off[t]);
+        }
+        if (kind == TC_COST_PRIOR) {
+            bool end;
+            const int64_t sum = run_sum_at_end<int64_t>(s, c, &end);
+            if (i < m && end) atomicAdd((unsigned long long *)&f[s], (unsigned long long)sum);
+        } else if (i < m) {
+            atomicAdd((unsigned long long *)&f[t], (unsigned long long)c);
+        }
+    }
+}
+
+// Step 6b: finish f for the per-node kinds, mask lists handled by whole
+// workgroups (their work is scheduled separately), flag them, and find the
+// longest list.
+__global__ void k_node_costs(const int64_t *__restrict__ off, const int32_t *__restrict__ deg_old,
+                             const int32_t *__restrict__ perm, int64_t N, int kind, int small_max,
+                             int64_t *__restrict__ f, uint32_t *__restrict__ wide, int32_t *__restrict__ max_dhat) {
+    int32_t local_max = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t dh = off[r + 1] - off[r];
+        local_max = max(local_max, (int32_t)dh);
+        int64_t c = f[r];
+        if (kind == TC_COST_ONE) c = 1;
+        if (kind == TC_COST_DEGREE) c = deg_old[perm[r]];
+        const bool w = dh > small_max;
+        f[r] = w ? 0 : c;
+        wide[r] = w ? 1u : 0u;
+    }
+    local_max = wave_reduce_max(local_max);
+    if (__lane_id() == 0) atomicMax(max_dhat, local_max);
+}
+
+__global__ void k_compact_index(const uint32_t *__restrict__ flag, const int64_t *__restrict__ pos, int64_t n,
+                                int32_t *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (flag[i]) out[pos[i]] = (int32_t)i;
+}
+
+// Step 6c: task boundaries.  bnd[0] = 0; bnd[j+1] = first x with F[x] >= target[j]
+// (target < 0 encodes "end": x = N).
+__global__ void k_task_bounds(const int64_t *__restrict__ F, int64_t N, const int64_t *__restrict__ target,
+                              int64_t ntargets, int32_t *__restrict__ bnd) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j <= ntargets;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        if (j == 0) {
+            bnd[0] = 0;
+            continue;
+        }
+        const int64_t tg = target[j - 1];
+        int64_t x = N;
+        if (tg >= 0) {
+            int64_t lo = 0, hi = N;
+            while (lo < hi) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                if (F[mid] >= tg)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            x = lo;
+        }
+        bnd[j] = (int32_t)x;
+    }
+}
+
+// Step 6d (k > 1): merge interior graph starts into the boundaries, so no
+// task spans two graphs, and record each task's graph.
+__global__ void k_merge_bounds(const int32_t *__restrict__ bnd, int64_t nb1, const int64_t *__restrict__ node_base,
+                               int k, int32_t *__restrict__ out) {
+    const int64_t total = nb1 + (k - 1);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < nb1) {
+            const int64_t v = bnd[i];
+            // interior starts strictly below v come first
+            int lo = 1, hi = k;  // interior starts are node_base[1..k-1]
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (node_base[mid] < v)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (i + (lo - 1) < total) out[i + (lo - 1)] = (int32_t)v;
+        } else {
+            const int g = (int)(i - nb1) + 1;
+            const int64_t v = node_base[g];
+            // boundaries <= v come first
+            int64_t lo = 0, hi = nb1;
+            while (lo < hi) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                if (bnd[mid] <= v)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo + (g - 1) < total) out[lo + (g - 1)] = (int32_t)v;
+        }
+    }
+}
+
+__global__ void k_task_graph(const int32_t *__restrict__ bnd, int64_t ntasks, const int64_t *__restrict__ node_base,
+                             int k, int32_t *__restrict__ gid) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ntasks; c += (int64_t)gridDim.x * blockDim.x) {
+        int g = upper_bound_i64(node_base, k + 1, (int64_t)bnd[c]) - 1;
+        gid[c] = g < 0 ? 0 : (g > k - 1 ? k - 1 : g);
+    }
+}
+
+template <class T>
+void d2h(T *host, const T *dev, size_t count, hipStream_t s) {
+    TC_HIP(hipMemcpyAsync(host, dev, count * sizeof(T), hipMemcpyDeviceToHost, s));
+}
+
+}  // namespace
+
+void fill_zero(void *p, size_t bytes, hipStream_t s) {
+    const int64_t words = (int64_t)((bytes + 3) / 4);
+    if (words <= 0) return;
+    k_fill_zero_u32<<<grid_for(words, 4), kThreads, 0, s>>>((uint32_t *)p, words);
+    TC_LAUNCH_CHECK();
+}
+
+// Eq. (1)/(2) cost targets (see the schedule reading in the design notes of
+// the oracle and of this library): initial W targets ceil((i+1) H / W) with
+// H = ceil(total/2); then C += max(ceil((total - C) / W), min_chunk) until C
+// reaches total, which ends the last task at the end of the node range.
+std::vector<int64_t> task_targets(int64_t total, int32_t W, int64_t min_chunk) {
+    std::vector<int64_t> t;
+    const int64_t H = (total + 1) / 2;
+    t.reserve((size_t)W * 8 + 16);
+    for (int32_t i = 0; i < W; ++i) t.push_back(((int64_t)(i + 1) * H + W - 1) / W);
+    int64_t C = H;
+    while (C < total) {
+        int64_t step = (total - C + W - 1) / W;
+        if (step < min_chunk) step = min_chunk;
+        C += step;
+        t.push_back(C >= total ? -1 : C);
+    }
+    if (t.empty() || t.back() != -1) t.push_back(-1);
+    // identical to the oracle's boundary rule: a final target equal to an
+    // earlier end would repeat the end boundary; keep the sequence as is.
+    return t;
+}
+
+void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
+                           Allocator &al, hipStream_t s, Oriented &out) {
+    const int64_t N = pk.N, M_in = pk.M_in;
+    const int k = pk.k;
+    const int gb = std::max(1, bits_for((uint64_t)std::max<int64_t>(N - 1, 1)));  // bits of a packed label
+
+    out.node_base = DevBuf<int64_t>(al, (size_t)k + 1);
+    TC_HIP(hipMemcpyAsync(out.node_base.p, pk.node_base.data(), (k + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DevBuf<int64_t> edge_base(al, (size_t)k + 1);
+    TC_HIP(hipMemcpyAsync(edge_base.p, pk.edge_base.data(), (k + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DevBuf<uint32_t> err(al, 4);
+    fill_zero(err.p, 16, s);
+
+    // ---- 1. canonical edge set
+    int64_t M = 0;
+    DevBuf<uint64_t> ka(al, (size_t)std::max<int64_t>(M_in, 1));
+    DevBuf<uint64_t> kb(al, (size_t)std::max<int64_t>(M_in, 1));
+    uint64_t *ukeys = kb.p;
+    if (M_in > 0) {
+        k_edge_keys<<<grid_for(M_in, 4), kThreads, 0, s>>>(src, dst, M_in, edge_base.p, out.node_base.p, k, gb, ka.p,
+                                                            err.p);
+        TC_LAUNCH_CHECK();
+        uint64_t *sorted = radix_sort_u64(ka.p, kb.p, M_in, 0, 2 * gb, al, s);
+        uint64_t *other = sorted == ka.p ? kb.p : ka.p;
+        DevBuf<uint32_t> flag(al, (size_t)M_in);
+        DevBuf<int64_t> pos(al, (size_t)M_in + 1);
+        k_unique_flags<<<grid_for(M_in, 4), kThreads, 0, s>>>(sorted, M_in, flag.p);
+        TC_LAUNCH_CHECK();
+        exclusive_scan(flag.p, pos.p, M_in, true, al, s);
+        k_compact_keys<<<grid_for(M_in, 4), kThreads, 0, s>>>(sorted, flag.p, pos.p, M_in, other);
+        TC_LAUNCH_CHECK();
+        ukeys = other;
+        uint32_t herr = 0;
+        d2h(&M, pos.p + M_in, 1, s);
+        d2h(&herr, err.p, 1, s);
+        TC_HIP(hipStreamSynchronize(s));
+        if (herr & 1u) throw Error(TC_ERR_ID_RANGE, "an edge endpoint is outside 0..n-1 of its graph");
+    }
+    out.M = M;
+    uint64_t *spare = ukeys == ka.p ? kb.p : ka.p;
+
+    // ---- 2. degrees
+    DevBuf<int32_t> deg(al, (size_t)std::max<int64_t>(N, 1));
+    fill_zero(deg.p, deg.bytes(), s);
+    if (M > 0) {
+        k_degrees<<<grid_for(M, 4), kThreads, 0, s>>>(ukeys, M, gb, deg.p);
+        TC_LAUNCH_CHECK();
+    }
+
+    // ---- 3. degree order
+    out.perm = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(N, 1));
+    DevBuf<int32_t> rank(al, (size_t)std::max<int64_t>(N, 1));
+    const int vb = std::max(1, bits_for((uint64_t)std::max<int64_t>(pk.max_n - 1, 1)));
+    const int db = std::max(1, bits_for((uint64_t)std::max<int64_t>(pk.max_n - 1, 1)));
+    const int kb_bits = bits_for((uint64_t)(k - 1));
+    if (kb_bits + db + vb > 64) throw Error(TC_ERR_TOO_LARGE, "too many graphs of this size in one handle");
+    if (N > 0) {
+        DevBuf<uint64_t> ra(al, (size_t)N), rb(al, (size_t)N);
+        k_rank_keys<<<grid_for(N, 4), kThreads, 0, s>>>(deg.p, N, out.node_base.p, k, db, vb, ra.p);
+        TC_LAUNCH_CHECK();
+        uint64_t *sorted = radix_sort_u64(ra.p, rb.p, N, 0, kb_bits + db + vb, al, s);
+        k_rank_from_sorted<<<grid_for(N, 4), kThreads, 0, s>>>(sorted, N, out.node_base.p, db, vb, out.perm.p, rank.p);
+        TC_LAUNCH_CHECK();
+    }
+
+    // ---- 4. orientation, 5. CSR
+    out.col = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(M, 1));
+    out.off = DevBuf<int64_t>(al, (size_t)N + 1);
+    DevBuf<int32_t> rowlen(al, (size_t)std::max<int64_t>(N, 1));
+    fill_zero(rowlen.p, rowlen.bytes(), s);
+    uint64_t *okeys = nullptr;
+    if (M > 0) {
+        k_orient_keys<<<grid_for(M, 4), kThreads, 0, s>>>(ukeys, M, gb, rank.p, spare);
+        TC_LAUNCH_CHECK();
+        okeys = radix_sort_u64(spare, ukeys, M, 0, 2 * gb, al, s);
+        k_csr_rows<<<grid_for(M, 4), kThreads, 0, s>>>(okeys, M, gb, out.col.p, rowlen.p);
+        TC_LAUNCH_CHECK();
+    }
+    exclusive_scan(rowlen.p, out.off.p, N, true, al, s);
+
+    // ---- 6. costs, wide lists, task table
+    DevBuf<int64_t> f(al, (size_t)std::max<int64_t>(N, 1));
+    fill_zero(f.p, f.bytes(), s);
+    if (M > 0 && (bp.cost_fn == TC_COST_PRIOR || bp.cost_fn == TC_COST_NEW)) {
+        k_edge_costs<<<grid_for(M, 4), kThreads, 0, s>>>(out.off.p, out.col.p, okeys, M, gb, bp.cost_fn, f.p);
+        TC_LAUNCH_CHECK();
+    }
+    DevBuf<uint32_t> wide(al, (size_t)std::max<int64_t>(N, 1));
+    DevBuf<int32_t> maxd(al, 1);
+    fill_zero(maxd.p, 4, s);
+    DevBuf<int64_t> F(al, (size_t)N + 1);
+    DevBuf<int64_t> widepos(al, (size_t)N + 1);
+    if (N > 0) {
+        k_node_costs<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, deg.p, out.perm.p, N, bp.cost_fn, bp.small_max,
+                                                          f.p, wide.p, maxd.p);
+        TC_LAUNCH_CHECK();
+    }
+    exclusive_scan(f.p, F.p, N, true, al, s);
+    exclusive_scan(wide.p, widepos.p, N, true, al, s);
+    int64_t hv[2] = {0, 0};
+    int32_t hmax = 0;
+    d2h(&hv[0], F.p + N, 1, s);
+    d2h(&hv[1], widepos.p + N, 1, s);
+    d2h(&hmax, maxd.p, 1, s);
+    TC_HIP(hipStreamSynchronize(s));
+    out.total_cost = hv[0];
+    out.nbig = hv[1];
+    out.max_dhat = hmax;
+
+    out.big = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(out.nbig, 1));
+    if (out.nbig > 0) {
+        k_compact_index<<<grid_for(N, 4), kThreads, 0, s>>>(wide.p, widepos.p, N, out.big.p);
+        TC_LAUNCH_CHECK();
+    }
+
+    int64_t min_chunk = bp.min_chunk;
+    if (min_chunk <= 0) {
+        // automatic floor: about 1/64 of an initial task's cost, at least 256
+        min_chunk = std::max<int64_t>(256, out.total_cost / ((int64_t)bp.workers * 128 + 1));
+    }
+    std::vector<int64_t> tg = task_targets(out.total_cost, bp.workers, min_chunk);
+    const int64_t ntg = (int64_t)tg.size();
+    DevBuf<int64_t> dtg(al, (size_t)ntg);
+    TC_HIP(hipMemcpyAsync(dtg.p, tg.data(), ntg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DevBuf<int32_t> bnd(al, (size_t)ntg + 1);
+    k_task_bounds<<<grid_for(ntg + 1), kThreads, 0, s>>>(F.p, N, dtg.p, ntg, bnd.p);
+    TC_LAUNCH_CHECK();
+    if (k > 1) {
+        const int64_t tot = ntg + 1 + (k - 1);
+        out.bnd = DevBuf<int32_t>(al, (size_t)tot);
+        k_merge_bounds<<<grid_for(tot), kThreads, 0, s>>>(bnd.p, ntg + 1, out.node_base.p, k, out.bnd.p);
+        TC_LAUNCH_CHECK();
+        out.tasks = tot - 1;
+        out.gid = DevBuf<int32_t>(al, (size_t)out.tasks);
+        k_task_graph<<<grid_for(out.tasks), kThreads, 0, s>>>(out.bnd.p, out.tasks, out.node_base.p, k, out.gid.p);
+        TC_LAUNCH_CHECK();
+    } else {
+        out.bnd = std::move(bnd);
+        out.tasks = ntg;
+    }
+    // Scratch buffers are released in stream order when this scope ends.
+    TC_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace tc

@@ -1,0 +1,190 @@
+// Shared host/device helpers for the gfx950 triangle-counting library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+
+#include "tc.h"
+
+namespace tc {
+
+// ----------------------------------------------------------------- errors
+
+struct Error : std::runtime_error {
+    tc_status code;
+    Error(tc_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+inline void hip_check(hipError_t e, const char *what, const char *file, int line) {
+    if (e != hipSuccess)
+        throw Error(TC_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e) + " (" + file + ":" +
+                                       std::to_string(line) + ")");
+}
+#define TC_HIP(x) ::tc::hip_check((x), #x, __FILE__, __LINE__)
+#define TC_LAUNCH_CHECK() ::tc::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline int bits_for(uint64_t max_value) {  // bits needed to hold values 0..max_value
+    int b = 0;
+    while (b < 64 && (max_value >> b) != 0) ++b;
+    return b;
+}
+
+// ------------------------------------------------------- device allocator
+
+// Device memory comes from the caller's allocator callbacks when given,
+// otherwise from the stream-ordered pool (hipMallocAsync).  An optional
+// budget caps the bytes outstanding through one Allocator.
+struct Allocator {
+    void *(*fn_alloc)(size_t, void *, void *) = nullptr;
+    void (*fn_free)(void *, size_t, void *, void *) = nullptr;
+    void *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    uint64_t budget = 0;  // 0 = none
+    uint64_t live = 0;
+    uint64_t peak = 0;
+
+    void *get(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        bytes = (bytes + 255) & ~size_t(255);
+        if (budget && live + bytes > budget)
+            throw Error(TC_ERR_OUT_OF_MEMORY, "device budget exceeded: need " + std::to_string(live + bytes) +
+                                                  " bytes, budget " + std::to_string(budget));
+        void *p = nullptr;
+        if (fn_alloc) {
+            p = fn_alloc(bytes, (void *)stream, ctx);
+        } else {
+            if (hipMallocAsync(&p, bytes, stream) != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+            }
+        }
+        if (!p) throw Error(TC_ERR_OUT_OF_MEMORY, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        live += bytes;
+        if (live > peak) peak = live;
+        return p;
+    }
+    void put(void *p, size_t bytes) {
+        if (!p) return;
+        if (bytes == 0) bytes = 256;
+        bytes = (bytes + 255) & ~size_t(255);
+        if (fn_free)
+            fn_free(p, bytes, (void *)stream, ctx);
+        else
+            (void)hipFreeAsync(p, stream);
+        live -= bytes;
+    }
+};
+
+// Owning device buffer.
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    Allocator *a = nullptr;
+    DevBuf() = default;
+    DevBuf(Allocator &al, size_t count) : n(count), a(&al) { p = (T *)al.get(count * sizeof(T)); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), a(o.a) {
+        o.p = nullptr;
+        o.n = 0;
+    }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            a = o.a;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void release() {
+        if (p && a) a->put(p, n * sizeof(T));
+        p = nullptr;
+        n = 0;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// -------------------------------------------------------- device helpers
+
+#ifdef __HIPCC__
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int l = __lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Orders this wave's LDS traffic: writes issued before are visible to reads
+// issued after, for every lane of the wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class T>
+__device__ __forceinline__ T wave_inclusive_sum(T x) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T y = __shfl_up(x, d, 64);
+        if (__lane_id() >= d) x += y;
+    }
+    return x;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_reduce_max(T x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const T y = __shfl_xor(x, d, 64);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+
+__device__ __forceinline__ int32_t readlane32(int32_t x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
+
+__device__ __forceinline__ int64_t readlane64(int64_t x, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), lane);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int32_t uniform32(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) { return readlane64(x, __builtin_amdgcn_readfirstlane(__lane_id())); }
+
+// Lanes of the wave holding the same 9-bit value v (bit 8 flags an inactive
+// lane), found with one ballot per bit.
+__device__ __forceinline__ uint64_t match_peers9(uint32_t v) {
+    uint64_t peers = ~0ull;
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+        const bool bit = (v >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+#endif
+
+}  // namespace tc

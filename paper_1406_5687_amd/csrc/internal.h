@@ -1,0 +1,101 @@
+// Internal interfaces between the translation units of the library.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace tc {
+
+// scan.hip -- exclusive prefix sums; with write_total, out[n] = sum (out has n+1 slots)
+void exclusive_scan(const uint32_t *in, int64_t *out, int64_t n, bool write_total, Allocator &al, hipStream_t s);
+void exclusive_scan(const int32_t *in, int64_t *out, int64_t n, bool write_total, Allocator &al, hipStream_t s);
+void exclusive_scan(const int64_t *in, int64_t *out, int64_t n, bool write_total, Allocator &al, hipStream_t s);
+void exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, bool write_total, Allocator &al, hipStream_t s);
+
+// sort.hip -- LSD radix sort by bits [begin_bit, end_bit); returns the buffer holding the result
+uint64_t *radix_sort_u64(uint64_t *keys, uint64_t *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al,
+                         hipStream_t s);
+
+// build.hip -------------------------------------------------------------
+
+// Node and edge layout of the k graphs packed into one handle.
+struct Packing {
+    int32_t k = 0;
+    std::vector<int64_t> node_base;  // k+1, host
+    std::vector<int64_t> edge_base;  // k+1, host
+    int64_t N = 0;                   // sum of n
+    int64_t M_in = 0;                // sum of input edges
+    int32_t max_n = 0;
+};
+
+struct BuildParams {
+    int32_t workers = 0;
+    int32_t cost_fn = TC_COST_PRIOR;
+    int64_t min_chunk = 0;
+    int32_t small_max = 128;
+};
+
+// Device-side product of a build (all in degree-order labels).
+struct Oriented {
+    DevBuf<int64_t> off;        // N+1
+    DevBuf<int32_t> col;        // M
+    DevBuf<int32_t> perm;       // N: packed caller label of each position
+    DevBuf<int64_t> node_base;  // k+1 (device copy)
+    DevBuf<int32_t> bnd;        // tasks+1
+    DevBuf<int32_t> gid;        // tasks (k > 1 only)
+    DevBuf<int32_t> big;        // wide nodes, handled by whole workgroups
+    int64_t M = 0;
+    int64_t tasks = 0;
+    int64_t total_cost = 0;
+    int64_t nbig = 0;
+    int32_t max_dhat = 0;
+};
+
+// src/dst: packed input edges on the device (edge e of graph g at edge_base[g] + i).
+void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
+                           Allocator &al, hipStream_t s, Oriented &out);
+
+// Fill helpers usable inside captured streams (no memset nodes).
+void fill_zero(void *p, size_t bytes, hipStream_t s);
+
+// count.hip --------------------------------------------------------------
+
+struct CountDesc {
+    const int64_t *off;
+    const int32_t *col;
+    const int32_t *bnd;
+    const int32_t *gid;        // NULL when k == 1
+    const int64_t *node_base;  // k+1
+    const int32_t *big;
+    int64_t *totals;  // k
+    int64_t *tv;      // N (degree-order labels) or NULL
+    int64_t m;  // entries of col (bounds every row read)
+    int64_t task_base;
+    int64_t big_base;
+    int32_t k;
+    int32_t small_max;  // lists up to this length were scheduled for single waves
+};
+
+struct CountLaunch {
+    const CountDesc *descs;  // device array
+    int32_t ndesc;
+    int64_t total_tasks;
+    int64_t total_big;
+    uint32_t *heads;  // 2 counters, zeroed before launch
+    int32_t workers;  // persistent waves for the small-list kernel
+    int32_t lds_max;     // longest list kept in LDS by the workgroup kernel
+    int32_t big_blocks;  // persistent workgroups for long lists
+    bool per_node;
+};
+
+void count_launch(const CountLaunch &L, hipStream_t s);
+
+// out[perm[i]] = tv[i] for i < n
+void scatter_per_node(const int64_t *tv, const int32_t *perm, int64_t n, int64_t *out, hipStream_t s);
+
+int device_cu_count();
+int max_small_list();
+int max_lds_list();
+
+}  // namespace tc

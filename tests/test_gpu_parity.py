@@ -1,0 +1,292 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Every comparison is exact (integer counts, labels and boundaries): tolerance 0.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests import golden_io
+from tests import graphs_small as gs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tc():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1406_5687_amd as tcmod
+
+    tcmod.load()
+    return tcmod
+
+
+def gpu_count(tc, n, src, dst, **kw):
+    with tc.build_oriented([(n, src, dst)], **kw) as g:
+        tv, tot = g.count_per_node()
+        tot2 = g.count_total()
+        assert tot2[0] == tot[0]
+        return int(tot[0]), tv
+
+
+def check(tc, n, src, dst, **kw):
+    T_ref, tv_ref, _ = oracle.count(n, src, dst)
+    T, tv = gpu_count(tc, n, src, dst, **kw)
+    assert T == T_ref
+    np.testing.assert_array_equal(tv, tv_ref)
+    return T
+
+
+# ------------------------------------------------------------ small cases
+
+@pytest.mark.parametrize("name", golden_io.all_graphs())
+def test_golden(tc, name):
+    g = golden_io.graph(name)
+    T, tv = gpu_count(tc, g["n"], g["src"], g["dst"])
+    assert T == g["T"]
+    np.testing.assert_array_equal(tv, g["Tv"])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 9, 30, 64, 65, 129, 200])
+def test_complete(tc, n):
+    T, tv = gpu_count(tc, *gs.complete(n))
+    assert T == math.comb(n, 3)
+    assert (tv == math.comb(n - 1, 2)).all()
+
+
+@pytest.mark.parametrize("n", [5, 7, 100, 1000])
+def test_wheel(tc, n):
+    T, tv = gpu_count(tc, *gs.wheel(n))
+    assert T == n - 1 and tv[0] == n - 1 and (tv[1:] == 2).all()
+
+
+@pytest.mark.parametrize("g", [gs.complete_bipartite(5, 7), gs.complete_bipartite(1, 300), gs.grid(30, 40),
+                               gs.hypercube(10), gs.cycle(1000)])
+def test_bipartite(tc, g):
+    T, tv = gpu_count(tc, *g)
+    assert T == 0 and not tv.any()
+
+
+def test_empty_inputs(tc):
+    T, tv = gpu_count(tc, 10, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert T == 0 and tv.shape == (10,) and not tv.any()
+    T, tv = gpu_count(tc, 5, np.array([1, 2, 3], np.int32), np.array([1, 2, 3], np.int32))
+    assert T == 0 and not tv.any()
+    with tc.build_oriented([(0, np.zeros(0, np.int32), np.zeros(0, np.int32))]) as g:
+        assert g.count_total()[0] == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_gnp(tc, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 300))
+    n, s, d = gs.gnp(n, float(rng.uniform(0.01, 0.6)), rng)
+    check(tc, n, s, d)
+
+
+def test_id_range_error(tc):
+    with pytest.raises(tc.tc.IdRangeError):
+        tc.build_oriented([(3, np.array([0, 3], np.int32), np.array([1, 1], np.int32))])
+    with pytest.raises(tc.tc.IdRangeError):
+        tc.build_oriented([(3, np.array([0, -1], np.int32), np.array([1, 1], np.int32))])
+
+
+# ------------------------------------------------------------ workload shapes
+
+@pytest.mark.parametrize("maker", [
+    lambda: graphgen.workload_er(1),
+    lambda: graphgen.workload_er(2),
+    lambda: graphgen.preferential_attachment(50_000, 20, 3),
+    lambda: graphgen.preferential_attachment(20_000, 50, 4),
+    lambda: graphgen.rmat(14, 16, seed=5),
+    lambda: graphgen.rmat(16, 16, seed=6),
+    lambda: graphgen.chung_lu(40_000, 640_000, 2.1, 7),
+], ids=["er1", "er2", "pa50k", "pa20k_d50", "rmat14", "rmat16", "cl40k"])
+def test_workloads(tc, maker):
+    g = maker()
+    check(tc, g.n, g.src, g.dst)
+
+
+def test_device_inputs_and_outputs(tc):
+    import torch
+
+    g = graphgen.rmat(13, 16, seed=9)
+    T_ref, tv_ref, _ = oracle.count(g.n, g.src, g.dst)
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    with tc.build_oriented([(g.n, src, dst)]) as h:
+        out = torch.full((g.n,), -7, dtype=torch.int64, device="cuda")
+        tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+        h.count_per_node(out=out, totals=tot)
+        t2 = torch.zeros(1, dtype=torch.int64, device="cuda")
+        h.count_total(out=t2)
+        torch.cuda.synchronize()
+        assert int(tot.item()) == T_ref == int(t2.item())
+        np.testing.assert_array_equal(out.cpu().numpy(), tv_ref)
+
+
+# ------------------------------------------------------------ build parity (a1-a3)
+
+@pytest.mark.parametrize("maker", [
+    lambda: graphgen.workload_er(1),
+    lambda: graphgen.rmat(12, 16, seed=2),
+    lambda: graphgen.preferential_attachment(5000, 10, 3),
+], ids=["er", "rmat12", "pa5k"])
+def test_oriented_csr_matches_oracle(tc, maker):
+    g = maker()
+    m, off_o, col_o, deg = oracle.orient(g.n, g.src, g.dst)
+    perm_o = oracle.degree_order(deg)
+    with tc.build_oriented([(g.n, g.src, g.dst)]) as h:
+        off, col, perm = h.export_csr()
+        info = h.info()
+    assert info["m"] == m
+    np.testing.assert_array_equal(perm, perm_o)               # degree order, ties by id
+    rank = np.empty(g.n, np.int64)
+    rank[perm] = np.arange(g.n)
+    dh = np.diff(off)
+    np.testing.assert_array_equal(dh, np.diff(off_o)[perm])   # effective degrees
+    for r in range(g.n):
+        row = col[off[r]:off[r + 1]]
+        assert (np.diff(row) > 0).all()                       # rows ascending
+        expect = np.sort(rank[col_o[off_o[perm[r]]:off_o[perm[r] + 1]]])
+        np.testing.assert_array_equal(row, expect)
+    assert info["max_out_degree"] == int(dh.max(initial=0))
+
+
+# ------------------------------------------------------------ schedule parity (a4)
+
+@pytest.mark.parametrize("cost", [0, 1, 2, 3])
+@pytest.mark.parametrize("W,floor", [(64, 1), (4096, 0), (7, 500)])
+def test_schedule_matches_oracle(tc, cost, W, floor):
+    g = graphgen.preferential_attachment(20_000, 8, 11)
+    m, off_o, col_o, deg = oracle.orient(g.n, g.src, g.dst)
+    perm = oracle.degree_order(deg)
+    f_orig = oracle.costs(off_o, col_o, deg, cost)
+    f = f_orig[perm].copy()
+    dh = np.diff(off_o)[perm]
+    f[dh > 128] = 0                       # long lists go to the workgroup kernel
+    total = int(f.sum())
+    min_chunk = floor if floor > 0 else max(256, total // (W * 128 + 1))
+    bnd_ref = oracle.schedule(f, W, min_chunk)
+    with tc.build_oriented([(g.n, g.src, g.dst)], workers=W, cost_fn=cost, min_chunk=floor) as h:
+        bnd, gid = h.export_schedule()
+        info = h.info()
+        tv, tot = h.count_per_node()
+    np.testing.assert_array_equal(bnd, bnd_ref)
+    assert info["total_cost"] == total
+    T_ref, tv_ref, _ = oracle.count(g.n, g.src, g.dst)
+    assert tot[0] == T_ref
+    np.testing.assert_array_equal(tv, tv_ref)
+
+
+# ------------------------------------------------------------ invariance (Section V-D)
+
+@pytest.mark.parametrize("kw", [
+    dict(workers=1), dict(workers=7), dict(workers=64), dict(workers=20000),
+    dict(small_max=2), dict(small_max=16), dict(small_max=128),
+    dict(lds_list_max=2), dict(lds_list_max=50), dict(small_max=4, lds_list_max=8),
+    dict(cost_fn=0), dict(cost_fn=1), dict(cost_fn=3), dict(min_chunk=1), dict(min_chunk=10**12),
+], ids=lambda kw: ",".join(f"{k}={v}" for k, v in kw.items()))
+def test_tuning_invariance(tc, kw):
+    g = graphgen.rmat(13, 16, seed=13)
+    check(tc, g.n, g.src, g.dst, **kw)
+
+
+def test_long_lists_all_paths(tc):
+    # K_300: lists up to 299 entries -> workgroup kernel; with lds_list_max=64
+    # most of them take the device-memory binary-search path.
+    n, s, d = gs.complete(300)
+    for kw in (dict(), dict(lds_list_max=64), dict(small_max=8, lds_list_max=16)):
+        T, tv = gpu_count(tc, n, s, d, **kw)
+        assert T == math.comb(300, 3) and (tv == math.comb(299, 2)).all()
+
+
+# ------------------------------------------------------------ metamorphic
+
+def test_relabel_and_input_noise(tc):
+    g = graphgen.rmat(12, 16, seed=21)
+    T, tv = gpu_count(tc, g.n, g.src, g.dst)
+    rng = np.random.default_rng(0)
+    pi = rng.permutation(g.n).astype(np.int32)
+    T2, tv2 = gpu_count(tc, g.n, pi[g.src], pi[g.dst])
+    assert T2 == T
+    np.testing.assert_array_equal(tv2[pi], tv)
+    order = rng.permutation(g.m)
+    s = np.concatenate([g.dst[order], g.src[:500], np.arange(40, dtype=np.int32)])
+    d = np.concatenate([g.src[order], g.dst[:500], np.arange(40, dtype=np.int32)])
+    T3, tv3 = gpu_count(tc, g.n, s, d)
+    assert T3 == T
+    np.testing.assert_array_equal(tv3, tv)
+
+
+# ------------------------------------------------------------ packed graphs and batches
+
+def test_packed_handle_equals_separate(tc):
+    parts = [graphgen.rmat(10, 16, seed=1), graphgen.erdos_renyi(0 + 500, 3000, 2),
+             graphgen.EdgeList(0, np.zeros(0, np.int32), np.zeros(0, np.int32)),
+             graphgen.preferential_attachment(3000, 12, 3), graphgen.chung_lu(2000, 30000, 2.1, 4),
+             graphgen.EdgeList(7, np.zeros(0, np.int32), np.zeros(0, np.int32))]
+    with tc.build_oriented([(p.n, p.src, p.dst) for p in parts]) as h:
+        tv, tot = h.count_per_node()
+        tot2 = h.count_total()
+        bnd, gid = h.export_schedule()
+    np.testing.assert_array_equal(tot, tot2)
+    base = 0
+    for i, p in enumerate(parts):
+        T_ref, tv_ref, _ = oracle.count(p.n, p.src, p.dst)
+        assert tot[i] == T_ref
+        np.testing.assert_array_equal(tv[base:base + p.n], tv_ref)
+        base += p.n
+    # no task spans two graphs
+    nb = np.cumsum([0] + [p.n for p in parts])
+    for c in range(len(gid)):
+        if bnd[c] < bnd[c + 1]:
+            assert nb[gid[c]] <= bnd[c] and bnd[c + 1] <= nb[gid[c] + 1]
+
+
+def test_batch_of_handles_equals_separate(tc):
+    parts = [graphgen.rmat(11, 16, seed=s) for s in range(3)] + [graphgen.erdos_renyi(800, 5000, 9)]
+    hs = [tc.build_oriented([(p.n, p.src, p.dst)]) for p in parts]
+    hs.append(tc.build_oriented([(p.n, p.src, p.dst) for p in parts[:2]]))
+    tots, tvs = tc.count_batch(hs, per_node=True)
+    tots_only, _ = tc.count_batch(hs, per_node=False)
+    for h, t, t2, tv in zip(hs, tots, tots_only, tvs):
+        tv1, t1 = h.count_per_node()
+        np.testing.assert_array_equal(t, t1)
+        np.testing.assert_array_equal(t2, t1)
+        np.testing.assert_array_equal(tv, tv1)
+    for h in hs:
+        h.free()
+
+
+# ------------------------------------------------------------ full-size workloads
+
+@pytest.mark.slow
+def test_full_er_config(tc):
+    g = graphgen.workload_er(1)
+    check(tc, g.n, g.src, g.dst)
+
+
+@pytest.mark.slow
+def test_full_pa_config(tc):
+    """PA(10^6, 50) at full size, in the launch configuration the bench times:
+    per-node counts compared element by element with the oracle."""
+    import torch
+
+    g = graphgen.workload_pa(1)
+    T_ref, tv_ref, m = oracle.count(g.n, g.src, g.dst)
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    with tc.build_oriented([(g.n, src, dst)]) as h:
+        out = torch.zeros(g.n, dtype=torch.int64, device="cuda")
+        tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+        h.count_per_node(out=out, totals=tot)
+        torch.cuda.synchronize()
+        assert h.info()["m"] == m
+    assert int(tot.item()) == T_ref
+    np.testing.assert_array_equal(out.cpu().numpy(), tv_ref)
