@@ -83,7 +83,9 @@ typedef struct {
                            whole workgroup; 0 = automatic (128, also the maximum) */
     int32_t lds_list_max; /* longest list a workgroup stages in LDS; longer lists are probed by
                              binary search in device memory; 0 = automatic (4096, the maximum) */
-    int32_t reserved[8];
+    int32_t time_kernels; /* 1: record device events around the counting kernels of each count
+                             call; the elapsed time is reported by tc_graph_info */
+    int32_t reserved[7];
 } tc_options;
 
 /* Fills *opt with the defaults (all zero except cost_fn = TC_COST_PRIOR). */
@@ -132,7 +134,10 @@ typedef struct {
     int64_t wide_nodes;     /* nodes whose list is longer than small_max */
     uint64_t device_bytes;  /* device memory held by the handle */
     int32_t partitions;     /* node-range partitions used for counting (1 = resident) */
-    int32_t reserved[7];
+    int32_t reserved0;
+    double last_count_ms;   /* device time of the counting kernels of the last count call made
+                               with time_kernels = 1 (waits for it); -1 when none */
+    int32_t reserved[4];
 } tc_graph_info_t;
 
 tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info);

@@ -20,6 +20,13 @@ struct tc_graph {
     tc::DevBuf<int64_t> tv;
     tc::DevBuf<tc::CountDesc> desc;  // one descriptor pointing at the buffers above
     bool desc_has_tv = false;
+    // optional device timing of the counting kernels
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool timed = false;
+    ~tc_graph() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -214,7 +221,17 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
         L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
         L.big_blocks = tc::device_cu_count();
         L.per_node = want_tv;
+        const bool timing = opt && opt->time_kernels;
+        if (timing) {
+            for (hipEvent_t &e : g->ev)
+                if (!e) TC_HIP(hipEventCreate(&e));
+            TC_HIP(hipEventRecord(g->ev[0], s));
+        }
         tc::count_launch(L, s);
+        if (timing) {
+            TC_HIP(hipEventRecord(g->ev[1], s));
+            g->timed = true;
+        }
         if (want_tv) {
             if (on_dev) {
                 tc::scatter_per_node(g->tv.p, g->o.perm.p, g->pk.N, per_node, s);
@@ -336,6 +353,12 @@ tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info) {
     info->wide_nodes = g->o.nbig;
     info->device_bytes = g->al.live;
     info->partitions = 1;
+    info->last_count_ms = -1.0;
+    if (g->timed) {
+        float ms = 0.f;
+        if (hipEventSynchronize(g->ev[1]) == hipSuccess && hipEventElapsedTime(&ms, g->ev[0], g->ev[1]) == hipSuccess)
+            info->last_count_ms = ms;
+    }
     return TC_OK;
 }
 

@@ -61,7 +61,8 @@ class Options(ctypes.Structure):
         ("min_chunk", ctypes.c_int64),
         ("small_max", ctypes.c_int32),
         ("lds_list_max", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 8),
+        ("time_kernels", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
     ]
 
 
@@ -81,7 +82,9 @@ class GraphInfo(ctypes.Structure):
         ("wide_nodes", ctypes.c_int64),
         ("device_bytes", ctypes.c_uint64),
         ("partitions", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("reserved0", ctypes.c_int32),
+        ("last_count_ms", ctypes.c_double),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -169,7 +172,8 @@ def _is_tensor(x) -> bool:
 
 
 def make_options(*, stream=None, inputs_on_device=False, outputs_on_device=False, hbm_budget_bytes=0, workers=0,
-                 cost_fn=COST_PRIOR, min_chunk=0, small_max=0, lds_list_max=0, torch_allocator=True) -> Options:
+                 cost_fn=COST_PRIOR, min_chunk=0, small_max=0, lds_list_max=0, time_kernels=False,
+                 torch_allocator=True) -> Options:
     global _torch_alloc
     o = Options()
     load().tc_options_default(ctypes.byref(o))
@@ -181,6 +185,7 @@ def make_options(*, stream=None, inputs_on_device=False, outputs_on_device=False
     o.min_chunk = int(min_chunk)
     o.small_max = int(small_max)
     o.lds_list_max = int(lds_list_max)
+    o.time_kernels = int(bool(time_kernels))
     if stream is None:
         try:
             torch = _torch()
@@ -272,7 +277,7 @@ class Graph:
     def info(self) -> dict:
         gi = GraphInfo()
         _raise(load().tc_graph_info(self._h, ctypes.byref(gi)))
-        return {f: getattr(gi, f) for f, _ in GraphInfo._fields_ if f != "reserved"}
+        return {f: getattr(gi, f) for f, _ in GraphInfo._fields_ if not f.startswith("reserved")}
 
     def export_csr(self):
         """(off[n+1], col[m], perm[n]) in degree-order labels."""
