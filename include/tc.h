@@ -76,7 +76,8 @@ typedef struct {
     void *(*alloc)(size_t bytes, void *stream, void *ctx);
     void (*free)(void *ptr, size_t bytes, void *stream, void *ctx);
     void *alloc_ctx;
-    int32_t workers;    /* persistent waves pulling tasks; 0 = 16 per compute unit */
+    int32_t workers;    /* persistent waves pulling tasks; 0 = as many as fit on the device at once;
+                           launches never exceed that resident capacity */
     int32_t cost_fn;    /* TC_COST_*; used when the schedule is built */
     int64_t min_chunk;  /* floor on a task's cost target (Eq. (2)); 0 = automatic */
     int32_t small_max;  /* lists up to this length are handled by one wave, longer ones by a

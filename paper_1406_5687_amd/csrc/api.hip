@@ -162,7 +162,7 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
         g->al = make_allocator(&o);
         g->al.budget = 0;  // resident build; budgets are handled by the partitioned path
         const int cus = tc::device_cu_count();
-        g->workers = o.workers > 0 ? o.workers : 16 * cus;
+        g->workers = o.workers > 0 ? o.workers : tc::small_kernel_waves_per_cu(true) * cus;
         g->small_max = o.small_max > 0 ? std::min(o.small_max, tc::max_small_list()) : tc::max_small_list();
         g->lds_max = o.lds_list_max > 0 ? std::max(2, std::min(o.lds_list_max, tc::max_lds_list())) : tc::max_lds_list();
         g->cost_fn = o.cost_fn;

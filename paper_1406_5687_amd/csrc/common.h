@@ -124,6 +124,21 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
+// Global-address-space views of device pointers: loads through them compile
+// to global_load (not flat_load, which also waits on the LDS counter).
+template <class T>
+using gptr_t = __attribute__((address_space(1))) T *;
+
+template <class T>
+__device__ __forceinline__ gptr_t<const T> gview(const T *p) {
+    return (gptr_t<const T>)p;
+}
+
+template <class T>
+__device__ __forceinline__ gptr_t<T> gview_mut(T *p) {
+    return (gptr_t<T>)p;
+}
+
 // Orders this wave's LDS traffic: writes issued before are visible to reads
 // issued after, for every lane of the wave.
 __device__ __forceinline__ void wave_lds_sync() {

@@ -43,6 +43,9 @@ constexpr int kBigHash = 1 << kBigHashBits;  // load factor <= 1/2
 constexpr int kBigWaves = 16;
 constexpr int kBigThreads = kBigWaves * 64;
 
+constexpr int kWin = 4;           // 64-id windows walked per step
+constexpr int kStep = 64 * kWin;  // ids per step
+
 __device__ __forceinline__ uint32_t hash_slot(int32_t x, int bits) {
     return ((uint32_t)x * 2654435769u) >> (32 - bits);
 }
@@ -80,45 +83,146 @@ __device__ __forceinline__ void add_u64(int64_t *p, uint64_t v) {
 
 // --------------------------------------------------------------- one wave
 
-struct SmallLds {
+// Walks the virtual sequence of target-row ids from e_begin to e_end (a
+// multiple of kStep apart, e_end may pass total), kStep ids per step: marks
+// the row starts that fall inside the step, finds every lane's row with one
+// ballot per 64-id window, loads the 4 ids of each lane together, then probes
+// them together.  `cur` is the row holding e_begin.
+//   IN_LDS: membership in the source list by the LDS hash (key/pos);
+//   otherwise by binary search in the sorted list col[rs .. rs+a) (huge lists).
+// Per-node counts go to LDS counters by list position, or (huge lists) to tv.
+template <int HBITS, bool PER_NODE, bool IN_LDS, class PosT>
+__device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *pos, const int32_t *P,
+                                               const int64_t *base, const PosT *tpos, int32_t *cnt, uint8_t *flag,
+                                               gptr_t<const int32_t> col, int64_t m, int32_t nt, int32_t total,
+                                               int cur, int32_t e_begin, int32_t e_end, int64_t rs, int32_t a,
+                                               int32_t i0, int64_t *__restrict__ tv) {
+    constexpr uint32_t kMask = (1u << HBITS) - 1;
+    const int lane = __lane_id();
+    const uint64_t upto = lanemask_lt() | (1ull << lane);
+    uint32_t hits = 0;
+    for (int32_t e0 = e_begin; e0 < e_end; e0 += kStep) {
+#pragma unroll
+        for (int q = 0; q < kWin; ++q) {
+            const int jj = cur + 1 + lane + 64 * q;
+            if (jj < nt) {
+                const int32_t p = P[jj] - e0;
+                if (p < kStep) flag[p] = 1;
+            }
+        }
+        wave_lds_sync();
+        uint64_t M[kWin];
+        int pre[kWin];
+        int acc = 0;
+#pragma unroll
+        for (int q = 0; q < kWin; ++q) {
+            M[q] = __ballot(flag[64 * q + lane] != 0);
+            pre[q] = acc;
+            acc += popc64(M[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < kWin; ++q) flag[64 * q + lane] = 0;
+        int seg[kWin];
+        int64_t at[kWin];
+        int32_t w[kWin];
+#pragma unroll
+        for (int q = 0; q < kWin; ++q) {
+            seg[q] = cur + pre[q] + popc64(M[q] & upto);
+            const int32_t e = e0 + 64 * q + lane;
+            const int64_t x = e < total ? base[seg[q]] + e : -1;
+            at[q] = (uint64_t)x < (uint64_t)m ? x : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < kWin; ++q) w[q] = col[at[q] < 0 ? 0 : at[q]];
+#pragma unroll
+        for (int q = 0; q < kWin; ++q) w[q] = at[q] < 0 ? -1 : w[q];
+        if (IN_LDS) {
+            uint32_t sl[kWin];
+            int32_t k[kWin];
+#pragma unroll
+            for (int q = 0; q < kWin; ++q) {
+                sl[q] = hash_slot(w[q], HBITS);
+                k[q] = key[sl[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < kWin; ++q) {
+                while (k[q] != w[q] && k[q] != -1) {  // collision chain (rare)
+                    sl[q] = (sl[q] + 1) & kMask;
+                    k[q] = key[sl[q]];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kWin; ++q) {
+                const bool hit = w[q] >= 0 && k[q] == w[q];
+                hits += hit ? 1u : 0u;
+                if (PER_NODE && hit) {
+                    atomicAdd(&cnt[pos[sl[q]]], 1);
+                    atomicAdd(&cnt[tpos[seg[q]]], 1);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kWin; ++q) {
+                if (w[q] < 0) continue;
+                int32_t lo = 0, hi = a;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if (col[rs + mid] < w[q])
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                if (lo < a && col[rs + lo] == w[q]) {
+                    ++hits;
+                    if (PER_NODE) {
+                        add_u64(&tv[w[q]], 1);
+                        add_u64(&tv[col[rs + i0 + tpos[seg[q]]]], 1);
+                    }
+                }
+            }
+        }
+        int nc = cur + acc;
+        if (nc + 1 < nt && P[nc + 1] == e0 + kStep) ++nc;
+        cur = nc;
+        wave_lds_sync();
+    }
+    return hits;
+}
+
+struct alignas(16) SmallLds {
     int64_t base[kSmallMax];  // per target row: row start minus its prefix
     int32_t key[kSmallHash];  // hashed source list, -1 = empty
     int32_t P[kSmallMax + 1]; // exclusive prefix of row lengths, then the total
     int32_t cnt[kSmallMax];   // per-position counts (per-node mode)
-    int32_t flag[64];         // row starts inside the current window
     uint8_t pos[kSmallHash];  // list position of each hashed id
     uint8_t tpos[kSmallMax];  // list position of each target row
+    uint8_t flag[kStep];      // row starts inside the current step
 };
 
+// One source s whose list (a entries, 2 <= a <= 128) is already in registers:
+// x0 = L[lane], x1 = L[64 + lane].
 template <bool PER_NODE>
-__device__ __forceinline__ uint64_t source_small(SmallLds &S, const int32_t *__restrict__ col,
-                                                 const int64_t *__restrict__ off, int64_t *__restrict__ tv, int64_t m,
-                                                 int32_t s, int64_t rs, int32_t a, int lane) {
+__device__ __forceinline__ uint64_t source_small(SmallLds &S, gptr_t<const int32_t> col, gptr_t<const int64_t> off,
+                                                 int64_t *__restrict__ tv, int64_t m, int32_t s, int32_t a,
+                                                 int32_t x0, int32_t x1, int lane) {
     const bool h0 = lane < a, h1 = lane + 64 < a;
-    const int32_t x0 = h0 ? col[rs + lane] : 0;
-    const int32_t x1 = h1 ? col[rs + 64 + lane] : 0;
-    uint32_t sl0 = 0, sl1 = 0;
     if (h0) {
-        sl0 = hash_slot(x0, kSmallHashBits);
-        while (atomicCAS(&S.key[sl0], -1, x0) != -1) sl0 = (sl0 + 1) & (kSmallHash - 1);
-        S.pos[sl0] = (uint8_t)lane;
+        uint32_t sl = hash_slot(x0, kSmallHashBits);
+        while (atomicCAS(&S.key[sl], -1, x0) != -1) sl = (sl + 1) & (kSmallHash - 1);
+        if (PER_NODE) S.pos[sl] = (uint8_t)lane;
     }
     if (h1) {
-        sl1 = hash_slot(x1, kSmallHashBits);
-        while (atomicCAS(&S.key[sl1], -1, x1) != -1) sl1 = (sl1 + 1) & (kSmallHash - 1);
-        S.pos[sl1] = (uint8_t)(64 + lane);
+        uint32_t sl = hash_slot(x1, kSmallHashBits);
+        while (atomicCAS(&S.key[sl], -1, x1) != -1) sl = (sl + 1) & (kSmallHash - 1);
+        if (PER_NODE) S.pos[sl] = (uint8_t)(64 + lane);
     }
-    // rows of t_0 .. t_{a-2}; empty rows are dropped so row starts are distinct
-    int32_t b0 = 0, b1 = 0;
-    int64_t r0 = 0, r1 = 0;
-    if (lane < a - 1) {
-        r0 = off[x0];
-        b0 = (int32_t)(off[x0 + 1] - r0);
-    }
-    if (lane + 64 < a - 1) {
-        r1 = off[x1];
-        b1 = (int32_t)(off[x1 + 1] - r1);
-    }
+    // rows of t_0 .. t_{a-2}; empty rows are dropped so row starts are distinct.
+    // Loads are unconditional (x0 / x1 hold valid labels in every lane) so all
+    // four are in flight together.
+    const int64_t r0 = off[x0], e0r = off[x0 + 1];
+    const int64_t r1 = off[x1], e1r = off[x1 + 1];
+    const int32_t b0 = lane < a - 1 ? (int32_t)(e0r - r0) : 0;
+    const int32_t b1 = lane + 64 < a - 1 ? (int32_t)(e1r - r1) : 0;
     const uint64_t m0 = __ballot(b0 > 0), m1 = __ballot(b1 > 0);
     const int n0 = popc64(m0);
     const int32_t inc0 = wave_inclusive_sum(b0);
@@ -141,41 +245,11 @@ __device__ __forceinline__ uint64_t source_small(SmallLds &S, const int32_t *__r
     if (lane == 0) S.P[nt] = total;
     wave_lds_sync();
 
-    uint64_t hits = 0;
-    int cur = 0;  // row holding the window's first id
-    const uint64_t upto = lanemask_lt() | (1ull << lane);
-    for (int32_t e0 = 0; e0 < total; e0 += 64) {
-        const int jj = cur + 1 + lane;
-        if (jj < nt) {
-            const int32_t p = S.P[jj] - e0;
-            if (p < 64) S.flag[p] = 1;
-        }
-        wave_lds_sync();
-        const uint64_t M = __ballot(S.flag[lane] != 0);
-        S.flag[lane] = 0;
-        const int seg = cur + popc64(M & upto);
-        const int32_t e = e0 + lane;
-        const int64_t at = e < total ? S.base[seg] + e : -1;
-        if ((uint64_t)at < (uint64_t)m) {
-            const int32_t w = col[at];
-            uint32_t sl = hash_slot(w, kSmallHashBits);
-            int32_t kk;
-            while ((kk = S.key[sl]) != w && kk != -1) sl = (sl + 1) & (kSmallHash - 1);
-            if (kk == w) {
-                ++hits;
-                if (PER_NODE) {
-                    atomicAdd(&S.cnt[S.pos[sl]], 1);
-                    atomicAdd(&S.cnt[S.tpos[seg]], 1);
-                }
-            }
-        }
-        int nc = cur + popc64(M);
-        if (nc + 1 < nt && S.P[nc + 1] == e0 + 64) ++nc;
-        cur = nc;
-        wave_lds_sync();
-    }
+    const int32_t e_end = ((total + kStep - 1) / kStep) * kStep;
+    const uint32_t hits = walk_steps<kSmallHashBits, PER_NODE, true, uint8_t>(
+        S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag, col, m, nt, total, 0, 0, e_end, 0, a, 0, tv);
     if (PER_NODE) {
-        const uint64_t hs = wave_sum(hits);
+        const uint64_t hs = wave_sum((uint64_t)hits);
         wave_lds_sync();
         if (h0) {
             const int32_t c = S.cnt[lane];
@@ -193,14 +267,17 @@ __device__ __forceinline__ uint64_t source_small(SmallLds &S, const int32_t *__r
         }
         if (lane == 0 && hs) add_u64(&tv[s], hs);
     }
-    if (h0) S.key[sl0] = -1;
-    if (h1) S.key[sl1] = -1;
+    // empty the whole table (two 16-byte stores per lane)
+    static_assert(kSmallHash == 64 * 8, "table clear assumes 8 slots per lane");
+    int4 *kv = reinterpret_cast<int4 *>(S.key);
+    kv[lane] = make_int4(-1, -1, -1, -1);
+    kv[64 + lane] = make_int4(-1, -1, -1, -1);
     wave_lds_sync();
-    return hits;
+    return (uint64_t)hits;
 }
 
 template <bool PER_NODE>
-__global__ __launch_bounds__(kSmallWaves * 64) void k_count_small(const CountDesc *__restrict__ descs, int ndesc,
+__global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_count_small(const CountDesc *__restrict__ descs, int ndesc,
                                                                   int64_t total_tasks, uint32_t *__restrict__ head,
                                                                   int nworkers) {
     __shared__ SmallLds lds[kSmallWaves];
@@ -208,14 +285,14 @@ __global__ __launch_bounds__(kSmallWaves * 64) void k_count_small(const CountDes
     SmallLds &S = lds[wave];
     for (int i = lane; i < kSmallHash; i += 64) S.key[i] = -1;
     for (int i = lane; i < kSmallMax; i += 64) S.cnt[i] = 0;
-    S.flag[lane] = 0;
+    for (int i = lane; i < kStep; i += 64) S.flag[i] = 0;
     wave_lds_sync();
 
     int64_t c = (int64_t)blockIdx.x * kSmallWaves + wave;
     while (c < total_tasks) {
         const int h = ndesc > 1 ? find_desc(descs, ndesc, c, false) : 0;
-        const int32_t *__restrict__ col = descs[h].col;
-        const int64_t *__restrict__ off = descs[h].off;
+        const gptr_t<const int32_t> col = gview(descs[h].col);
+        const gptr_t<const int64_t> off = gview(descs[h].off);
         int64_t *__restrict__ tv = descs[h].tv;
         const int64_t m = descs[h].m;
         const int64_t lt = c - descs[h].task_base;
@@ -224,19 +301,35 @@ __global__ __launch_bounds__(kSmallWaves * 64) void k_count_small(const CountDes
         const int small_max = descs[h].small_max;
         uint64_t tri = 0;
         for (int32_t s0 = v0; s0 < v1; s0 += 64) {
-            const int32_t sv = s0 + lane;
-            int64_t o0 = 0;
-            int32_t a = 0;
-            if (sv < v1) {
-                o0 = off[sv];
-                a = (int32_t)(off[sv + 1] - o0);
-            }
-            uint64_t work = __ballot(a >= 2 && a <= small_max);
+            const int32_t sv = min(s0 + lane, v1 - 1);
+            const int64_t o0 = off[sv], o1 = off[sv + 1];
+            const int32_t al = s0 + lane < v1 ? (int32_t)(o1 - o0) : 0;
+            uint64_t work = __ballot(al >= 2 && al <= small_max);
+            if (!work) continue;
+            // the list of the next source is loaded while the current one is counted;
+            // indices are clamped into the list so every lane loads a valid label
+            int j = __ffsll((unsigned long long)work) - 1;
+            int32_t a = readlane32(al, j);
+            int64_t rs = readlane64(o0, j);
+            int32_t x0 = col[rs + min(lane, a - 1)];
+            int32_t x1 = col[rs + min(lane + 64, a - 1)];
             while (work) {
-                const int j = __ffsll((unsigned long long)work) - 1;
                 work &= work - 1;
-                tri += source_small<PER_NODE>(S, col, off, tv, m, s0 + j, readlane64(o0, j), readlane32(a, j),
-                                              lane);
+                int jn = j, an = a;
+                int64_t rn = rs;
+                if (work) {
+                    jn = __ffsll((unsigned long long)work) - 1;
+                    an = readlane32(al, jn);
+                    rn = readlane64(o0, jn);
+                }
+                const int32_t nx0 = col[rn + min(lane, an - 1)];
+                const int32_t nx1 = col[rn + min(lane + 64, an - 1)];
+                tri += source_small<PER_NODE>(S, col, off, tv, m, s0 + j, a, x0, x1, lane);
+                j = jn;
+                a = an;
+                rs = rn;
+                x0 = nx0;
+                x1 = nx1;
             }
         }
         tri = wave_sum(tri);
@@ -256,7 +349,7 @@ struct BigLds {
     int32_t cnt[kLdsMax];
     int16_t pos[kBigHash];
     int16_t tpos[kLdsMax];
-    int32_t flag[kBigWaves][64];
+    uint8_t flag[kBigWaves][kStep];
     int32_t wsum[kBigWaves];
     int32_t wcnt[kBigWaves];
     uint64_t whits[kBigWaves];
@@ -265,7 +358,7 @@ struct BigLds {
 
 // Lays out the rows of targets i in [i0, i1) (positions in the source list)
 // into P / base / tpos (tpos relative to i0).  Returns (rows, total ids).
-__device__ __forceinline__ void big_rows(BigLds &S, const int32_t *__restrict__ col, const int64_t *__restrict__ off,
+__device__ __forceinline__ void big_rows(BigLds &S, gptr_t<const int32_t> col, gptr_t<const int64_t> off,
                                          int64_t rs, int32_t i0, int32_t i1, int32_t *nt_out, int32_t *total_out) {
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     int32_t carry_n = 0, carry_sum = 0;
@@ -313,84 +406,33 @@ __device__ __forceinline__ void big_rows(BigLds &S, const int32_t *__restrict__ 
     *total_out = carry_sum;
 }
 
-// Walks this wave's share of the virtual sequence.  in_lds: probe the LDS
-// hash; otherwise binary search in the sorted list col[rs .. rs+a).
+// This wave's contiguous share of the virtual sequence, in whole steps.
 template <bool PER_NODE>
-__device__ __forceinline__ uint64_t big_windows(BigLds &S, const int32_t *__restrict__ col, int64_t *__restrict__ tv,
+__device__ __forceinline__ uint64_t big_windows(BigLds &S, gptr_t<const int32_t> col, int64_t *__restrict__ tv,
                                                 int64_t m, int64_t rs, int32_t a, int32_t i0, int32_t nt,
                                                 int32_t total, bool in_lds) {
-    const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    const int32_t nwin = (total + 63) / 64;
-    const int32_t per = (nwin + kBigWaves - 1) / kBigWaves;
-    const int32_t w0 = wave * per;
-    const int32_t w1 = min(nwin, w0 + per);
-    uint64_t hits = 0;
-    if (w0 >= w1) return 0;
-    int32_t *flag = S.flag[wave];
-    // row holding id w0*64: last row whose start is <= it
-    int cur;
-    {
-        const int32_t e = w0 * 64;
-        int lo = 0, hi = nt - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (S.P[mid] <= e)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        cur = lo;
+    const int wave = threadIdx.x >> 6;
+    const int32_t nsteps = (total + kStep - 1) / kStep;
+    const int32_t per = (nsteps + kBigWaves - 1) / kBigWaves;
+    const int32_t s0 = wave * per;
+    const int32_t s1 = min(nsteps, s0 + per);
+    if (s0 >= s1) return 0;
+    const int32_t e_begin = s0 * kStep;
+    int lo = 0, hi = nt - 1;  // row holding e_begin: last row whose start is <= it
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (S.P[mid] <= e_begin)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
-    const uint64_t upto = lanemask_lt() | (1ull << lane);
-    for (int32_t e0 = w0 * 64; e0 < w1 * 64; e0 += 64) {
-        const int jj = cur + 1 + lane;
-        if (jj < nt) {
-            const int32_t p = S.P[jj] - e0;
-            if (p < 64) flag[p] = 1;
-        }
-        wave_lds_sync();
-        const uint64_t M = __ballot(flag[lane] != 0);
-        flag[lane] = 0;
-        const int seg = cur + popc64(M & upto);
-        const int32_t e = e0 + lane;
-        const int64_t at = e < total ? S.base[seg] + e : -1;
-        if ((uint64_t)at < (uint64_t)m) {
-            const int32_t w = col[at];
-            if (in_lds) {
-                uint32_t sl = hash_slot(w, kBigHashBits);
-                int32_t kk;
-                while ((kk = S.key[sl]) != w && kk != -1) sl = (sl + 1) & (kBigHash - 1);
-                if (kk == w) {
-                    ++hits;
-                    if (PER_NODE) {
-                        atomicAdd(&S.cnt[S.pos[sl]], 1);
-                        atomicAdd(&S.cnt[S.tpos[seg]], 1);
-                    }
-                }
-            } else {
-                int32_t lo = 0, hi = a;
-                while (lo < hi) {
-                    const int32_t mid = (lo + hi) >> 1;
-                    if (col[rs + mid] < w)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
-                }
-                if (lo < a && col[rs + lo] == w) {
-                    ++hits;
-                    if (PER_NODE) {
-                        add_u64(&tv[w], 1);
-                        add_u64(&tv[col[rs + i0 + S.tpos[seg]]], 1);
-                    }
-                }
-            }
-        }
-        int nc = cur + popc64(M);
-        if (nc + 1 < nt && S.P[nc + 1] == e0 + 64) ++nc;
-        cur = nc;
-        wave_lds_sync();
-    }
-    return hits;
+    if (in_lds)
+        return walk_steps<kBigHashBits, PER_NODE, true, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
+                                                                 S.flag[wave], col, m, nt, total, lo, e_begin,
+                                                                 s1 * kStep, rs, a, i0, tv);
+    return walk_steps<kBigHashBits, PER_NODE, false, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
+                                                              S.flag[wave], col, m, nt, total, lo, e_begin,
+                                                              s1 * kStep, rs, a, i0, tv);
 }
 
 template <bool PER_NODE>
@@ -401,7 +443,7 @@ __global__ __launch_bounds__(kBigThreads) void k_count_big(const CountDesc *__re
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < kBigHash; i += kBigThreads) S.key[i] = -1;
     for (int i = threadIdx.x; i < kLdsMax; i += kBigThreads) S.cnt[i] = 0;
-    for (int i = threadIdx.x; i < kBigWaves * 64; i += kBigThreads) (&S.flag[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < kBigWaves * kStep; i += kBigThreads) (&S.flag[0][0])[i] = 0;
     if (threadIdx.x == 0) S.item = blockIdx.x;
     __syncthreads();
 
@@ -409,8 +451,8 @@ __global__ __launch_bounds__(kBigThreads) void k_count_big(const CountDesc *__re
         const int64_t item = S.item;
         if (item >= total_big) break;
         const int h = ndesc > 1 ? find_desc(descs, ndesc, item, true) : 0;
-        const int32_t *__restrict__ col = descs[h].col;
-        const int64_t *__restrict__ off = descs[h].off;
+        const gptr_t<const int32_t> col = gview(descs[h].col);
+        const gptr_t<const int64_t> off = gview(descs[h].off);
         int64_t *__restrict__ tv = descs[h].tv;
         const int64_t m = descs[h].m;
         const int32_t s = descs[h].big[item - descs[h].big_base];
@@ -475,6 +517,20 @@ __global__ void k_scatter(const int64_t *__restrict__ tv, const int32_t *__restr
 }  // namespace
 
 int max_small_list() { return kSmallMax; }
+
+int small_kernel_waves_per_cu(bool per_node) {
+    static int cached[2] = {0, 0};
+    int &c = cached[per_node ? 1 : 0];
+    if (!c) {
+        int blocks = 0;
+        if (per_node)
+            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<true>, kSmallWaves * 64, 0));
+        else
+            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<false>, kSmallWaves * 64, 0));
+        c = std::max(1, blocks) * kSmallWaves;
+    }
+    return c;
+}
 int max_lds_list() { return kLdsMax; }
 
 int device_cu_count() {
@@ -487,7 +543,10 @@ int device_cu_count() {
 void count_launch(const CountLaunch &L, hipStream_t s) {
     const int lds_max = L.lds_max < 2 ? kLdsMax : (L.lds_max > kLdsMax ? kLdsMax : L.lds_max);
     if (L.total_tasks > 0) {
-        const int blocks = (int)ceil_div(L.workers, kSmallWaves);
+        // never launch more workers than can be resident at once: a worker that
+        // starts late would hold its first task until the end
+        const int resident = small_kernel_waves_per_cu(L.per_node) / kSmallWaves * device_cu_count();
+        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(L.workers, kSmallWaves), resident));
         if (L.per_node)
             k_count_small<true><<<blocks, kSmallWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_tasks, L.heads,
                                                                     blocks * kSmallWaves);

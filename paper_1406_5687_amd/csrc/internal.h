@@ -96,6 +96,7 @@ void scatter_per_node(const int64_t *tv, const int32_t *perm, int64_t n, int64_t
 
 int device_cu_count();
 int max_small_list();
+int small_kernel_waves_per_cu(bool per_node);  // resident waves per CU
 int max_lds_list();
 
 }  // namespace tc
