@@ -15,6 +15,7 @@
 //   6. costs and tasks     -- f per node (Sections IV-B, IV-F, V-A), prefix sums,
 //                             Eq. (1)/(2) targets, one binary search per task boundary
 #include <algorithm>
+#include <cstring>
 
 #include "internal.h"
 
@@ -70,18 +71,75 @@ __global__ void k_edge_keys(const int32_t *__restrict__ src, const int32_t *__re
     }
 }
 
-// Step 1b: first occurrence of each valid key.
-__global__ void k_unique_flags(const uint64_t *__restrict__ keys, int64_t n, uint32_t *__restrict__ flag) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t k = keys[i];
-        flag[i] = (k != kInvalid && (i == 0 || keys[i - 1] != k)) ? 1u : 0u;
+// Unique selection in two passes over tiles of sorted keys: count the first
+// occurrences per tile, then (after a scan of the tile counts) write them.
+constexpr int kSelItems = 16;
+constexpr int kSelTile = kThreads * kSelItems;
+
+__device__ __forceinline__ bool first_of_run(const uint64_t *keys, int64_t i, uint64_t k) {
+    return k != kInvalid && (i == 0 || keys[i - 1] != k);
+}
+
+__global__ __launch_bounds__(kThreads) void k_unique_count(const uint64_t *__restrict__ keys, int64_t n,
+                                                           int64_t *__restrict__ partial) {
+    __shared__ int64_t wsum[kThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kSelTile;
+    int64_t c = 0;
+#pragma unroll
+    for (int j = 0; j < kSelItems; ++j) {
+        const int64_t i = base + (int64_t)j * kThreads + threadIdx.x;
+        if (i < n) c += first_of_run(keys, i, keys[i]) ? 1 : 0;
+    }
+    c = wave_sum(c);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < kThreads / 64; ++w) t += wsum[w];
+        partial[blockIdx.x] = t;
     }
 }
 
-__global__ void k_compact_keys(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ flag,
-                               const int64_t *__restrict__ pos, int64_t n, uint64_t *__restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        if (flag[i]) out[pos[i]] = keys[i];
+// Each wave owns a contiguous quarter of the tile and walks it 64 keys at a
+// time, so both the reads and the writes of selected keys are coalesced.
+__global__ __launch_bounds__(kThreads) void k_unique_write(const uint64_t *__restrict__ keys, int64_t n,
+                                                           const int64_t *__restrict__ offsets,
+                                                           uint64_t *__restrict__ out) {
+    constexpr int kWaves = kThreads / 64;
+    __shared__ int32_t wcount[kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t wbase = (int64_t)blockIdx.x * kSelTile + (int64_t)wave * 64 * kSelItems;
+    uint64_t k[kSelItems];
+    uint64_t sel[kSelItems];
+    int32_t cnt = 0;
+#pragma unroll
+    for (int r = 0; r < kSelItems; ++r) {
+        const int64_t i = wbase + r * 64 + lane;
+        k[r] = i < n ? keys[i] : kInvalid;
+    }
+    const int64_t i0 = wbase - 1;
+    uint64_t carry = (i0 >= 0 && i0 < n) ? keys[i0] : kInvalid;  // key before this wave's range
+#pragma unroll
+    for (int r = 0; r < kSelItems; ++r) {
+        uint64_t prev = __shfl_up(k[r], 1, 64);
+        if (lane == 0) prev = carry;
+        const int64_t i = wbase + r * 64 + lane;
+        const bool f = k[r] != kInvalid && (i == 0 || prev != k[r]);
+        sel[r] = __ballot(f);
+        cnt += popc64(sel[r]);
+        carry = __shfl(k[r], 63, 64);
+    }
+    if (lane == 0) wcount[wave] = cnt;
+    __syncthreads();
+    int64_t o = offsets[blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w)
+        if (w < wave) o += wcount[w];
+#pragma unroll
+    for (int r = 0; r < kSelItems; ++r) {
+        if ((sel[r] >> lane) & 1ull) out[o + popc64(sel[r] & lanemask_lt())] = k[r];
+        o += popc64(sel[r]);
+    }
 }
 
 // Lanes of a wave holding equal, contiguous values of `key` form a run; the
@@ -100,9 +158,12 @@ __device__ __forceinline__ T run_sum_at_end(int64_t key, T val, bool *is_end) {
     return val;
 }
 
-// Step 2: degrees.  Keys are sorted, so the lower endpoints arrive in runs.
-__global__ void k_degrees(const uint64_t *__restrict__ keys, int64_t m, int gb, int32_t *__restrict__ deg) {
-    const uint64_t mask = (gb >= 64) ? ~0ull : ((1ull << gb) - 1);
+// Step 2: degrees.  Keys are sorted, so the lower endpoints arrive in runs and
+// are counted per run; the upper endpoints are written out, sorted, and then
+// counted the same way (no per-edge atomics).
+__global__ void k_degrees_lo(const uint64_t *__restrict__ keys, int64_t m, int gb, int32_t *__restrict__ deg,
+                             uint32_t *__restrict__ hi_out) {
+    const uint64_t mask = (1ull << gb) - 1;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
         const int64_t i = base + threadIdx.x;
@@ -110,11 +171,22 @@ __global__ void k_degrees(const uint64_t *__restrict__ keys, int64_t m, int gb, 
         if (i < m) {
             const uint64_t k = keys[i];
             lo = (int64_t)(k >> gb);
-            atomicAdd(&deg[(int64_t)(k & mask)], 1);
+            hi_out[i] = (uint32_t)(k & mask);
         }
         bool end;
         const int32_t cnt = run_sum_at_end<int32_t>(lo, i < m ? 1 : 0, &end);
         if (i < m && end) atomicAdd(&deg[lo], cnt);
+    }
+}
+
+__global__ void k_run_counts(const uint32_t *__restrict__ v, int64_t m, int32_t *__restrict__ deg) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t x = i < m ? (int64_t)v[i] : -1 - (int64_t)threadIdx.x;
+        bool end;
+        const int32_t cnt = run_sum_at_end<int32_t>(x, i < m ? 1 : 0, &end);
+        if (i < m && end) atomicAdd(&deg[x], cnt);
     }
 }
 
@@ -175,18 +247,25 @@ __global__ void k_csr_rows(const uint64_t *__restrict__ okeys, int64_t m, int gb
 
 // Step 6a: per-node cost f (degree-order labels) over stored pairs (s, t).
 //   kind PRIOR: f[s] += dhat_s + dhat_t;   kind NEW: f[t] += dhat_t + dhat_s.
-__global__ void k_edge_costs(const int64_t *__restrict__ off, const int32_t *__restrict__ col, const uint64_t *okeys,
-                             int64_t m, int gb, int kind, int64_t *__restrict__ f) {
+__global__ void k_row_lengths(const int64_t *__restrict__ off, int64_t N, int32_t *__restrict__ dh) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x)
+        dh[r] = (int32_t)(off[r + 1] - off[r]);
+}
+
+__global__ void k_edge_costs(const int32_t *__restrict__ dh, const uint64_t *__restrict__ okeys, int64_t m, int gb,
+                             int kind, int64_t *__restrict__ f) {
+    const uint64_t mask = (1ull << gb) - 1;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
         const int64_t i = base + threadIdx.x;
         int64_t s = -1 - (int64_t)threadIdx.x;
         int64_t c = 0;
-        int32_t t = 0;
+        int64_t t = 0;
         if (i < m) {
-            s = (int64_t)(okeys[i] >> gb);
-            t = col[i];
-            c = (off[s + 1] - off[s]) + (off[(int64_t)t + 1] - off[t]);
+            const uint64_t k = okeys[i];
+            s = (int64_t)(k >> gb);
+            t = (int64_t)(k & mask);
+            c = (int64_t)dh[s] + (int64_t)dh[t];
         }
         if (kind == TC_COST_PRIOR) {
             bool end;
@@ -309,62 +388,120 @@ void fill_zero(void *p, size_t bytes, hipStream_t s) {
     TC_LAUNCH_CHECK();
 }
 
-// Eq. (1)/(2) cost targets (see the schedule reading in the design notes of
-// the oracle and of this library): initial W targets ceil((i+1) H / W) with
+// Eq. (1)/(2) cost targets: initial W targets ceil((i+1) H / W) with
 // H = ceil(total/2); then C += max(ceil((total - C) / W), min_chunk) until C
-// reaches total, which ends the last task at the end of the node range.
+// reaches total, which ends the last task at the end of the node range
+// (encoded as -1).  The division by W uses a precomputed reciprocal.
 std::vector<int64_t> task_targets(int64_t total, int32_t W, int64_t min_chunk) {
     std::vector<int64_t> t;
     const int64_t H = (total + 1) / 2;
+    const uint64_t w = (uint64_t)W;
+    const uint64_t magic = ~0ull / w;  // floor((2^64 - 1) / W)
+    auto ceil_div_w = [&](uint64_t r) -> uint64_t {
+        uint64_t q = (uint64_t)(((unsigned __int128)r * magic) >> 64);
+        uint64_t rem = r - q * w;
+        while (rem >= w) {
+            ++q;
+            rem -= w;
+        }
+        return q + (rem != 0);
+    };
     t.reserve((size_t)W * 8 + 16);
-    for (int32_t i = 0; i < W; ++i) t.push_back(((int64_t)(i + 1) * H + W - 1) / W);
+    for (int32_t i = 0; i < W; ++i) t.push_back((int64_t)ceil_div_w((uint64_t)(i + 1) * (uint64_t)H));
     int64_t C = H;
     while (C < total) {
-        int64_t step = (total - C + W - 1) / W;
+        int64_t step = (int64_t)ceil_div_w((uint64_t)(total - C));
         if (step < min_chunk) step = min_chunk;
         C += step;
         t.push_back(C >= total ? -1 : C);
     }
-    if (t.empty() || t.back() != -1) t.push_back(-1);
-    // identical to the oracle's boundary rule: a final target equal to an
-    // earlier end would repeat the end boundary; keep the sequence as is.
+    if (t.back() != -1) t.push_back(-1);
     return t;
 }
 
+namespace {
+// Page-locked staging for small host-to-device uploads (grown on demand, kept
+// for the life of the thread; each build synchronises before returning).
+struct PinnedStage {
+    void *p = nullptr;
+    size_t cap = 0;
+    void *get(size_t bytes) {
+        if (bytes > cap) {
+            if (p) (void)hipHostFree(p);
+            p = nullptr;
+            cap = 0;
+            const size_t want = std::max<size_t>(bytes, 1 << 20);
+            if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+                return nullptr;
+            }
+            cap = want;
+        }
+        return p;
+    }
+};
+thread_local PinnedStage t_stage;
+}  // namespace
+
+void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp, Allocator &al,
+                Allocator &tmp, hipStream_t s, Oriented &out);
+
 void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
                            Allocator &al, hipStream_t s, Oriented &out) {
+    const int64_t N = pk.N, M_in = pk.M_in;
+    // One scratch region for every temporary of the build (bump allocation),
+    // sized from the input: keys 16 B/edge, sort tables < 3 B/edge, node
+    // arrays < 64 B/node, task targets.
+    const size_t arena_bytes = (size_t)M_in * 19 + (size_t)N * 64 + (size_t)bp.workers * 128 + (8u << 20);
+    void *arena = al.get(arena_bytes);
+    Allocator tmp = al;
+    tmp.arena = (uint8_t *)arena;
+    tmp.arena_size = arena_bytes;
+    tmp.arena_used = 0;
+    try {
+        build_into(src, dst, pk, bp, al, tmp, s, out);
+    } catch (...) {
+        al.put(arena, arena_bytes);
+        throw;
+    }
+    al.put(arena, arena_bytes);
+}
+
+void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp, Allocator &al,
+                Allocator &tmp, hipStream_t s, Oriented &out) {
     const int64_t N = pk.N, M_in = pk.M_in;
     const int k = pk.k;
     const int gb = std::max(1, bits_for((uint64_t)std::max<int64_t>(N - 1, 1)));  // bits of a packed label
 
     out.node_base = DevBuf<int64_t>(al, (size_t)k + 1);
     TC_HIP(hipMemcpyAsync(out.node_base.p, pk.node_base.data(), (k + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    DevBuf<int64_t> edge_base(al, (size_t)k + 1);
+    DevBuf<int64_t> edge_base(tmp, (size_t)k + 1);
     TC_HIP(hipMemcpyAsync(edge_base.p, pk.edge_base.data(), (k + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    DevBuf<uint32_t> err(al, 4);
+    DevBuf<uint32_t> err(tmp, 4);
     fill_zero(err.p, 16, s);
 
     // ---- 1. canonical edge set
     int64_t M = 0;
-    DevBuf<uint64_t> ka(al, (size_t)std::max<int64_t>(M_in, 1));
-    DevBuf<uint64_t> kb(al, (size_t)std::max<int64_t>(M_in, 1));
+    DevBuf<uint64_t> ka(tmp, (size_t)std::max<int64_t>(M_in, 1));
+    DevBuf<uint64_t> kb(tmp, (size_t)std::max<int64_t>(M_in, 1));
     uint64_t *ukeys = kb.p;
     if (M_in > 0) {
         k_edge_keys<<<grid_for(M_in, 4), kThreads, 0, s>>>(src, dst, M_in, edge_base.p, out.node_base.p, k, gb, ka.p,
                                                             err.p);
         TC_LAUNCH_CHECK();
-        uint64_t *sorted = radix_sort_u64(ka.p, kb.p, M_in, 0, 2 * gb, al, s);
+        uint64_t *sorted = radix_sort_u64(ka.p, kb.p, M_in, 0, 2 * gb, tmp, s);
         uint64_t *other = sorted == ka.p ? kb.p : ka.p;
-        DevBuf<uint32_t> flag(al, (size_t)M_in);
-        DevBuf<int64_t> pos(al, (size_t)M_in + 1);
-        k_unique_flags<<<grid_for(M_in, 4), kThreads, 0, s>>>(sorted, M_in, flag.p);
+        const int64_t nt = ceil_div(M_in, kSelTile);
+        DevBuf<int64_t> part(tmp, (size_t)nt + 1);
+        k_unique_count<<<(unsigned)nt, kThreads, 0, s>>>(sorted, M_in, part.p);
         TC_LAUNCH_CHECK();
-        exclusive_scan(flag.p, pos.p, M_in, true, al, s);
-        k_compact_keys<<<grid_for(M_in, 4), kThreads, 0, s>>>(sorted, flag.p, pos.p, M_in, other);
+        exclusive_scan(part.p, part.p, nt, true, tmp, s);
+        k_unique_write<<<(unsigned)nt, kThreads, 0, s>>>(sorted, M_in, part.p, other);
         TC_LAUNCH_CHECK();
         ukeys = other;
         uint32_t herr = 0;
-        d2h(&M, pos.p + M_in, 1, s);
+        d2h(&M, part.p + nt, 1, s);
         d2h(&herr, err.p, 1, s);
         TC_HIP(hipStreamSynchronize(s));
         if (herr & 1u) throw Error(TC_ERR_ID_RANGE, "an edge endpoint is outside 0..n-1 of its graph");
@@ -373,25 +510,30 @@ void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing
     uint64_t *spare = ukeys == ka.p ? kb.p : ka.p;
 
     // ---- 2. degrees
-    DevBuf<int32_t> deg(al, (size_t)std::max<int64_t>(N, 1));
+    DevBuf<int32_t> deg(tmp, (size_t)std::max<int64_t>(N, 1));
     fill_zero(deg.p, deg.bytes(), s);
     if (M > 0) {
-        k_degrees<<<grid_for(M, 4), kThreads, 0, s>>>(ukeys, M, gb, deg.p);
+        uint32_t *hi = reinterpret_cast<uint32_t *>(spare);  // spare holds >= 2 M words
+        uint32_t *hi_tmp = hi + M;
+        k_degrees_lo<<<grid_for(M, 4), kThreads, 0, s>>>(ukeys, M, gb, deg.p, hi);
+        TC_LAUNCH_CHECK();
+        uint32_t *hs = radix_sort_u32(hi, hi_tmp, M, 0, gb, tmp, s);
+        k_run_counts<<<grid_for(M, 4), kThreads, 0, s>>>(hs, M, deg.p);
         TC_LAUNCH_CHECK();
     }
 
     // ---- 3. degree order
     out.perm = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(N, 1));
-    DevBuf<int32_t> rank(al, (size_t)std::max<int64_t>(N, 1));
+    DevBuf<int32_t> rank(tmp, (size_t)std::max<int64_t>(N, 1));
     const int vb = std::max(1, bits_for((uint64_t)std::max<int64_t>(pk.max_n - 1, 1)));
     const int db = std::max(1, bits_for((uint64_t)std::max<int64_t>(pk.max_n - 1, 1)));
     const int kb_bits = bits_for((uint64_t)(k - 1));
     if (kb_bits + db + vb > 64) throw Error(TC_ERR_TOO_LARGE, "too many graphs of this size in one handle");
     if (N > 0) {
-        DevBuf<uint64_t> ra(al, (size_t)N), rb(al, (size_t)N);
+        DevBuf<uint64_t> ra(tmp, (size_t)N), rb(tmp, (size_t)N);
         k_rank_keys<<<grid_for(N, 4), kThreads, 0, s>>>(deg.p, N, out.node_base.p, k, db, vb, ra.p);
         TC_LAUNCH_CHECK();
-        uint64_t *sorted = radix_sort_u64(ra.p, rb.p, N, 0, kb_bits + db + vb, al, s);
+        uint64_t *sorted = radix_sort_u64(ra.p, rb.p, N, 0, kb_bits + db + vb, tmp, s);
         k_rank_from_sorted<<<grid_for(N, 4), kThreads, 0, s>>>(sorted, N, out.node_base.p, db, vb, out.perm.p, rank.p);
         TC_LAUNCH_CHECK();
     }
@@ -399,37 +541,40 @@ void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing
     // ---- 4. orientation, 5. CSR
     out.col = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(M, 1));
     out.off = DevBuf<int64_t>(al, (size_t)N + 1);
-    DevBuf<int32_t> rowlen(al, (size_t)std::max<int64_t>(N, 1));
+    DevBuf<int32_t> rowlen(tmp, (size_t)std::max<int64_t>(N, 1));
     fill_zero(rowlen.p, rowlen.bytes(), s);
     uint64_t *okeys = nullptr;
     if (M > 0) {
         k_orient_keys<<<grid_for(M, 4), kThreads, 0, s>>>(ukeys, M, gb, rank.p, spare);
         TC_LAUNCH_CHECK();
-        okeys = radix_sort_u64(spare, ukeys, M, 0, 2 * gb, al, s);
+        okeys = radix_sort_u64(spare, ukeys, M, 0, 2 * gb, tmp, s);
         k_csr_rows<<<grid_for(M, 4), kThreads, 0, s>>>(okeys, M, gb, out.col.p, rowlen.p);
         TC_LAUNCH_CHECK();
     }
-    exclusive_scan(rowlen.p, out.off.p, N, true, al, s);
+    exclusive_scan(rowlen.p, out.off.p, N, true, tmp, s);
 
     // ---- 6. costs, wide lists, task table
-    DevBuf<int64_t> f(al, (size_t)std::max<int64_t>(N, 1));
+    DevBuf<int64_t> f(tmp, (size_t)std::max<int64_t>(N, 1));
     fill_zero(f.p, f.bytes(), s);
     if (M > 0 && (bp.cost_fn == TC_COST_PRIOR || bp.cost_fn == TC_COST_NEW)) {
-        k_edge_costs<<<grid_for(M, 4), kThreads, 0, s>>>(out.off.p, out.col.p, okeys, M, gb, bp.cost_fn, f.p);
+        int32_t *dh = reinterpret_cast<int32_t *>(rank.p);  // ranks are no longer needed
+        k_row_lengths<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, N, dh);
+        TC_LAUNCH_CHECK();
+        k_edge_costs<<<grid_for(M, 4), kThreads, 0, s>>>(dh, okeys, M, gb, bp.cost_fn, f.p);
         TC_LAUNCH_CHECK();
     }
-    DevBuf<uint32_t> wide(al, (size_t)std::max<int64_t>(N, 1));
-    DevBuf<int32_t> maxd(al, 1);
+    DevBuf<uint32_t> wide(tmp, (size_t)std::max<int64_t>(N, 1));
+    DevBuf<int32_t> maxd(tmp, 1);
     fill_zero(maxd.p, 4, s);
-    DevBuf<int64_t> F(al, (size_t)N + 1);
-    DevBuf<int64_t> widepos(al, (size_t)N + 1);
+    DevBuf<int64_t> F(tmp, (size_t)N + 1);
+    DevBuf<int64_t> widepos(tmp, (size_t)N + 1);
     if (N > 0) {
         k_node_costs<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, deg.p, out.perm.p, N, bp.cost_fn, bp.small_max,
                                                           f.p, wide.p, maxd.p);
         TC_LAUNCH_CHECK();
     }
-    exclusive_scan(f.p, F.p, N, true, al, s);
-    exclusive_scan(wide.p, widepos.p, N, true, al, s);
+    exclusive_scan(f.p, F.p, N, true, tmp, s);
+    exclusive_scan(wide.p, widepos.p, N, true, tmp, s);
     int64_t hv[2] = {0, 0};
     int32_t hmax = 0;
     d2h(&hv[0], F.p + N, 1, s);
@@ -453,8 +598,14 @@ void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing
     }
     std::vector<int64_t> tg = task_targets(out.total_cost, bp.workers, min_chunk);
     const int64_t ntg = (int64_t)tg.size();
-    DevBuf<int64_t> dtg(al, (size_t)ntg);
-    TC_HIP(hipMemcpyAsync(dtg.p, tg.data(), ntg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DevBuf<int64_t> dtg(tmp, (size_t)ntg);
+    void *pin = t_stage.get((size_t)ntg * sizeof(int64_t));
+    if (pin) {
+        std::memcpy(pin, tg.data(), ntg * sizeof(int64_t));
+        TC_HIP(hipMemcpyAsync(dtg.p, pin, ntg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    } else {
+        TC_HIP(hipMemcpyAsync(dtg.p, tg.data(), ntg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    }
     DevBuf<int32_t> bnd(al, (size_t)ntg + 1);
     k_task_bounds<<<grid_for(ntg + 1), kThreads, 0, s>>>(F.p, N, dtg.p, ntg, bnd.p);
     TC_LAUNCH_CHECK();

@@ -47,10 +47,20 @@ struct Allocator {
     uint64_t budget = 0;  // 0 = none
     uint64_t live = 0;
     uint64_t peak = 0;
+    // Optional bump region: requests are carved from it while it has room and
+    // released all at once by its owner (put() ignores them).
+    uint8_t *arena = nullptr;
+    size_t arena_size = 0;
+    size_t arena_used = 0;
 
     void *get(size_t bytes) {
         if (bytes == 0) bytes = 256;
         bytes = (bytes + 255) & ~size_t(255);
+        if (arena && arena_used + bytes <= arena_size) {
+            void *p = arena + arena_used;
+            arena_used += bytes;
+            return p;
+        }
         if (budget && live + bytes > budget)
             throw Error(TC_ERR_OUT_OF_MEMORY, "device budget exceeded: need " + std::to_string(live + bytes) +
                                                   " bytes, budget " + std::to_string(budget));
@@ -70,6 +80,7 @@ struct Allocator {
     }
     void put(void *p, size_t bytes) {
         if (!p) return;
+        if (arena && (uint8_t *)p >= arena && (uint8_t *)p < arena + arena_size) return;
         if (bytes == 0) bytes = 256;
         bytes = (bytes + 255) & ~size_t(255);
         if (fn_free)

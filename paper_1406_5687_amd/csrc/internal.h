@@ -16,6 +16,8 @@ void exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, bool write_tot
 // sort.hip -- LSD radix sort by bits [begin_bit, end_bit); returns the buffer holding the result
 uint64_t *radix_sort_u64(uint64_t *keys, uint64_t *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al,
                          hipStream_t s);
+uint32_t *radix_sort_u32(uint32_t *keys, uint32_t *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al,
+                         hipStream_t s);
 
 // build.hip -------------------------------------------------------------
 

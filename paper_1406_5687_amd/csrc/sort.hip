@@ -23,7 +23,8 @@ __device__ __forceinline__ int64_t key_index(int64_t tile_base, int wave, int r,
     return tile_base + (int64_t)wave * 64 * kSortRounds + r * 64 + lane;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+template <class K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K *__restrict__ keys, int64_t n, int shift,
                                                              int64_t nblocks, uint32_t *__restrict__ hist) {
     __shared__ uint32_t h[kRadix];
     for (int i = threadIdx.x; i < kRadix; i += kSortThreads) h[i] = 0;
@@ -43,13 +44,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__r
     for (int i = threadIdx.x; i < kRadix; i += kSortThreads) hist[(int64_t)i * nblocks + blockIdx.x] = h[i];
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t *__restrict__ keys,
-                                                                uint64_t *__restrict__ out, int64_t n, int shift,
-                                                                int64_t nblocks, const int64_t *__restrict__ base) {
+template <class K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K *__restrict__ keys, K *__restrict__ out,
+                                                                int64_t n, int shift, int64_t nblocks,
+                                                                const int64_t *__restrict__ base) {
     __shared__ uint32_t wcnt[kSortWaves][kRadix];
     __shared__ uint32_t bstart[kRadix];
     __shared__ int64_t gbase[kRadix];
-    __shared__ uint64_t stage[kSortTile];
+    __shared__ K stage[kSortTile];
     __shared__ uint32_t scan_tmp[kSortWaves];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -57,12 +59,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t *
     __syncthreads();
 
     const int64_t tile = (int64_t)blockIdx.x * kSortTile;
-    uint64_t k[kSortRounds];
+    K k[kSortRounds];
     uint32_t rank[kSortRounds];
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         const int64_t i = key_index(tile, wave, r, lane);
-        k[r] = i < n ? keys[i] : 0ull;
+        k[r] = i < n ? keys[i] : (K)0;
     }
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
@@ -111,40 +113,45 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t *
     __syncthreads();
     const int64_t valid = n - tile < kSortTile ? n - tile : kSortTile;
     for (int i = threadIdx.x; i < valid; i += kSortThreads) {
-        const uint64_t key = stage[i];
+        const K key = stage[i];
         const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
         const int64_t at = gbase[d] + (i - (int64_t)bstart[d]);
         if ((uint64_t)at < (uint64_t)n) out[at] = key;
     }
 }
 
-}  // namespace
-
-size_t radix_sort_scratch_bytes(int64_t n) {
-    const int64_t nb = ceil_div(n > 0 ? n : 1, kSortTile);
-    return (size_t)(nb * kRadix) * (sizeof(uint32_t) + sizeof(int64_t)) + 4096;
+template <class K>
+K *radix_sort_impl(K *keys, K *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al, hipStream_t s) {
+    if (n <= 1 || end_bit <= begin_bit) return keys;
+    const int64_t nb = ceil_div(n, kSortTile);
+    DevBuf<uint32_t> hist(al, (size_t)(nb * kRadix));
+    DevBuf<int64_t> base(al, (size_t)(nb * kRadix) + 1);
+    K *a = keys, *b = tmp;
+    for (int shift = begin_bit; shift < end_bit; shift += 8) {
+        k_radix_hist<K><<<(unsigned)nb, kSortThreads, 0, s>>>(a, n, shift, nb, hist.p);
+        TC_LAUNCH_CHECK();
+        exclusive_scan(hist.p, base.p, nb * kRadix, false, al, s);
+        k_radix_scatter<K><<<(unsigned)nb, kSortThreads, 0, s>>>(a, b, n, shift, nb, base.p);
+        TC_LAUNCH_CHECK();
+        K *t = a;
+        a = b;
+        b = t;
+    }
+    return a;
 }
+
+}  // namespace
 
 // Sorts keys[0..n) by bits [begin_bit, end_bit).  tmp must hold n keys.
 // Returns whichever of keys / tmp holds the result.
 uint64_t *radix_sort_u64(uint64_t *keys, uint64_t *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al,
                          hipStream_t s) {
-    if (n <= 1 || end_bit <= begin_bit) return keys;
-    const int64_t nb = ceil_div(n, kSortTile);
-    DevBuf<uint32_t> hist(al, (size_t)(nb * kRadix));
-    DevBuf<int64_t> base(al, (size_t)(nb * kRadix) + 1);
-    uint64_t *a = keys, *b = tmp;
-    for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        k_radix_hist<<<(unsigned)nb, kSortThreads, 0, s>>>(a, n, shift, nb, hist.p);
-        TC_LAUNCH_CHECK();
-        exclusive_scan(hist.p, base.p, nb * kRadix, false, al, s);
-        k_radix_scatter<<<(unsigned)nb, kSortThreads, 0, s>>>(a, b, n, shift, nb, base.p);
-        TC_LAUNCH_CHECK();
-        uint64_t *t = a;
-        a = b;
-        b = t;
-    }
-    return a;
+    return radix_sort_impl<uint64_t>(keys, tmp, n, begin_bit, end_bit, al, s);
+}
+
+uint32_t *radix_sort_u32(uint32_t *keys, uint32_t *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al,
+                         hipStream_t s) {
+    return radix_sort_impl<uint32_t>(keys, tmp, n, begin_bit, end_bit, al, s);
 }
 
 }  // namespace tc
