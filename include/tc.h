@@ -107,6 +107,15 @@ typedef struct tc_graph tc_graph;
  * TC_ERR_OUT_OF_MEMORY, TC_ERR_DEVICE.  *out is written only on TC_OK. */
 tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options *opt, tc_graph **out);
 
+/* Rebuilds the task table of an existing handle with the schedule options of
+ * opt (workers, cost_fn, min_chunk, small_max; 0 = automatic, as in
+ * tc_build_oriented) without touching the adjacency: per-node costs f
+ * (Sections IV-B, IV-F, V-A), the split between lists counted by one wave and
+ * by a whole workgroup, and the tasks of Eq. (1)/(2).  Counts are unchanged
+ * by construction (Section V-D); only their speed changes.  Errors:
+ * TC_ERR_INVALID_ARG, TC_ERR_OUT_OF_MEMORY, TC_ERR_DEVICE. */
+tc_status tc_graph_reschedule(tc_graph *g, const tc_options *opt);
+
 /* Total triangle count of each graph in the handle (Fig. 1; Fig. 10/11 task
  * by task): totals[k], int64, host or device per opt->outputs_on_device.
  * Counting one handle concurrently on two streams is not supported. */
@@ -135,10 +144,12 @@ typedef struct {
     int64_t wide_nodes;     /* nodes whose list is longer than small_max */
     uint64_t device_bytes;  /* device memory held by the handle */
     int32_t partitions;     /* node-range partitions used for counting (1 = resident) */
-    int32_t reserved0;
+    int32_t workers;        /* W of the task table (workers it was built for) */
     double last_count_ms;   /* device time of the counting kernels of the last count call made
                                with time_kernels = 1 (waits for it); -1 when none */
-    int32_t reserved[4];
+    int32_t small_max;      /* longest list counted by one wave in the current task table */
+    int32_t cost_fn;        /* cost function of the current task table */
+    int32_t reserved[2];
 } tc_graph_info_t;
 
 tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info);

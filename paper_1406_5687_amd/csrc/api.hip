@@ -200,6 +200,33 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
     return TC_OK;
 }
 
+tc_status tc_graph_reschedule(tc_graph *g, const tc_options *opt) {
+    if (!g) return fail(TC_ERR_INVALID_ARG, "graph must be non-NULL");
+    return guarded([&] {
+        check_options(opt);
+        tc_options o;
+        if (opt)
+            o = *opt;
+        else
+            tc_options_default(&o);
+        hipStream_t s = (hipStream_t)o.stream;
+        g->al.stream = s;
+        const int cus = tc::device_cu_count();
+        tc::BuildParams bp;
+        bp.workers = o.workers > 0 ? o.workers : tc::small_kernel_waves_per_cu(true) * cus;
+        bp.cost_fn = o.cost_fn;
+        bp.min_chunk = o.min_chunk;
+        bp.small_max = o.small_max > 0 ? std::min(o.small_max, tc::max_small_list()) : tc::max_small_list();
+        tc::reschedule_device(g->pk, bp, g->al, s, g->o);
+        g->workers = bp.workers;
+        g->small_max = bp.small_max;
+        g->cost_fn = bp.cost_fn;
+        // the per-handle count descriptor caches the wide list and small_max
+        g->desc.release();
+        g->desc_has_tv = false;
+    });
+}
+
 static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node, int64_t *totals) {
     return guarded([&] {
         check_options(opt);
@@ -353,6 +380,9 @@ tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info) {
     info->wide_nodes = g->o.nbig;
     info->device_bytes = g->al.live;
     info->partitions = 1;
+    info->workers = g->workers;
+    info->small_max = g->small_max;
+    info->cost_fn = g->cost_fn;
     info->last_count_ms = -1.0;
     if (g->timed) {
         float ms = 0.f;

@@ -277,11 +277,35 @@ __global__ void k_edge_costs(const int32_t *__restrict__ dh, const uint64_t *__r
     }
 }
 
+// Same costs computed row by row (used when the sorted pair keys are gone).
+__global__ void k_row_costs(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                            const int32_t *__restrict__ dh, int64_t N, int kind, int64_t *__restrict__ f) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = dh[r];
+        if (kind == TC_COST_PRIOR) {
+            int64_t sum = 0;
+            for (int64_t p = off[r]; p < off[r + 1]; ++p) sum += a + (int64_t)dh[col[p]];
+            atomicAdd((unsigned long long *)&f[r], (unsigned long long)sum);
+        } else {
+            for (int64_t p = off[r]; p < off[r + 1]; ++p) {
+                const int32_t t = col[p];
+                atomicAdd((unsigned long long *)&f[t], (unsigned long long)(a + (int64_t)dh[t]));
+            }
+        }
+    }
+}
+
+__global__ void k_gather_deg(const int32_t *__restrict__ deg_old, const int32_t *__restrict__ perm, int64_t N,
+                             int32_t *__restrict__ deg_rank) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x)
+        deg_rank[r] = deg_old[perm[r]];
+}
+
 // Step 6b: finish f for the per-node kinds, mask lists handled by whole
 // workgroups (their work is scheduled separately), flag them, and find the
 // longest list.
-__global__ void k_node_costs(const int64_t *__restrict__ off, const int32_t *__restrict__ deg_old,
-                             const int32_t *__restrict__ perm, int64_t N, int kind, int small_max,
+__global__ void k_node_costs(const int64_t *__restrict__ off, const int32_t *__restrict__ deg_rank, int64_t N,
+                             int kind, int small_max,
                              int64_t *__restrict__ f, uint32_t *__restrict__ wide, int32_t *__restrict__ max_dhat) {
     int32_t local_max = 0;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
@@ -289,7 +313,7 @@ __global__ void k_node_costs(const int64_t *__restrict__ off, const int32_t *__r
         local_max = max(local_max, (int32_t)dh);
         int64_t c = f[r];
         if (kind == TC_COST_ONE) c = 1;
-        if (kind == TC_COST_DEGREE) c = deg_old[perm[r]];
+        if (kind == TC_COST_DEGREE) c = deg_rank[r];
         const bool w = dh > small_max;
         f[r] = w ? 0 : c;
         wide[r] = w ? 1u : 0u;
@@ -446,14 +470,16 @@ thread_local PinnedStage t_stage;
 
 void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp, Allocator &al,
                 Allocator &tmp, hipStream_t s, Oriented &out);
+void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
+                   Oriented &out, const uint64_t *okeys, int gb);
 
 void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
                            Allocator &al, hipStream_t s, Oriented &out) {
     const int64_t N = pk.N, M_in = pk.M_in;
     // One scratch region for every temporary of the build (bump allocation),
     // sized from the input: keys 16 B/edge, sort tables < 3 B/edge, node
-    // arrays < 64 B/node, task targets.
-    const size_t arena_bytes = (size_t)M_in * 19 + (size_t)N * 64 + (size_t)bp.workers * 128 + (8u << 20);
+    // arrays < 72 B/node, task targets.
+    const size_t arena_bytes = (size_t)M_in * 19 + (size_t)N * 72 + (size_t)bp.workers * 128 + (8u << 20);
     void *arena = al.get(arena_bytes);
     Allocator tmp = al;
     tmp.arena = (uint8_t *)arena;
@@ -554,13 +580,31 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     exclusive_scan(rowlen.p, out.off.p, N, true, tmp, s);
 
     // ---- 6. costs, wide lists, task table
+    out.deg = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(N, 1));
+    if (N > 0) {
+        k_gather_deg<<<grid_for(N, 4), kThreads, 0, s>>>(deg.p, out.perm.p, N, out.deg.p);
+        TC_LAUNCH_CHECK();
+    }
+    schedule_into(pk, bp, al, tmp, s, out, okeys, gb);
+}
+
+// Step 6 proper.  okeys (sorted pair keys) speed up the edge costs when the
+// build still holds them; otherwise costs are computed row by row.
+void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
+                   Oriented &out, const uint64_t *okeys, int gb) {
+    const int64_t N = pk.N, M = out.M;
+    const int k = pk.k;
     DevBuf<int64_t> f(tmp, (size_t)std::max<int64_t>(N, 1));
     fill_zero(f.p, f.bytes(), s);
     if (M > 0 && (bp.cost_fn == TC_COST_PRIOR || bp.cost_fn == TC_COST_NEW)) {
-        int32_t *dh = reinterpret_cast<int32_t *>(rank.p);  // ranks are no longer needed
-        k_row_lengths<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, N, dh);
+        DevBuf<int32_t> dh(tmp, (size_t)N);
+        k_row_lengths<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, N, dh.p);
         TC_LAUNCH_CHECK();
-        k_edge_costs<<<grid_for(M, 4), kThreads, 0, s>>>(dh, okeys, M, gb, bp.cost_fn, f.p);
+        if (okeys) {
+            k_edge_costs<<<grid_for(M, 4), kThreads, 0, s>>>(dh.p, okeys, M, gb, bp.cost_fn, f.p);
+        } else {
+            k_row_costs<<<grid_for(N, 1), kThreads, 0, s>>>(out.off.p, out.col.p, dh.p, N, bp.cost_fn, f.p);
+        }
         TC_LAUNCH_CHECK();
     }
     DevBuf<uint32_t> wide(tmp, (size_t)std::max<int64_t>(N, 1));
@@ -569,8 +613,8 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     DevBuf<int64_t> F(tmp, (size_t)N + 1);
     DevBuf<int64_t> widepos(tmp, (size_t)N + 1);
     if (N > 0) {
-        k_node_costs<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, deg.p, out.perm.p, N, bp.cost_fn, bp.small_max,
-                                                          f.p, wide.p, maxd.p);
+        k_node_costs<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, out.deg.p, N, bp.cost_fn, bp.small_max, f.p,
+                                                          wide.p, maxd.p);
         TC_LAUNCH_CHECK();
     }
     exclusive_scan(f.p, F.p, N, true, tmp, s);
@@ -624,6 +668,23 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     }
     // Scratch buffers are released in stream order when this scope ends.
     TC_HIP(hipStreamSynchronize(s));
+}
+
+
+void reschedule_device(const Packing &pk, const BuildParams &bp, Allocator &al, hipStream_t s, Oriented &out) {
+    const size_t arena_bytes = (size_t)pk.N * 48 + (size_t)bp.workers * 128 + (8u << 20);
+    void *arena = al.get(arena_bytes);
+    Allocator tmp = al;
+    tmp.arena = (uint8_t *)arena;
+    tmp.arena_size = arena_bytes;
+    tmp.arena_used = 0;
+    try {
+        schedule_into(pk, bp, al, tmp, s, out, nullptr, 0);
+    } catch (...) {
+        al.put(arena, arena_bytes);
+        throw;
+    }
+    al.put(arena, arena_bytes);
 }
 
 }  // namespace tc

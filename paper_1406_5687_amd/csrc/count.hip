@@ -534,10 +534,15 @@ int small_kernel_waves_per_cu(bool per_node) {
 int max_lds_list() { return kLdsMax; }
 
 int device_cu_count() {
-    int dev = 0, cus = 0;
+    static int cached[64] = {0};
+    int dev = 0;
     TC_HIP(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+    int cus = 0;
     TC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    return cus > 0 ? cus : 1;
+    cus = cus > 0 ? cus : 1;
+    if (dev >= 0 && dev < 64) cached[dev] = cus;
+    return cus;
 }
 
 void count_launch(const CountLaunch &L, hipStream_t s) {

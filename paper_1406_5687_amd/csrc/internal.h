@@ -43,6 +43,7 @@ struct Oriented {
     DevBuf<int64_t> off;        // N+1
     DevBuf<int32_t> col;        // M
     DevBuf<int32_t> perm;       // N: packed caller label of each position
+    DevBuf<int32_t> deg;        // N: degree (distinct neighbours) of each position
     DevBuf<int64_t> node_base;  // k+1 (device copy)
     DevBuf<int32_t> bnd;        // tasks+1
     DevBuf<int32_t> gid;        // tasks (k > 1 only)
@@ -57,6 +58,10 @@ struct Oriented {
 // src/dst: packed input edges on the device (edge e of graph g at edge_base[g] + i).
 void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
                            Allocator &al, hipStream_t s, Oriented &out);
+
+// Recomputes the per-node costs, the wide-list bucket and the task table of
+// an existing build with new parameters (the adjacency is unchanged).
+void reschedule_device(const Packing &pk, const BuildParams &bp, Allocator &al, hipStream_t s, Oriented &out);
 
 // Fill helpers usable inside captured streams (no memset nodes).
 void fill_zero(void *p, size_t bytes, hipStream_t s);

@@ -22,6 +22,7 @@ COST_ONE, COST_DEGREE, COST_PRIOR, COST_NEW = range(4)
 EXPORTED = [
     "tc_options_default", "tc_build_oriented", "tc_count_total", "tc_count_per_node", "tc_count_batch",
     "tc_graph_info", "tc_export_csr", "tc_export_schedule", "tc_graph_free", "tc_status_str", "tc_last_error",
+    "tc_graph_reschedule",
 ]
 
 
@@ -82,9 +83,11 @@ class GraphInfo(ctypes.Structure):
         ("wide_nodes", ctypes.c_int64),
         ("device_bytes", ctypes.c_uint64),
         ("partitions", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("workers", ctypes.c_int32),
         ("last_count_ms", ctypes.c_double),
-        ("reserved", ctypes.c_int32 * 4),
+        ("small_max", ctypes.c_int32),
+        ("cost_fn", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -110,6 +113,7 @@ def load(path: str = LIB_PATH):
     lib.tc_count_batch.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(Options), P,
                                    ctypes.POINTER(P)]
     lib.tc_graph_info.argtypes = [P, ctypes.POINTER(GraphInfo)]
+    lib.tc_graph_reschedule.argtypes = [P, ctypes.POINTER(Options)]
     lib.tc_export_csr.argtypes = [P, ctypes.POINTER(Options), P, P, P]
     lib.tc_export_schedule.argtypes = [P, ctypes.POINTER(Options), P, P, ctypes.c_int64,
                                        ctypes.POINTER(ctypes.c_int64)]
@@ -120,7 +124,7 @@ def load(path: str = LIB_PATH):
     lib.tc_last_error.argtypes = []
     lib.tc_last_error.restype = ctypes.c_char_p
     for name in ("tc_build_oriented", "tc_count_total", "tc_count_per_node", "tc_count_batch", "tc_graph_info",
-                 "tc_export_csr", "tc_export_schedule"):
+                 "tc_export_csr", "tc_export_schedule", "tc_graph_reschedule"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -272,6 +276,13 @@ class Graph:
         _raise(lib.tc_count_per_node(self._h, ctypes.byref(o), ctypes.c_void_p(tv.ctypes.data),
                                      ctypes.c_void_p(tot.ctypes.data)))
         return tv[: self.n_total], tot[: self.k]
+
+    def reschedule(self, workers=0, cost_fn=COST_PRIOR, min_chunk=0, small_max=0):
+        """New task table for the same adjacency (tc_graph_reschedule); later
+        counts use it."""
+        self._kw.update(workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max)
+        o = self._opts()
+        _raise(load().tc_graph_reschedule(self._h, ctypes.byref(o)))
 
     # -- inspection
     def info(self) -> dict:
