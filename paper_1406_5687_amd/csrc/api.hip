@@ -78,7 +78,7 @@ void check_options(const tc_options *opt) {
 // Per-handle descriptor used by single-handle counts (kept on the device).
 void ensure_scratch(tc_graph *g, bool per_node, hipStream_t s) {
     g->al.stream = s;
-    if (!g->heads.p) g->heads = tc::DevBuf<uint32_t>(g->al, 4);
+    if (!g->heads.p) g->heads = tc::DevBuf<uint32_t>(g->al, 4);  // 3 queue heads
     if (!g->totals.p) g->totals = tc::DevBuf<int64_t>(g->al, (size_t)std::max(g->pk.k, 1));
     if (per_node && !g->tv.p) g->tv = tc::DevBuf<int64_t>(g->al, (size_t)std::max<int64_t>(g->pk.N, 1));
     if (!g->desc.p || (per_node && !g->desc_has_tv)) {
@@ -92,8 +92,11 @@ void ensure_scratch(tc_graph *g, bool per_node, hipStream_t s) {
         d.m = g->o.M;
         d.totals = g->totals.p;
         d.tv = g->tv.p;
+        d.nmed = g->o.nmed;
+        d.nbig = g->o.nbig;
         d.task_base = 0;
-        d.big_base = 0;
+        d.med_base = 0;
+        d.large_base = 0;
         d.k = g->pk.k;
         d.small_max = g->small_max;
         if (!g->desc.p) g->desc = tc::DevBuf<tc::CountDesc>(g->al, 1);
@@ -242,11 +245,12 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
         L.descs = g->desc.p;
         L.ndesc = 1;
         L.total_tasks = g->o.tasks;
-        L.total_big = g->o.nbig;
+        L.total_med = g->o.nmed;
+        L.total_large = g->o.nbig - g->o.nmed;
+        L.max_m = g->o.M;
         L.heads = g->heads.p;
         L.workers = opt && opt->workers > 0 ? opt->workers : g->workers;
         L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
-        L.big_blocks = tc::device_cu_count();
         L.per_node = want_tv;
         const bool timing = opt && opt->time_kernels;
         if (timing) {
@@ -313,7 +317,7 @@ tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt,
         int64_t *tot = (int64_t *)(scratch.p + head_words * 4);
         int64_t *tv = tot + kbase[ng];
         std::vector<tc::CountDesc> hd((size_t)ng);
-        int64_t task_base = 0, big_base = 0;
+        int64_t task_base = 0, med_base = 0, large_base = 0;
         int32_t workers = 0, lds_max = tc::max_lds_list();
         for (int32_t i = 0; i < ng; ++i) {
             const tc_graph *g = gs[i];
@@ -327,12 +331,16 @@ tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt,
             d.m = g->o.M;
             d.totals = tot + kbase[i];
             d.tv = want_tv ? tv + nbase[i] : nullptr;
+            d.nmed = g->o.nmed;
+            d.nbig = g->o.nbig;
             d.task_base = task_base;
-            d.big_base = big_base;
+            d.med_base = med_base;
+            d.large_base = large_base;
             d.k = g->pk.k;
             d.small_max = g->small_max;
             task_base += g->o.tasks;
-            big_base += g->o.nbig;
+            med_base += g->o.nmed;
+            large_base += g->o.nbig - g->o.nmed;
             workers = std::max(workers, g->workers);
             lds_max = std::min(lds_max, g->lds_max);
         }
@@ -342,11 +350,13 @@ tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt,
         L.descs = ddesc.p;
         L.ndesc = ng;
         L.total_tasks = task_base;
-        L.total_big = big_base;
+        L.total_med = med_base;
+        L.total_large = large_base;
+        L.max_m = 0;
+        for (int32_t i = 0; i < ng; ++i) L.max_m = std::max<int64_t>(L.max_m, gs[i]->o.M);
         L.heads = heads;
         L.workers = opt && opt->workers > 0 ? opt->workers : workers;
         L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : lds_max;
-        L.big_blocks = tc::device_cu_count();
         L.per_node = want_tv;
         tc::count_launch(L, s);
         for (int32_t i = 0; i < ng && per_node; ++i) {

@@ -305,8 +305,9 @@ __global__ void k_gather_deg(const int32_t *__restrict__ deg_old, const int32_t 
 // workgroups (their work is scheduled separately), flag them, and find the
 // longest list.
 __global__ void k_node_costs(const int64_t *__restrict__ off, const int32_t *__restrict__ deg_rank, int64_t N,
-                             int kind, int small_max,
-                             int64_t *__restrict__ f, uint32_t *__restrict__ wide, int32_t *__restrict__ max_dhat) {
+                             int kind, int small_max, int med_max, int64_t *__restrict__ f,
+                             uint32_t *__restrict__ wide_med, uint32_t *__restrict__ wide_large,
+                             int32_t *__restrict__ max_dhat) {
     int32_t local_max = 0;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t dh = off[r + 1] - off[r];
@@ -316,7 +317,8 @@ __global__ void k_node_costs(const int64_t *__restrict__ off, const int32_t *__r
         if (kind == TC_COST_DEGREE) c = deg_rank[r];
         const bool w = dh > small_max;
         f[r] = w ? 0 : c;
-        wide[r] = w ? 1u : 0u;
+        wide_med[r] = (w && dh <= med_max) ? 1u : 0u;
+        wide_large[r] = (w && dh > med_max) ? 1u : 0u;
     }
     local_max = wave_reduce_max(local_max);
     if (__lane_id() == 0) atomicMax(max_dhat, local_max);
@@ -607,31 +609,38 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
         }
         TC_LAUNCH_CHECK();
     }
-    DevBuf<uint32_t> wide(tmp, (size_t)std::max<int64_t>(N, 1));
+    DevBuf<uint32_t> wmed(tmp, (size_t)std::max<int64_t>(N, 1)), wlarge(tmp, (size_t)std::max<int64_t>(N, 1));
     DevBuf<int32_t> maxd(tmp, 1);
     fill_zero(maxd.p, 4, s);
     DevBuf<int64_t> F(tmp, (size_t)N + 1);
-    DevBuf<int64_t> widepos(tmp, (size_t)N + 1);
+    DevBuf<int64_t> pmed(tmp, (size_t)N + 1), plarge(tmp, (size_t)N + 1);
     if (N > 0) {
-        k_node_costs<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, out.deg.p, N, bp.cost_fn, bp.small_max, f.p,
-                                                          wide.p, maxd.p);
+        k_node_costs<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, out.deg.p, N, bp.cost_fn, bp.small_max,
+                                                          max_medium_list(), f.p, wmed.p, wlarge.p, maxd.p);
         TC_LAUNCH_CHECK();
     }
     exclusive_scan(f.p, F.p, N, true, tmp, s);
-    exclusive_scan(wide.p, widepos.p, N, true, tmp, s);
-    int64_t hv[2] = {0, 0};
+    exclusive_scan(wmed.p, pmed.p, N, true, tmp, s);
+    exclusive_scan(wlarge.p, plarge.p, N, true, tmp, s);
+    int64_t hv[3] = {0, 0, 0};
     int32_t hmax = 0;
     d2h(&hv[0], F.p + N, 1, s);
-    d2h(&hv[1], widepos.p + N, 1, s);
+    d2h(&hv[1], pmed.p + N, 1, s);
+    d2h(&hv[2], plarge.p + N, 1, s);
     d2h(&hmax, maxd.p, 1, s);
     TC_HIP(hipStreamSynchronize(s));
     out.total_cost = hv[0];
-    out.nbig = hv[1];
+    out.nmed = hv[1];
+    out.nbig = hv[1] + hv[2];
     out.max_dhat = hmax;
 
     out.big = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(out.nbig, 1));
-    if (out.nbig > 0) {
-        k_compact_index<<<grid_for(N, 4), kThreads, 0, s>>>(wide.p, widepos.p, N, out.big.p);
+    if (out.nmed > 0) {
+        k_compact_index<<<grid_for(N, 4), kThreads, 0, s>>>(wmed.p, pmed.p, N, out.big.p);
+        TC_LAUNCH_CHECK();
+    }
+    if (out.nbig > out.nmed) {
+        k_compact_index<<<grid_for(N, 4), kThreads, 0, s>>>(wlarge.p, plarge.p, N, out.big.p + out.nmed);
         TC_LAUNCH_CHECK();
     }
 

@@ -10,22 +10,29 @@
 //
 // Work layout on gfx950: L is inserted into an LDS hash table; the rows
 // N_{t_i} of all targets are laid end to end into one virtual sequence of
-// sum_i |N_{t_i}| ids, and a wave walks that sequence 64 ids per step: each
-// lane loads one id (consecutive lanes read consecutive addresses of a row)
-// and probes the hash table.  The row a lane falls in is found from the
-// segment starts inside the 64-wide window (one ballot), so short rows never
+// sum_i |N_{t_i}| ids, and a wave walks that sequence 256 ids per step: each
+// lane loads four ids (consecutive lanes read consecutive addresses of a row)
+// and probes the hash table.  The row a lane falls in is found from the row
+// starts inside the step (one ballot per 64-id window), so short rows never
 // leave lanes idle and long rows need no per-row loop.
 //
 //   - lists with 2 <= a <= small_max (at most 128): one wave per list, tasks
 //     of consecutive sources pulled by waves (k_count_small);
-//   - longer lists: one 1024-thread workgroup per list, its 16 waves splitting
-//     the virtual sequence (k_count_big); lists longer than lds_max are probed
-//     by binary search in device memory instead of the LDS table.
+//   - longer lists: one workgroup per list (k_count_wide): 4 waves for lists
+//     up to 1024 entries, 16 waves above; lists longer than the LDS table
+//     (lds_max) are probed by binary search in device memory instead.
 //
 // Per-node counts (Section II): a triangle {s, t_i, w} found at probe w adds
 // one to each of s, t_i and w.  Counts for entries of L are gathered in LDS
 // counters indexed by list position and flushed with one device atomic per
 // non-zero position.
+//
+// Row addressing: when the adjacency has fewer than 2^29 entries, row starts
+// are 32-bit and rows are read with buffer loads (hardware range check);
+// otherwise 64-bit offsets and global loads are used (IDX32 = false).
+#include <cstdlib>
+#include <type_traits>
+
 #include "internal.h"
 
 namespace tc {
@@ -37,24 +44,32 @@ constexpr int kSmallHashBits = 9;
 constexpr int kSmallHash = 1 << kSmallHashBits;  // load factor <= 1/4
 constexpr int kSmallWaves = 4;
 
+constexpr int kMedWaves = 4;
+constexpr int kMedMax = 1024;
+constexpr int kMedHashBits = 11;  // load factor <= 1/2
+
 constexpr int kLdsMax = 4096;
-constexpr int kBigHashBits = 13;
-constexpr int kBigHash = 1 << kBigHashBits;  // load factor <= 1/2
+constexpr int kBigHashBits = 13;  // load factor <= 1/2
 constexpr int kBigWaves = 16;
 constexpr int kBigThreads = kBigWaves * 64;
 
 constexpr int kWin = 4;           // 64-id windows walked per step
 constexpr int kStep = 64 * kWin;  // ids per step
+// flag bytes: position p of a step is byte (p % 64) * 4 + p / 64, so lane l
+// finds its four window flags in one 32-bit word; byte kStep is a sink.
+constexpr int kFlagBytes = kStep + 4;
 
+// multiplicative hash on the low 24 bits (full-rate 24-bit multiply)
 __device__ __forceinline__ uint32_t hash_slot(int32_t x, int bits) {
-    return ((uint32_t)x * 2654435769u) >> (32 - bits);
+    return (uint32_t)__umul24((uint32_t)x, 0x9E3779u) >> (32 - bits);
 }
 
-__device__ __forceinline__ int find_desc(const CountDesc *__restrict__ d, int nd, int64_t c, bool big) {
+// which = 0: tasks, 1: medium lists, 2: long lists
+__device__ __forceinline__ int find_desc(const CountDesc *__restrict__ d, int nd, int64_t c, int which) {
     int lo = 0, hi = nd - 1;  // largest h whose first index is <= c
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int64_t b = big ? d[mid].big_base : d[mid].task_base;
+        const int64_t b = which == 0 ? d[mid].task_base : (which == 1 ? d[mid].med_base : d[mid].large_base);
         if (b <= c)
             lo = mid;
         else
@@ -81,61 +96,95 @@ __device__ __forceinline__ void add_u64(int64_t *p, uint64_t v) {
     atomicAdd((unsigned long long *)p, (unsigned long long)v);
 }
 
-// --------------------------------------------------------------- one wave
+__device__ __forceinline__ int mbcnt64(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Reads col entries: buffer loads with a 32-bit byte offset when IDX32,
+// global loads otherwise.
+template <bool IDX32>
+struct ColReader;
+
+template <>
+struct ColReader<true> {
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ ColReader(const int32_t *col, int64_t m) {
+        rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)col, (short)0, (int)(m * 4), 0x00020000);
+    }
+    // offsets at or past the end read 0 (hardware range check); callers mask those lanes
+    __device__ __forceinline__ int32_t load(int32_t idx, bool ok) const {
+        const uint32_t byte_off = ok ? (uint32_t)idx << 2 : 0xffffffffu;
+        return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rsrc, byte_off, 0, 0);
+    }
+};
+
+template <>
+struct ColReader<false> {
+    gptr_t<const int32_t> col;
+    int64_t m;
+    __device__ __forceinline__ ColReader(const int32_t *c, int64_t mm) : col(gview(c)), m(mm) {}
+    __device__ __forceinline__ int32_t load(int64_t idx, bool ok) const {
+        ok = ok && (uint64_t)idx < (uint64_t)m;
+        return col[ok ? idx : 0];
+    }
+};
+
+template <bool IDX32>
+using idx_t = typename std::conditional<IDX32, int32_t, int64_t>::type;
 
 // Walks the virtual sequence of target-row ids from e_begin to e_end (a
 // multiple of kStep apart, e_end may pass total), kStep ids per step: marks
 // the row starts that fall inside the step, finds every lane's row with one
 // ballot per 64-id window, loads the 4 ids of each lane together, then probes
-// them together.  `cur` is the row holding e_begin.
+// them together.  `cur` is the row holding e_begin.  Row indices are clamped
+// so every LDS read is valid, lanes past the end are masked, and the
+// collision chains of the hash are entered only when some lane needs one.
 //   IN_LDS: membership in the source list by the LDS hash (key/pos);
 //   otherwise by binary search in the sorted list col[rs .. rs+a) (huge lists).
 // Per-node counts go to LDS counters by list position, or (huge lists) to tv.
-template <int HBITS, bool PER_NODE, bool IN_LDS, class PosT>
+template <int HBITS, bool PER_NODE, bool IN_LDS, bool IDX32, class PosT>
 __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *pos, const int32_t *P,
-                                               const int64_t *base, const PosT *tpos, int32_t *cnt, uint8_t *flag,
-                                               gptr_t<const int32_t> col, int64_t m, int32_t nt, int32_t total,
-                                               int cur, int32_t e_begin, int32_t e_end, int64_t rs, int32_t a,
-                                               int32_t i0, int64_t *__restrict__ tv) {
+                                               const idx_t<IDX32> *base, const PosT *tpos, int32_t *cnt,
+                                               uint8_t *flag, const ColReader<IDX32> &rd,
+                                               gptr_t<const int32_t> gcol, int32_t nt, int32_t total, int cur,
+                                               int32_t e_begin, int32_t e_end, int64_t rs, int32_t a, int32_t i0,
+                                               int64_t *__restrict__ tv) {
     constexpr uint32_t kMask = (1u << HBITS) - 1;
     const int lane = __lane_id();
-    const uint64_t upto = lanemask_lt() | (1ull << lane);
+    uint32_t *flag_word = reinterpret_cast<uint32_t *>(flag);
     uint32_t hits = 0;
     for (int32_t e0 = e_begin; e0 < e_end; e0 += kStep) {
-#pragma unroll
-        for (int q = 0; q < kWin; ++q) {
-            const int jj = cur + 1 + lane + 64 * q;
-            if (jj < nt) {
-                const int32_t p = P[jj] - e0;
-                if (p < kStep) flag[p] = 1;
-            }
+        // row starts inside (e0, e0 + kStep); rows past the last read the total
+        for (int jb = cur + 1;; jb += 64) {
+            const int jj = min(jb + lane, nt);
+            const int32_t p = P[jj] - e0;  // >= 1
+            if (p < kStep) flag[((p & 63) << 2) + (p >> 6)] = 1;
+            if (readlane32(p, 63) >= kStep || jb + 63 >= nt) break;
         }
         wave_lds_sync();
+        const uint32_t fw = flag_word[lane];
+        flag_word[lane] = 0u;
         uint64_t M[kWin];
         int pre[kWin];
         int acc = 0;
 #pragma unroll
         for (int q = 0; q < kWin; ++q) {
-            M[q] = __ballot(flag[64 * q + lane] != 0);
+            M[q] = __ballot(((fw >> (8 * q)) & 0xffu) != 0u);
             pre[q] = acc;
             acc += popc64(M[q]);
         }
-#pragma unroll
-        for (int q = 0; q < kWin; ++q) flag[64 * q + lane] = 0;
         int seg[kWin];
-        int64_t at[kWin];
         int32_t w[kWin];
+        bool ok[kWin];
 #pragma unroll
         for (int q = 0; q < kWin; ++q) {
-            seg[q] = cur + pre[q] + popc64(M[q] & upto);
+            seg[q] = min(cur + pre[q] + mbcnt64(M[q]) + (int)((fw >> (8 * q)) & 1u), nt - 1);
             const int32_t e = e0 + 64 * q + lane;
-            const int64_t x = e < total ? base[seg[q]] + e : -1;
-            at[q] = (uint64_t)x < (uint64_t)m ? x : -1;
+            ok[q] = e < total;
+            w[q] = rd.load(base[seg[q]] + e, ok[q]);
         }
 #pragma unroll
-        for (int q = 0; q < kWin; ++q) w[q] = col[at[q] < 0 ? 0 : at[q]];
-#pragma unroll
-        for (int q = 0; q < kWin; ++q) w[q] = at[q] < 0 ? -1 : w[q];
+        for (int q = 0; q < kWin; ++q) w[q] = ok[q] ? w[q] : -1;
         if (IN_LDS) {
             uint32_t sl[kWin];
             int32_t k[kWin];
@@ -144,16 +193,21 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
                 sl[q] = hash_slot(w[q], HBITS);
                 k[q] = key[sl[q]];
             }
+            bool chain = false;
 #pragma unroll
-            for (int q = 0; q < kWin; ++q) {
-                while (k[q] != w[q] && k[q] != -1) {  // collision chain (rare)
-                    sl[q] = (sl[q] + 1) & kMask;
-                    k[q] = key[sl[q]];
+            for (int q = 0; q < kWin; ++q) chain = chain || (k[q] != w[q] && k[q] != -1);
+            if (__ballot(chain)) {
+#pragma unroll
+                for (int q = 0; q < kWin; ++q) {
+                    while (k[q] != w[q] && k[q] != -1) {  // collision chain (rare)
+                        sl[q] = (sl[q] + 1) & kMask;
+                        k[q] = key[sl[q]];
+                    }
                 }
             }
 #pragma unroll
             for (int q = 0; q < kWin; ++q) {
-                const bool hit = w[q] >= 0 && k[q] == w[q];
+                const bool hit = ok[q] && k[q] == w[q];
                 hits += hit ? 1u : 0u;
                 if (PER_NODE && hit) {
                     atomicAdd(&cnt[pos[sl[q]]], 1);
@@ -163,20 +217,20 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
         } else {
 #pragma unroll
             for (int q = 0; q < kWin; ++q) {
-                if (w[q] < 0) continue;
+                if (!ok[q]) continue;
                 int32_t lo = 0, hi = a;
                 while (lo < hi) {
                     const int32_t mid = (lo + hi) >> 1;
-                    if (col[rs + mid] < w[q])
+                    if (gcol[rs + mid] < w[q])
                         lo = mid + 1;
                     else
                         hi = mid;
                 }
-                if (lo < a && col[rs + lo] == w[q]) {
+                if (lo < a && gcol[rs + lo] == w[q]) {
                     ++hits;
                     if (PER_NODE) {
                         add_u64(&tv[w[q]], 1);
-                        add_u64(&tv[col[rs + i0 + tpos[seg[q]]]], 1);
+                        add_u64(&tv[gcol[rs + i0 + tpos[seg[q]]]], 1);
                     }
                 }
             }
@@ -189,22 +243,26 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
     return hits;
 }
 
+// --------------------------------------------------------------- one wave
+
+template <bool IDX32>
 struct alignas(16) SmallLds {
-    int64_t base[kSmallMax];  // per target row: row start minus its prefix
-    int32_t key[kSmallHash];  // hashed source list, -1 = empty
-    int32_t P[kSmallMax + 1]; // exclusive prefix of row lengths, then the total
-    int32_t cnt[kSmallMax];   // per-position counts (per-node mode)
-    uint8_t pos[kSmallHash];  // list position of each hashed id
-    uint8_t tpos[kSmallMax];  // list position of each target row
-    uint8_t flag[kStep];      // row starts inside the current step
+    idx_t<IDX32> base[kSmallMax];  // per target row: row start minus its prefix
+    int32_t key[kSmallHash];       // hashed source list, -1 = empty
+    int32_t P[kSmallMax + 1];      // exclusive prefix of row lengths, then the total
+    int32_t cnt[kSmallMax];        // per-position counts (per-node mode)
+    uint8_t pos[kSmallHash];       // list position of each hashed id
+    uint8_t tpos[kSmallMax];       // list position of each target row
+    alignas(4) uint8_t flag[kFlagBytes];
 };
 
 // One source s whose list (a entries, 2 <= a <= 128) is already in registers:
-// x0 = L[lane], x1 = L[64 + lane].
-template <bool PER_NODE>
-__device__ __forceinline__ uint64_t source_small(SmallLds &S, gptr_t<const int32_t> col, gptr_t<const int64_t> off,
-                                                 int64_t *__restrict__ tv, int64_t m, int32_t s, int32_t a,
-                                                 int32_t x0, int32_t x1, int lane) {
+// x0 = L[lane], x1 = L[64 + lane] (clamped copies beyond a).
+template <bool PER_NODE, bool IDX32>
+__device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColReader<IDX32> &rd,
+                                                 gptr_t<const int32_t> gcol, gptr_t<const int64_t> off,
+                                                 int64_t *__restrict__ tv, int32_t s, int32_t a, int32_t x0,
+                                                 int32_t x1, int lane) {
     const bool h0 = lane < a, h1 = lane + 64 < a;
     if (h0) {
         uint32_t sl = hash_slot(x0, kSmallHashBits);
@@ -217,8 +275,7 @@ __device__ __forceinline__ uint64_t source_small(SmallLds &S, gptr_t<const int32
         if (PER_NODE) S.pos[sl] = (uint8_t)(64 + lane);
     }
     // rows of t_0 .. t_{a-2}; empty rows are dropped so row starts are distinct.
-    // Loads are unconditional (x0 / x1 hold valid labels in every lane) so all
-    // four are in flight together.
+    // Loads are unconditional (x0 / x1 hold valid labels in every lane).
     const int64_t r0 = off[x0], e0r = off[x0 + 1];
     const int64_t r1 = off[x1], e1r = off[x1 + 1];
     const int32_t b0 = lane < a - 1 ? (int32_t)(e0r - r0) : 0;
@@ -230,15 +287,15 @@ __device__ __forceinline__ uint64_t source_small(SmallLds &S, gptr_t<const int32
     const int32_t inc1 = tot0 + wave_inclusive_sum(b1);
     const int32_t total = readlane32(inc1, 63);
     if (b0 > 0) {
-        const int j = popc64(m0 & lanemask_lt());
+        const int j = mbcnt64(m0);
         S.P[j] = inc0 - b0;
-        S.base[j] = r0 - (int64_t)(inc0 - b0);
+        S.base[j] = (idx_t<IDX32>)(r0 - (int64_t)(inc0 - b0));
         S.tpos[j] = (uint8_t)lane;
     }
     if (b1 > 0) {
-        const int j = n0 + popc64(m1 & lanemask_lt());
+        const int j = n0 + mbcnt64(m1);
         S.P[j] = inc1 - b1;
-        S.base[j] = r1 - (int64_t)(inc1 - b1);
+        S.base[j] = (idx_t<IDX32>)(r1 - (int64_t)(inc1 - b1));
         S.tpos[j] = (uint8_t)(64 + lane);
     }
     const int nt = n0 + popc64(m1);
@@ -246,8 +303,8 @@ __device__ __forceinline__ uint64_t source_small(SmallLds &S, gptr_t<const int32
     wave_lds_sync();
 
     const int32_t e_end = ((total + kStep - 1) / kStep) * kStep;
-    const uint32_t hits = walk_steps<kSmallHashBits, PER_NODE, true, uint8_t>(
-        S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag, col, m, nt, total, 0, 0, e_end, 0, a, 0, tv);
+    const uint32_t hits = walk_steps<kSmallHashBits, PER_NODE, true, IDX32, uint8_t>(
+        S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag, rd, gcol, nt, total, 0, 0, e_end, 0, a, 0, tv);
     if (PER_NODE) {
         const uint64_t hs = wave_sum((uint64_t)hits);
         wave_lds_sync();
@@ -276,25 +333,24 @@ __device__ __forceinline__ uint64_t source_small(SmallLds &S, gptr_t<const int32
     return (uint64_t)hits;
 }
 
-template <bool PER_NODE>
-__global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_count_small(const CountDesc *__restrict__ descs, int ndesc,
-                                                                  int64_t total_tasks, uint32_t *__restrict__ head,
-                                                                  int nworkers) {
-    __shared__ SmallLds lds[kSmallWaves];
+template <bool PER_NODE, bool IDX32>
+__global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_count_small(
+    const CountDesc *__restrict__ descs, int ndesc, int64_t total_tasks, uint32_t *__restrict__ head, int nworkers) {
+    __shared__ SmallLds<IDX32> lds[kSmallWaves];
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    SmallLds &S = lds[wave];
+    SmallLds<IDX32> &S = lds[wave];
     for (int i = lane; i < kSmallHash; i += 64) S.key[i] = -1;
     for (int i = lane; i < kSmallMax; i += 64) S.cnt[i] = 0;
-    for (int i = lane; i < kStep; i += 64) S.flag[i] = 0;
+    for (int i = lane; i < kFlagBytes; i += 64) S.flag[i] = 0;
     wave_lds_sync();
 
     int64_t c = (int64_t)blockIdx.x * kSmallWaves + wave;
     while (c < total_tasks) {
-        const int h = ndesc > 1 ? find_desc(descs, ndesc, c, false) : 0;
+        const int h = ndesc > 1 ? find_desc(descs, ndesc, c, 0) : 0;
         const gptr_t<const int32_t> col = gview(descs[h].col);
         const gptr_t<const int64_t> off = gview(descs[h].off);
+        const ColReader<IDX32> rd(descs[h].col, descs[h].m);
         int64_t *__restrict__ tv = descs[h].tv;
-        const int64_t m = descs[h].m;
         const int64_t lt = c - descs[h].task_base;
         const int32_t v0 = descs[h].bnd[lt], v1 = descs[h].bnd[lt + 1];
         const int g = descs[h].gid ? descs[h].gid[lt] : 0;
@@ -324,7 +380,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
                 }
                 const int32_t nx0 = col[rn + min(lane, an - 1)];
                 const int32_t nx1 = col[rn + min(lane + 64, an - 1)];
-                tri += source_small<PER_NODE>(S, col, off, tv, m, s0 + j, a, x0, x1, lane);
+                tri += source_small<PER_NODE, IDX32>(S, rd, col, off, tv, s0 + j, a, x0, x1, lane);
                 j = jn;
                 a = an;
                 rs = rn;
@@ -342,35 +398,38 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
 
 // ---------------------------------------------------------- one workgroup
 
-struct BigLds {
-    int64_t base[kLdsMax];
-    int32_t key[kBigHash];
-    int32_t P[kLdsMax + 1];
-    int32_t cnt[kLdsMax];
-    int16_t pos[kBigHash];
-    int16_t tpos[kLdsMax];
-    uint8_t flag[kBigWaves][kStep];
-    int32_t wsum[kBigWaves];
-    int32_t wcnt[kBigWaves];
-    uint64_t whits[kBigWaves];
+// Long lists: one workgroup per list.  Two tiers share this code: lists up to
+// 1024 entries go to 4-wave workgroups with a ~31 KB LDS table (several per
+// compute unit), longer ones to 16-wave workgroups with a 127 KB table.
+// Lists are handed out longest-rank first (roughly longest first).
+template <int WAVES, int LMAX, int HBITS, bool IDX32>
+struct WideLds {
+    idx_t<IDX32> base[LMAX];
+    int32_t key[1 << HBITS];
+    int32_t P[LMAX + 1];
+    int32_t cnt[LMAX];
+    int16_t pos[1 << HBITS];
+    int16_t tpos[LMAX];
+    alignas(4) uint8_t flag[WAVES][kFlagBytes];
+    int32_t wsum[WAVES];
+    int32_t wcnt[WAVES];
+    uint64_t whits[WAVES];
     int64_t item;
 };
 
 // Lays out the rows of targets i in [i0, i1) (positions in the source list)
 // into P / base / tpos (tpos relative to i0).  Returns (rows, total ids).
-__device__ __forceinline__ void big_rows(BigLds &S, gptr_t<const int32_t> col, gptr_t<const int64_t> off,
-                                         int64_t rs, int32_t i0, int32_t i1, int32_t *nt_out, int32_t *total_out) {
+template <int WAVES, bool IDX32, class L>
+__device__ __forceinline__ void wide_rows(L &S, gptr_t<const int32_t> col, gptr_t<const int64_t> off, int64_t rs,
+                                          int32_t i0, int32_t i1, int32_t *nt_out, int32_t *total_out) {
+    constexpr int kThreadsW = WAVES * 64;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     int32_t carry_n = 0, carry_sum = 0;
-    for (int32_t rb = i0; rb < i1; rb += kBigThreads) {
+    for (int32_t rb = i0; rb < i1; rb += kThreadsW) {
         const int32_t i = rb + (int32_t)threadIdx.x;
-        int32_t b = 0;
-        int64_t r = 0;
-        if (i < i1) {
-            const int32_t t = col[rs + i];
-            r = off[t];
-            b = (int32_t)(off[t + 1] - r);
-        }
+        const int32_t t = col[rs + min(i, i1 - 1)];
+        const int64_t r = off[t], re = off[t + 1];
+        const int32_t b = i < i1 ? (int32_t)(re - r) : 0;
         const int32_t inc = wave_inclusive_sum(b);
         const uint64_t m = __ballot(b > 0);
         if (lane == 63) {
@@ -380,7 +439,7 @@ __device__ __forceinline__ void big_rows(BigLds &S, gptr_t<const int32_t> col, g
         __syncthreads();
         int32_t sb = 0, cb = 0, st = 0, ct = 0;
 #pragma unroll
-        for (int w = 0; w < kBigWaves; ++w) {
+        for (int w = 0; w < WAVES; ++w) {
             const int32_t ws = S.wsum[w], wc = S.wcnt[w];
             if (w < wave) {
                 sb += ws;
@@ -390,10 +449,10 @@ __device__ __forceinline__ void big_rows(BigLds &S, gptr_t<const int32_t> col, g
             ct += wc;
         }
         if (b > 0) {
-            const int j = carry_n + cb + popc64(m & lanemask_lt());
+            const int j = carry_n + cb + mbcnt64(m);
             const int32_t p = carry_sum + sb + inc - b;
             S.P[j] = p;
-            S.base[j] = r - (int64_t)p;
+            S.base[j] = (idx_t<IDX32>)(r - (int64_t)p);
             S.tpos[j] = (int16_t)(i - i0);
         }
         carry_n += ct;
@@ -407,13 +466,13 @@ __device__ __forceinline__ void big_rows(BigLds &S, gptr_t<const int32_t> col, g
 }
 
 // This wave's contiguous share of the virtual sequence, in whole steps.
-template <bool PER_NODE>
-__device__ __forceinline__ uint64_t big_windows(BigLds &S, gptr_t<const int32_t> col, int64_t *__restrict__ tv,
-                                                int64_t m, int64_t rs, int32_t a, int32_t i0, int32_t nt,
-                                                int32_t total, bool in_lds) {
+template <int WAVES, int HBITS, bool PER_NODE, bool IDX32, class L>
+__device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &rd, gptr_t<const int32_t> gcol,
+                                                 int64_t *__restrict__ tv, int64_t rs, int32_t a, int32_t i0,
+                                                 int32_t nt, int32_t total, bool in_lds) {
     const int wave = threadIdx.x >> 6;
     const int32_t nsteps = (total + kStep - 1) / kStep;
-    const int32_t per = (nsteps + kBigWaves - 1) / kBigWaves;
+    const int32_t per = (nsteps + WAVES - 1) / WAVES;
     const int32_t s0 = wave * per;
     const int32_t s1 = min(nsteps, s0 + per);
     if (s0 >= s1) return 0;
@@ -427,52 +486,59 @@ __device__ __forceinline__ uint64_t big_windows(BigLds &S, gptr_t<const int32_t>
             hi = mid - 1;
     }
     if (in_lds)
-        return walk_steps<kBigHashBits, PER_NODE, true, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
-                                                                 S.flag[wave], col, m, nt, total, lo, e_begin,
+        return walk_steps<HBITS, PER_NODE, true, IDX32, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
+                                                                 S.flag[wave], rd, gcol, nt, total, lo, e_begin,
                                                                  s1 * kStep, rs, a, i0, tv);
-    return walk_steps<kBigHashBits, PER_NODE, false, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
-                                                              S.flag[wave], col, m, nt, total, lo, e_begin,
+    return walk_steps<HBITS, PER_NODE, false, IDX32, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
+                                                              S.flag[wave], rd, gcol, nt, total, lo, e_begin,
                                                               s1 * kStep, rs, a, i0, tv);
 }
 
-template <bool PER_NODE>
-__global__ __launch_bounds__(kBigThreads) void k_count_big(const CountDesc *__restrict__ descs, int ndesc,
-                                                           int64_t total_big, uint32_t *__restrict__ head,
+// tier 1: lists in big[0, nmed); tier 2: lists in big[nmed, nbig)
+template <bool PER_NODE, bool IDX32, int WAVES, int LMAX, int HBITS, int TIER>
+__global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__restrict__ descs, int ndesc,
+                                                           int64_t total_items, uint32_t *__restrict__ head,
                                                            int lds_max) {
-    __shared__ BigLds S;
+    constexpr int kThreadsW = WAVES * 64;
+    constexpr int kHash = 1 << HBITS;
+    __shared__ WideLds<WAVES, LMAX, HBITS, IDX32> S;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < kBigHash; i += kBigThreads) S.key[i] = -1;
-    for (int i = threadIdx.x; i < kLdsMax; i += kBigThreads) S.cnt[i] = 0;
-    for (int i = threadIdx.x; i < kBigWaves * kStep; i += kBigThreads) (&S.flag[0][0])[i] = 0;
+    const int cap = min(lds_max, LMAX);
+    for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = -1;
+    for (int i = threadIdx.x; i < LMAX; i += kThreadsW) S.cnt[i] = 0;
+    for (int i = threadIdx.x; i < WAVES * kFlagBytes; i += kThreadsW) (&S.flag[0][0])[i] = 0;
     if (threadIdx.x == 0) S.item = blockIdx.x;
     __syncthreads();
 
     for (;;) {
         const int64_t item = S.item;
-        if (item >= total_big) break;
-        const int h = ndesc > 1 ? find_desc(descs, ndesc, item, true) : 0;
+        if (item >= total_items) break;
+        const int h = ndesc > 1 ? find_desc(descs, ndesc, item, TIER) : 0;
         const gptr_t<const int32_t> col = gview(descs[h].col);
         const gptr_t<const int64_t> off = gview(descs[h].off);
+        const ColReader<IDX32> rd(descs[h].col, descs[h].m);
         int64_t *__restrict__ tv = descs[h].tv;
-        const int64_t m = descs[h].m;
-        const int32_t s = descs[h].big[item - descs[h].big_base];
+        const int64_t first = TIER == 1 ? 0 : descs[h].nmed;
+        const int64_t count = TIER == 1 ? descs[h].nmed : descs[h].nbig - descs[h].nmed;
+        const int64_t local = item - (TIER == 1 ? descs[h].med_base : descs[h].large_base);
+        const int32_t s = descs[h].big[first + (count - 1 - local)];
         const int64_t rs = off[s];
         const int32_t a = (int32_t)(off[s + 1] - rs);
         uint64_t hits = 0;
-        if (a <= lds_max) {
-            for (int32_t k = threadIdx.x; k < a; k += kBigThreads) {
+        if (a <= cap) {
+            for (int32_t k = threadIdx.x; k < a; k += kThreadsW) {
                 const int32_t x = col[rs + k];
-                uint32_t sl = hash_slot(x, kBigHashBits);
-                while (atomicCAS(&S.key[sl], -1, x) != -1) sl = (sl + 1) & (kBigHash - 1);
-                S.pos[sl] = (int16_t)k;
+                uint32_t sl = hash_slot(x, HBITS);
+                while (atomicCAS(&S.key[sl], -1, x) != -1) sl = (sl + 1) & (kHash - 1);
+                if (PER_NODE) S.pos[sl] = (int16_t)k;
             }
             __syncthreads();
             int32_t nt, total;
-            big_rows(S, col, off, rs, 0, a - 1, &nt, &total);
-            hits = big_windows<PER_NODE>(S, col, tv, m, rs, a, 0, nt, total, true);
+            wide_rows<WAVES, IDX32>(S, col, off, rs, 0, a - 1, &nt, &total);
+            hits = wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, 0, nt, total, true);
             __syncthreads();
             if (PER_NODE) {
-                for (int32_t k = threadIdx.x; k < a; k += kBigThreads) {
+                for (int32_t k = threadIdx.x; k < a; k += kThreadsW) {
                     const int32_t c = S.cnt[k];
                     if (c) {
                         add_u64(&tv[col[rs + k]], (uint64_t)c);
@@ -480,23 +546,22 @@ __global__ __launch_bounds__(kBigThreads) void k_count_big(const CountDesc *__re
                     }
                 }
             }
-            for (int i = threadIdx.x; i < kBigHash; i += kBigThreads) S.key[i] = -1;
+            for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = -1;
         } else {
-            for (int32_t i0 = 0; i0 < a - 1; i0 += lds_max) {
-                const int32_t i1 = min(a - 1, i0 + lds_max);
+            for (int32_t i0 = 0; i0 < a - 1; i0 += cap) {
+                const int32_t i1 = min(a - 1, i0 + cap);
                 int32_t nt, total;
-                big_rows(S, col, off, rs, i0, i1, &nt, &total);
-                hits += big_windows<PER_NODE>(S, col, tv, m, rs, a, i0, nt, total, false);
+                wide_rows<WAVES, IDX32>(S, col, off, rs, i0, i1, &nt, &total);
+                hits += wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, i0, nt, total, false);
                 __syncthreads();
             }
         }
-        // block total of hits
         const uint64_t wh = wave_sum(hits);
         if (lane == 0) S.whits[wave] = wh;
         __syncthreads();
         if (threadIdx.x == 0) {
             uint64_t H = 0;
-            for (int w = 0; w < kBigWaves; ++w) H += S.whits[w];
+            for (int w = 0; w < WAVES; ++w) H += S.whits[w];
             if (H) {
                 const int g = graph_of(descs[h].node_base, descs[h].k, s);
                 add_u64(&descs[h].totals[g], H);
@@ -514,9 +579,43 @@ __global__ void k_scatter(const int64_t *__restrict__ tv, const int32_t *__restr
         out[perm[i]] = tv[i];
 }
 
+template <bool PER_NODE, bool IDX32>
+void launch_all(const CountLaunch &L, int lds_max, hipStream_t s) {
+    const int cus = device_cu_count();
+    if (L.total_tasks > 0) {
+        // never launch more workers than can be resident at once: a worker that
+        // starts late would hold its first task until the end
+        int per_cu = 0;
+        TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count_small<PER_NODE, IDX32>,
+                                                            kSmallWaves * 64, 0));
+        const int64_t resident = (int64_t)std::max(1, per_cu) * cus;
+        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(L.workers, kSmallWaves), resident));
+        k_count_small<PER_NODE, IDX32>
+            <<<blocks, kSmallWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_tasks, L.heads, blocks * kSmallWaves);
+        TC_LAUNCH_CHECK();
+    }
+    if (L.total_med > 0) {
+        int per_cu = 0;
+        TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, k_count_wide<PER_NODE, IDX32, kMedWaves, kMedMax, kMedHashBits, 1>, kMedWaves * 64, 0));
+        const int blocks = (int)std::min<int64_t>((int64_t)std::max(1, per_cu) * cus, L.total_med);
+        k_count_wide<PER_NODE, IDX32, kMedWaves, kMedMax, kMedHashBits, 1>
+            <<<blocks, kMedWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_med, L.heads + 1, lds_max);
+        TC_LAUNCH_CHECK();
+    }
+    if (L.total_large > 0) {
+        const int blocks = (int)std::min<int64_t>(cus, L.total_large);
+        k_count_wide<PER_NODE, IDX32, kBigWaves, kLdsMax, kBigHashBits, 2>
+            <<<blocks, kBigThreads, 0, s>>>(L.descs, L.ndesc, L.total_large, L.heads + 2, lds_max);
+        TC_LAUNCH_CHECK();
+    }
+}
+
 }  // namespace
 
 int max_small_list() { return kSmallMax; }
+int max_medium_list() { return kMedMax; }
+int max_lds_list() { return kLdsMax; }
 
 int small_kernel_waves_per_cu(bool per_node) {
     static int cached[2] = {0, 0};
@@ -524,14 +623,15 @@ int small_kernel_waves_per_cu(bool per_node) {
     if (!c) {
         int blocks = 0;
         if (per_node)
-            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<true>, kSmallWaves * 64, 0));
+            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<true, false>,
+                                                                kSmallWaves * 64, 0));
         else
-            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<false>, kSmallWaves * 64, 0));
+            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<false, false>,
+                                                                kSmallWaves * 64, 0));
         c = std::max(1, blocks) * kSmallWaves;
     }
     return c;
 }
-int max_lds_list() { return kLdsMax; }
 
 int device_cu_count() {
     static int cached[64] = {0};
@@ -547,26 +647,23 @@ int device_cu_count() {
 
 void count_launch(const CountLaunch &L, hipStream_t s) {
     const int lds_max = L.lds_max < 2 ? kLdsMax : (L.lds_max > kLdsMax ? kLdsMax : L.lds_max);
-    if (L.total_tasks > 0) {
-        // never launch more workers than can be resident at once: a worker that
-        // starts late would hold its first task until the end
-        const int resident = small_kernel_waves_per_cu(L.per_node) / kSmallWaves * device_cu_count();
-        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(L.workers, kSmallWaves), resident));
-        if (L.per_node)
-            k_count_small<true><<<blocks, kSmallWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_tasks, L.heads,
-                                                                    blocks * kSmallWaves);
+    // 32-bit row addressing needs every descriptor's adjacency below 2^29
+    // entries; TC_FORCE_INDEX64=1 selects the 64-bit path anyway (testing)
+    static const bool force64 = [] {
+        const char *e = std::getenv("TC_FORCE_INDEX64");
+        return e && e[0] == '1';
+    }();
+    const bool idx32 = !force64 && L.max_m < ((int64_t)1 << 29);
+    if (L.per_node) {
+        if (idx32)
+            launch_all<true, true>(L, lds_max, s);
         else
-            k_count_small<false><<<blocks, kSmallWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_tasks, L.heads,
-                                                                     blocks * kSmallWaves);
-        TC_LAUNCH_CHECK();
-    }
-    if (L.total_big > 0) {
-        const int blocks = (int)std::min<int64_t>(L.big_blocks, L.total_big);
-        if (L.per_node)
-            k_count_big<true><<<blocks, kBigThreads, 0, s>>>(L.descs, L.ndesc, L.total_big, L.heads + 1, lds_max);
+            launch_all<true, false>(L, lds_max, s);
+    } else {
+        if (idx32)
+            launch_all<false, true>(L, lds_max, s);
         else
-            k_count_big<false><<<blocks, kBigThreads, 0, s>>>(L.descs, L.ndesc, L.total_big, L.heads + 1, lds_max);
-        TC_LAUNCH_CHECK();
+            launch_all<false, false>(L, lds_max, s);
     }
 }
 

@@ -47,11 +47,12 @@ struct Oriented {
     DevBuf<int64_t> node_base;  // k+1 (device copy)
     DevBuf<int32_t> bnd;        // tasks+1
     DevBuf<int32_t> gid;        // tasks (k > 1 only)
-    DevBuf<int32_t> big;        // wide nodes, handled by whole workgroups
+    DevBuf<int32_t> big;        // long lists, handled by whole workgroups: medium ones first
     int64_t M = 0;
     int64_t tasks = 0;
     int64_t total_cost = 0;
     int64_t nbig = 0;
+    int64_t nmed = 0;  // lists in big[0, nmed) have at most max_medium_list() entries
     int32_t max_dhat = 0;
 };
 
@@ -74,12 +75,15 @@ struct CountDesc {
     const int32_t *bnd;
     const int32_t *gid;        // NULL when k == 1
     const int64_t *node_base;  // k+1
-    const int32_t *big;
+    const int32_t *big;  // long lists: [0, nmed) up to 1024 entries, [nmed, nbig) longer
     int64_t *totals;  // k
     int64_t *tv;      // N (degree-order labels) or NULL
     int64_t m;  // entries of col (bounds every row read)
+    int64_t nmed;
+    int64_t nbig;
     int64_t task_base;
-    int64_t big_base;
+    int64_t med_base;
+    int64_t large_base;
     int32_t k;
     int32_t small_max;  // lists up to this length were scheduled for single waves
 };
@@ -88,11 +92,12 @@ struct CountLaunch {
     const CountDesc *descs;  // device array
     int32_t ndesc;
     int64_t total_tasks;
-    int64_t total_big;
-    uint32_t *heads;  // 2 counters, zeroed before launch
+    int64_t total_med;
+    int64_t total_large;
+    uint32_t *heads;  // 3 counters, zeroed before launch
+    int64_t max_m;    // largest adjacency (entries of col) among the descriptors
     int32_t workers;  // persistent waves for the small-list kernel
-    int32_t lds_max;     // longest list kept in LDS by the workgroup kernel
-    int32_t big_blocks;  // persistent workgroups for long lists
+    int32_t lds_max;     // longest list kept in LDS by the workgroup kernels
     bool per_node;
 };
 
@@ -103,6 +108,7 @@ void scatter_per_node(const int64_t *tv, const int32_t *perm, int64_t n, int64_t
 
 int device_cu_count();
 int max_small_list();
+int max_medium_list();
 int small_kernel_waves_per_cu(bool per_node);  // resident waves per CU
 int max_lds_list();
 

@@ -197,13 +197,18 @@ def test_tuning_invariance(tc, kw):
     check(tc, g.n, g.src, g.dst, **kw)
 
 
-def test_long_lists_all_paths(tc):
-    # K_300: lists up to 299 entries -> workgroup kernel; with lds_list_max=64
-    # most of them take the device-memory binary-search path.
-    n, s, d = gs.complete(300)
+@pytest.mark.parametrize("n", [300, 1100, 4200])
+def test_long_lists_all_paths(tc, n):
+    # K_n: lists up to n-1 entries.  300 -> 4-wave workgroups; 1100 -> also the
+    # 16-wave workgroups; 4200 -> also lists longer than the LDS table (binary
+    # search in device memory).  Smaller lds_list_max forces the binary-search
+    # path in both workgroup kernels.
+    nn, s, d = gs.complete(n)
     for kw in (dict(), dict(lds_list_max=64), dict(small_max=8, lds_list_max=16)):
-        T, tv = gpu_count(tc, n, s, d, **kw)
-        assert T == math.comb(300, 3) and (tv == math.comb(299, 2)).all()
+        if n == 4200 and kw:
+            continue
+        T, tv = gpu_count(tc, nn, s, d, **kw)
+        assert T == math.comb(n, 3) and (tv == math.comb(n - 1, 2)).all()
 
 
 # ------------------------------------------------------------ metamorphic
