@@ -149,6 +149,35 @@ def bench_batch(args) -> int:
     return 0 if same else 1
 
 
+def profile_counts(args) -> int:
+    """Short, fixed sequence of launches for hardware-counter runs."""
+    import torch
+
+    import paper_1406_5687_amd as tc
+
+    x = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1)
+    torch.cuda.synchronize()
+    y.copy_(x)  # reads and writes exactly 1 GiB
+    torch.cuda.synchronize()
+    del x, y
+    g, name = make_workload(args.workload)
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    h = tc.build_oriented([(g.n, src, dst)])
+    out = torch.zeros(g.n, dtype=torch.int64, device="cuda")
+    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for _ in range(3):
+        h.count_per_node(out=out, totals=tot)
+    for _ in range(3):
+        h.count_total(out=tot)
+    torch.cuda.synchronize()
+    log(f"{name}: T={int(tot.item())}")
+    h.free()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +187,9 @@ def main() -> int:
     ap.add_argument("--batch-graphs", type=int, default=4096, help="graphs in the batch workload")
     ap.add_argument("--tune", action="store_true", help="autotune the batch schedule before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-counts", action="store_true",
+                    help="profiling target: a 1 GiB device copy (counter calibration), then one build of the "
+                         "workload and three per-node and three total-only counts; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -174,6 +206,8 @@ def main() -> int:
     tc.load()
     if args.workload == "batch":
         return bench_batch(args)
+    if args.profile_counts:
+        return profile_counts(args)
 
     t0 = time.time()
     g, wl_name = make_workload(args.workload)
