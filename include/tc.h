@@ -68,9 +68,12 @@ typedef struct {
     void *stream;               /* hipStream_t; NULL = null stream */
     int32_t inputs_on_device;   /* tc_edges.src/dst are device pointers */
     int32_t outputs_on_device;  /* count outputs are device pointers */
-    uint64_t hbm_budget_bytes;  /* 0: no budget (resident).  Otherwise every device
-                                   allocation of a build or count stays below it and
-                                   the graph is counted in node-range partitions. */
+    uint64_t hbm_budget_bytes;  /* 0: no budget.  Otherwise every device allocation a
+                                   build or count makes for the handle stays below it:
+                                   a graph whose resident form does not fit is built
+                                   and counted in node-range partitions (see below);
+                                   TC_ERR_OUT_OF_MEMORY when even one partition does
+                                   not fit.  Set at build time. */
     /* Device allocator; both NULL = hipMallocAsync / hipFreeAsync on the stream.
      * alloc returns NULL on failure. */
     void *(*alloc)(size_t bytes, void *stream, void *ctx);
@@ -86,7 +89,10 @@ typedef struct {
                              binary search in device memory; 0 = automatic (4096, the maximum) */
     int32_t time_kernels; /* 1: record device events around the counting kernels of each count
                              call; the elapsed time is reported by tc_graph_info */
-    int32_t reserved[7];
+    int32_t partitions;   /* build time: > 0 forces the partitioned form with at least this many
+                             node-range partitions (one graph per handle); 0 = only when the
+                             budget requires it */
+    int32_t reserved[6];
 } tc_options;
 
 /* Fills *opt with the defaults (all zero except cost_fn = TC_COST_PRIOR). */
@@ -149,7 +155,9 @@ typedef struct {
                                with time_kernels = 1 (waits for it); -1 when none */
     int32_t small_max;      /* longest list counted by one wave in the current task table */
     int32_t cost_fn;        /* cost function of the current task table */
-    int32_t reserved[2];
+    int64_t streamed_bytes; /* partitioned form: host-to-device bytes moved by the last count */
+    uint64_t peak_device_bytes; /* largest device footprint of the handle so far (build included) */
+    int32_t reserved[4];
 } tc_graph_info_t;
 
 tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info);

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtc.so")
 
-SOURCES = ["scan.hip", "sort.hip", "build.hip", "count.hip", "api.hip"]
+SOURCES = ["scan.hip", "sort.hip", "build.hip", "count.hip", "partition.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -10,6 +10,8 @@ struct tc_graph {
     tc::Allocator al;  // allocator of the handle's own memory (stream = last stream used)
     tc::Packing pk;
     tc::Oriented o;
+    std::unique_ptr<tc::Partitioned> part;  // set when counted in node-range partitions
+    int64_t min_chunk = 0;
     int32_t workers = 0;
     int32_t small_max = 128;
     int32_t lds_max = 4096;
@@ -81,7 +83,7 @@ void ensure_scratch(tc_graph *g, bool per_node, hipStream_t s) {
     if (!g->heads.p) g->heads = tc::DevBuf<uint32_t>(g->al, 4);  // 3 queue heads
     if (!g->totals.p) g->totals = tc::DevBuf<int64_t>(g->al, (size_t)std::max(g->pk.k, 1));
     if (per_node && !g->tv.p) g->tv = tc::DevBuf<int64_t>(g->al, (size_t)std::max<int64_t>(g->pk.N, 1));
-    if (!g->desc.p || (per_node && !g->desc_has_tv)) {
+    if (!g->part && (!g->desc.p || (per_node && !g->desc_has_tv))) {
         tc::CountDesc d{};
         d.off = g->o.off.p;
         d.col = g->o.col.p;
@@ -163,24 +165,47 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
         if (pk.N >= ((int64_t)1 << 31) - 1) throw tc::Error(TC_ERR_TOO_LARGE, "sum of n must stay below 2^31 - 1");
 
         g->al = make_allocator(&o);
-        g->al.budget = 0;  // resident build; budgets are handled by the partitioned path
         const int cus = tc::device_cu_count();
         g->workers = o.workers > 0 ? o.workers : tc::small_kernel_waves_per_cu(true) * cus;
         g->small_max = o.small_max > 0 ? std::min(o.small_max, tc::max_small_list()) : tc::max_small_list();
         g->lds_max = o.lds_list_max > 0 ? std::max(2, std::min(o.lds_list_max, tc::max_lds_list())) : tc::max_lds_list();
         g->cost_fn = o.cost_fn;
+        g->min_chunk = o.min_chunk;
+        tc::BuildParams bp;
+        bp.workers = g->workers;
+        bp.cost_fn = o.cost_fn;
+        bp.min_chunk = o.min_chunk;
+        bp.small_max = g->small_max;
+
+        // Resident unless forced or over the budget: the resident build holds
+        // the input (when copied in), its scratch, the adjacency and the count
+        // buffers at once.
+        const uint64_t budget = o.hbm_budget_bytes;
+        const bool copy_in = !(k == 1 && o.inputs_on_device);
+        const uint64_t resident_need = (uint64_t)pk.M_in * (31 + (copy_in ? 8 : 0)) + (uint64_t)pk.N * 108 +
+                                       (uint64_t)g->workers * 160 + ((uint64_t)32 << 20);
+        const bool part = pk.N > 0 && (o.partitions > 0 || (budget > 0 && resident_need > budget));
+        if (part) {
+            if (k != 1) {
+                if (o.partitions > 0)
+                    throw tc::Error(TC_ERR_INVALID_ARG, "the partitioned form holds one graph per handle");
+                throw tc::Error(TC_ERR_OUT_OF_MEMORY, "graphs do not fit the device budget together");
+            }
+            g->part.reset(new tc::Partitioned());
+            tc::build_partitioned(graphs[0].src, graphs[0].dst, o.inputs_on_device != 0, pk, bp, o.partitions, g->al,
+                                  s, *g->part);
+            return;
+        }
 
         // packed input edges on the device
-        tc::Allocator scratch = g->al;
-        scratch.live = 0;
         tc::DevBuf<int32_t> psrc, pdst;
         const int32_t *dsrc = nullptr, *ddst = nullptr;
         if (k == 1 && o.inputs_on_device) {
             dsrc = graphs[0].src;
             ddst = graphs[0].dst;
         } else if (pk.M_in > 0) {
-            psrc = tc::DevBuf<int32_t>(scratch, (size_t)pk.M_in);
-            pdst = tc::DevBuf<int32_t>(scratch, (size_t)pk.M_in);
+            psrc = tc::DevBuf<int32_t>(g->al, (size_t)pk.M_in);
+            pdst = tc::DevBuf<int32_t>(g->al, (size_t)pk.M_in);
             const hipMemcpyKind kind = o.inputs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
             for (int32_t i = 0; i < k; ++i) {
                 const size_t bytes = (size_t)graphs[i].m * sizeof(int32_t);
@@ -191,12 +216,23 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
             dsrc = psrc.p;
             ddst = pdst.p;
         }
-        tc::BuildParams bp;
-        bp.workers = g->workers;
-        bp.cost_fn = o.cost_fn;
-        bp.min_chunk = o.min_chunk;
-        bp.small_max = g->small_max;
-        tc::build_oriented_device(dsrc, ddst, pk, bp, g->al, s, g->o);
+        if (budget > 0 && k == 1) {
+            // the estimate above is an upper bound in practice; should the
+            // resident build still run out of budget, build partitioned
+            try {
+                tc::build_oriented_device(dsrc, ddst, pk, bp, g->al, s, g->o);
+            } catch (const tc::Error &e) {
+                if (e.code != TC_ERR_OUT_OF_MEMORY) throw;
+                g->o = tc::Oriented();
+                psrc.release();
+                pdst.release();
+                g->part.reset(new tc::Partitioned());
+                tc::build_partitioned(graphs[0].src, graphs[0].dst, o.inputs_on_device != 0, pk, bp, 0, g->al, s,
+                                      *g->part);
+            }
+        } else {
+            tc::build_oriented_device(dsrc, ddst, pk, bp, g->al, s, g->o);
+        }
     });
     if (st != TC_OK) return st;
     *out = g.release();
@@ -220,7 +256,9 @@ tc_status tc_graph_reschedule(tc_graph *g, const tc_options *opt) {
         bp.cost_fn = o.cost_fn;
         bp.min_chunk = o.min_chunk;
         bp.small_max = o.small_max > 0 ? std::min(o.small_max, tc::max_small_list()) : tc::max_small_list();
-        tc::reschedule_device(g->pk, bp, g->al, s, g->o);
+        // a partitioned handle builds its task tables at count time
+        if (!g->part) tc::reschedule_device(g->pk, bp, g->al, s, g->o);
+        g->min_chunk = bp.min_chunk;
         g->workers = bp.workers;
         g->small_max = bp.small_max;
         g->cost_fn = bp.cost_fn;
@@ -238,37 +276,54 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
         const bool want_tv = per_node != nullptr;
         ensure_scratch(g, want_tv, s);
         const size_t k = (size_t)g->pk.k;
-        tc::fill_zero(g->heads.p, 16, s);
-        tc::fill_zero(g->totals.p, k * sizeof(int64_t), s);
-        if (want_tv) tc::fill_zero(g->tv.p, (size_t)g->pk.N * sizeof(int64_t), s);
-        tc::CountLaunch L{};
-        L.descs = g->desc.p;
-        L.ndesc = 1;
-        L.total_tasks = g->o.tasks;
-        L.total_med = g->o.nmed;
-        L.total_large = g->o.nbig - g->o.nmed;
-        L.max_m = g->o.M;
-        L.heads = g->heads.p;
-        L.workers = opt && opt->workers > 0 ? opt->workers : g->workers;
-        L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
-        L.per_node = want_tv;
         const bool timing = opt && opt->time_kernels;
         if (timing) {
             for (hipEvent_t &e : g->ev)
                 if (!e) TC_HIP(hipEventCreate(&e));
-            TC_HIP(hipEventRecord(g->ev[0], s));
         }
-        tc::count_launch(L, s);
-        if (timing) {
-            TC_HIP(hipEventRecord(g->ev[1], s));
-            g->timed = true;
+        if (g->part) {
+            tc::BuildParams bp;
+            bp.workers = opt && opt->workers > 0 ? opt->workers : g->workers;
+            bp.cost_fn = g->cost_fn;
+            bp.min_chunk = g->min_chunk;
+            bp.small_max = g->small_max;
+            const int32_t lds = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
+            if (timing) TC_HIP(hipEventRecord(g->ev[0], s));
+            tc::count_partitioned(*g->part, bp, lds, g->al, s, g->totals.p, want_tv ? g->tv.p : nullptr,
+                                  g->heads.p);
+            if (timing) {
+                TC_HIP(hipEventRecord(g->ev[1], s));
+                g->timed = true;
+            }
+        } else {
+            tc::fill_zero(g->heads.p, 16, s);
+            tc::fill_zero(g->totals.p, k * sizeof(int64_t), s);
+            if (want_tv) tc::fill_zero(g->tv.p, (size_t)g->pk.N * sizeof(int64_t), s);
+            tc::CountLaunch L{};
+            L.descs = g->desc.p;
+            L.ndesc = 1;
+            L.total_tasks = g->o.tasks;
+            L.total_med = g->o.nmed;
+            L.total_large = g->o.nbig - g->o.nmed;
+            L.max_m = g->o.M;
+            L.heads = g->heads.p;
+            L.workers = opt && opt->workers > 0 ? opt->workers : g->workers;
+            L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
+            L.per_node = want_tv;
+            if (timing) TC_HIP(hipEventRecord(g->ev[0], s));
+            tc::count_launch(L, s);
+            if (timing) {
+                TC_HIP(hipEventRecord(g->ev[1], s));
+                g->timed = true;
+            }
         }
+        const int32_t *perm = g->part ? g->part->perm.p : g->o.perm.p;
         if (want_tv) {
             if (on_dev) {
-                tc::scatter_per_node(g->tv.p, g->o.perm.p, g->pk.N, per_node, s);
+                tc::scatter_per_node(g->tv.p, perm, g->pk.N, per_node, s);
             } else {
                 tc::DevBuf<int64_t> stage(g->al, (size_t)std::max<int64_t>(g->pk.N, 1));
-                tc::scatter_per_node(g->tv.p, g->o.perm.p, g->pk.N, stage.p, s);
+                tc::scatter_per_node(g->tv.p, perm, g->pk.N, stage.p, s);
                 copy_out(per_node, stage.p, (size_t)g->pk.N * sizeof(int64_t), false, s);
                 TC_HIP(hipStreamSynchronize(s));
             }
@@ -292,8 +347,10 @@ tc_status tc_count_per_node(tc_graph *g, const tc_options *opt, int64_t *per_nod
 tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, int64_t *totals,
                          int64_t *const *per_node) {
     if (!gs || ng < 1 || !totals) return fail(TC_ERR_INVALID_ARG, "graphs, ng >= 1 and totals are required");
-    for (int32_t i = 0; i < ng; ++i)
+    for (int32_t i = 0; i < ng; ++i) {
         if (!gs[i]) return fail(TC_ERR_INVALID_ARG, "NULL graph in batch");
+        if (gs[i]->part) return fail(TC_ERR_INVALID_ARG, "a partitioned handle cannot join a batch");
+    }
     return guarded([&] {
         check_options(opt);
         const bool on_dev = opt && opt->outputs_on_device;
@@ -382,14 +439,16 @@ tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info) {
     std::memset(info, 0, sizeof(*info));
     info->k = g->pk.k;
     info->n = g->pk.N;
-    info->m = g->o.M;
+    info->m = g->part ? g->part->M : g->o.M;
     info->m_input = g->pk.M_in;
-    info->max_out_degree = g->o.max_dhat;
+    info->max_out_degree = g->part ? g->part->max_dhat : g->o.max_dhat;
     info->tasks = g->o.tasks;
     info->total_cost = g->o.total_cost;
     info->wide_nodes = g->o.nbig;
     info->device_bytes = g->al.live;
-    info->partitions = 1;
+    info->peak_device_bytes = g->al.peak;
+    info->partitions = g->part ? g->part->P : 1;
+    info->streamed_bytes = g->part ? g->part->streamed_bytes : 0;
     info->workers = g->workers;
     info->small_max = g->small_max;
     info->cost_fn = g->cost_fn;
@@ -406,6 +465,14 @@ tc_status tc_export_csr(const tc_graph *g, const tc_options *opt, int64_t *off, 
     if (!g) return fail(TC_ERR_INVALID_ARG, "graph must be non-NULL");
     return guarded([&] {
         hipStream_t s = opt ? (hipStream_t)opt->stream : nullptr;
+        if (g->part) {
+            // the adjacency is in host memory already
+            if (off) std::memcpy(off, g->part->off.p, (size_t)(g->pk.N + 1) * 8);
+            if (col && g->part->M) std::memcpy(col, g->part->col.p, (size_t)g->part->M * 4);
+            if (perm && g->pk.N) copy_out(perm, g->part->perm.p, (size_t)g->pk.N * 4, false, s);
+            TC_HIP(hipStreamSynchronize(s));
+            return;
+        }
         if (off) copy_out(off, g->o.off.p, (size_t)(g->pk.N + 1) * 8, false, s);
         if (col && g->o.M) copy_out(col, g->o.col.p, (size_t)g->o.M * 4, false, s);
         if (perm && g->pk.N) copy_out(perm, g->o.perm.p, (size_t)g->pk.N * 4, false, s);
@@ -416,6 +483,7 @@ tc_status tc_export_csr(const tc_graph *g, const tc_options *opt, int64_t *off, 
 tc_status tc_export_schedule(const tc_graph *g, const tc_options *opt, int32_t *bnd, int32_t *gid, int64_t cap,
                              int64_t *tasks) {
     if (!g || !tasks) return fail(TC_ERR_INVALID_ARG, "graph and tasks must be non-NULL");
+    if (g->part) return fail(TC_ERR_INVALID_ARG, "a partitioned handle builds one task table per streamed batch");
     *tasks = g->o.tasks;
     if (!bnd) return TC_OK;
     if (cap < g->o.tasks + 1) return fail(TC_ERR_INVALID_ARG, "bnd capacity below tasks + 1");

@@ -520,16 +520,9 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
         TC_LAUNCH_CHECK();
         uint64_t *sorted = radix_sort_u64(ka.p, kb.p, M_in, 0, 2 * gb, tmp, s);
         uint64_t *other = sorted == ka.p ? kb.p : ka.p;
-        const int64_t nt = ceil_div(M_in, kSelTile);
-        DevBuf<int64_t> part(tmp, (size_t)nt + 1);
-        k_unique_count<<<(unsigned)nt, kThreads, 0, s>>>(sorted, M_in, part.p);
-        TC_LAUNCH_CHECK();
-        exclusive_scan(part.p, part.p, nt, true, tmp, s);
-        k_unique_write<<<(unsigned)nt, kThreads, 0, s>>>(sorted, M_in, part.p, other);
-        TC_LAUNCH_CHECK();
+        M = unique_sorted_keys(sorted, M_in, other, tmp, s);  // synchronises
         ukeys = other;
         uint32_t herr = 0;
-        d2h(&M, part.p + nt, 1, s);
         d2h(&herr, err.p, 1, s);
         TC_HIP(hipStreamSynchronize(s));
         if (herr & 1u) throw Error(TC_ERR_ID_RANGE, "an edge endpoint is outside 0..n-1 of its graph");
@@ -540,31 +533,12 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     // ---- 2. degrees
     DevBuf<int32_t> deg(tmp, (size_t)std::max<int64_t>(N, 1));
     fill_zero(deg.p, deg.bytes(), s);
-    if (M > 0) {
-        uint32_t *hi = reinterpret_cast<uint32_t *>(spare);  // spare holds >= 2 M words
-        uint32_t *hi_tmp = hi + M;
-        k_degrees_lo<<<grid_for(M, 4), kThreads, 0, s>>>(ukeys, M, gb, deg.p, hi);
-        TC_LAUNCH_CHECK();
-        uint32_t *hs = radix_sort_u32(hi, hi_tmp, M, 0, gb, tmp, s);
-        k_run_counts<<<grid_for(M, 4), kThreads, 0, s>>>(hs, M, deg.p);
-        TC_LAUNCH_CHECK();
-    }
+    add_degrees(ukeys, M, gb, deg.p, reinterpret_cast<uint32_t *>(spare), tmp, s);  // spare: >= 2 M words
 
     // ---- 3. degree order
     out.perm = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(N, 1));
     DevBuf<int32_t> rank(tmp, (size_t)std::max<int64_t>(N, 1));
-    const int vb = std::max(1, bits_for((uint64_t)std::max<int64_t>(pk.max_n - 1, 1)));
-    const int db = std::max(1, bits_for((uint64_t)std::max<int64_t>(pk.max_n - 1, 1)));
-    const int kb_bits = bits_for((uint64_t)(k - 1));
-    if (kb_bits + db + vb > 64) throw Error(TC_ERR_TOO_LARGE, "too many graphs of this size in one handle");
-    if (N > 0) {
-        DevBuf<uint64_t> ra(tmp, (size_t)N), rb(tmp, (size_t)N);
-        k_rank_keys<<<grid_for(N, 4), kThreads, 0, s>>>(deg.p, N, out.node_base.p, k, db, vb, ra.p);
-        TC_LAUNCH_CHECK();
-        uint64_t *sorted = radix_sort_u64(ra.p, rb.p, N, 0, kb_bits + db + vb, tmp, s);
-        k_rank_from_sorted<<<grid_for(N, 4), kThreads, 0, s>>>(sorted, N, out.node_base.p, db, vb, out.perm.p, rank.p);
-        TC_LAUNCH_CHECK();
-    }
+    degree_rank(deg.p, N, out.node_base.p, k, pk.max_n, out.perm.p, rank.p, tmp, s);
 
     // ---- 4. orientation, 5. CSR
     out.col = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(M, 1));
@@ -595,7 +569,6 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
 void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
                    Oriented &out, const uint64_t *okeys, int gb) {
     const int64_t N = pk.N, M = out.M;
-    const int k = pk.k;
     DevBuf<int64_t> f(tmp, (size_t)std::max<int64_t>(N, 1));
     fill_zero(f.p, f.bytes(), s);
     if (M > 0 && (bp.cost_fn == TC_COST_PRIOR || bp.cost_fn == TC_COST_NEW)) {
@@ -612,35 +585,49 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
     DevBuf<uint32_t> wmed(tmp, (size_t)std::max<int64_t>(N, 1)), wlarge(tmp, (size_t)std::max<int64_t>(N, 1));
     DevBuf<int32_t> maxd(tmp, 1);
     fill_zero(maxd.p, 4, s);
-    DevBuf<int64_t> F(tmp, (size_t)N + 1);
-    DevBuf<int64_t> pmed(tmp, (size_t)N + 1), plarge(tmp, (size_t)N + 1);
     if (N > 0) {
         k_node_costs<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, out.deg.p, N, bp.cost_fn, bp.small_max,
                                                           max_medium_list(), f.p, wmed.p, wlarge.p, maxd.p);
         TC_LAUNCH_CHECK();
     }
-    exclusive_scan(f.p, F.p, N, true, tmp, s);
-    exclusive_scan(wmed.p, pmed.p, N, true, tmp, s);
-    exclusive_scan(wlarge.p, plarge.p, N, true, tmp, s);
+    Schedule sc;
+    schedule_sources(f.p, wmed.p, wlarge.p, N, pk.k, out.node_base.p, bp, al, tmp, s, sc, maxd.p, &out.max_dhat);
+    out.bnd = std::move(sc.bnd);
+    out.gid = std::move(sc.gid);
+    out.big = std::move(sc.big);
+    out.tasks = sc.tasks;
+    out.total_cost = sc.total_cost;
+    out.nmed = sc.nmed;
+    out.nbig = sc.nbig;
+}
+
+void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wlarge, int64_t N, int k,
+                      const int64_t *node_base, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
+                      Schedule &out, const int32_t *maxd_dev, int32_t *maxd_host) {
+    DevBuf<int64_t> F(tmp, (size_t)N + 1);
+    DevBuf<int64_t> pmed(tmp, (size_t)N + 1), plarge(tmp, (size_t)N + 1);
+    exclusive_scan(f, F.p, N, true, tmp, s);
+    exclusive_scan(wmed, pmed.p, N, true, tmp, s);
+    exclusive_scan(wlarge, plarge.p, N, true, tmp, s);
     int64_t hv[3] = {0, 0, 0};
     int32_t hmax = 0;
     d2h(&hv[0], F.p + N, 1, s);
     d2h(&hv[1], pmed.p + N, 1, s);
     d2h(&hv[2], plarge.p + N, 1, s);
-    d2h(&hmax, maxd.p, 1, s);
+    if (maxd_dev) d2h(&hmax, maxd_dev, 1, s);
     TC_HIP(hipStreamSynchronize(s));
     out.total_cost = hv[0];
     out.nmed = hv[1];
     out.nbig = hv[1] + hv[2];
-    out.max_dhat = hmax;
+    if (maxd_host) *maxd_host = hmax;
 
     out.big = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(out.nbig, 1));
     if (out.nmed > 0) {
-        k_compact_index<<<grid_for(N, 4), kThreads, 0, s>>>(wmed.p, pmed.p, N, out.big.p);
+        k_compact_index<<<grid_for(N, 4), kThreads, 0, s>>>(wmed, pmed.p, N, out.big.p);
         TC_LAUNCH_CHECK();
     }
     if (out.nbig > out.nmed) {
-        k_compact_index<<<grid_for(N, 4), kThreads, 0, s>>>(wlarge.p, plarge.p, N, out.big.p + out.nmed);
+        k_compact_index<<<grid_for(N, 4), kThreads, 0, s>>>(wlarge, plarge.p, N, out.big.p + out.nmed);
         TC_LAUNCH_CHECK();
     }
 
@@ -651,25 +638,16 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
     }
     std::vector<int64_t> tg = task_targets(out.total_cost, bp.workers, min_chunk);
     const int64_t ntg = (int64_t)tg.size();
-    DevBuf<int64_t> dtg(tmp, (size_t)ntg);
-    void *pin = t_stage.get((size_t)ntg * sizeof(int64_t));
-    if (pin) {
-        std::memcpy(pin, tg.data(), ntg * sizeof(int64_t));
-        TC_HIP(hipMemcpyAsync(dtg.p, pin, ntg * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    } else {
-        TC_HIP(hipMemcpyAsync(dtg.p, tg.data(), ntg * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    }
     DevBuf<int32_t> bnd(al, (size_t)ntg + 1);
-    k_task_bounds<<<grid_for(ntg + 1), kThreads, 0, s>>>(F.p, N, dtg.p, ntg, bnd.p);
-    TC_LAUNCH_CHECK();
+    task_bounds(F.p, N, tg, bnd.p, tmp, s);
     if (k > 1) {
         const int64_t tot = ntg + 1 + (k - 1);
         out.bnd = DevBuf<int32_t>(al, (size_t)tot);
-        k_merge_bounds<<<grid_for(tot), kThreads, 0, s>>>(bnd.p, ntg + 1, out.node_base.p, k, out.bnd.p);
+        k_merge_bounds<<<grid_for(tot), kThreads, 0, s>>>(bnd.p, ntg + 1, node_base, k, out.bnd.p);
         TC_LAUNCH_CHECK();
         out.tasks = tot - 1;
         out.gid = DevBuf<int32_t>(al, (size_t)out.tasks);
-        k_task_graph<<<grid_for(out.tasks), kThreads, 0, s>>>(out.bnd.p, out.tasks, out.node_base.p, k, out.gid.p);
+        k_task_graph<<<grid_for(out.tasks), kThreads, 0, s>>>(out.bnd.p, out.tasks, node_base, k, out.gid.p);
         TC_LAUNCH_CHECK();
     } else {
         out.bnd = std::move(bnd);
@@ -679,6 +657,64 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
     TC_HIP(hipStreamSynchronize(s));
 }
 
+void task_bounds(const int64_t *F, int64_t N, const std::vector<int64_t> &targets, int32_t *bnd, Allocator &tmp,
+                 hipStream_t s) {
+    const int64_t ntg = (int64_t)targets.size();
+    DevBuf<int64_t> dtg(tmp, (size_t)std::max<int64_t>(ntg, 1));
+    void *pin = t_stage.get((size_t)ntg * sizeof(int64_t));
+    if (pin) {
+        std::memcpy(pin, targets.data(), ntg * sizeof(int64_t));
+        TC_HIP(hipMemcpyAsync(dtg.p, pin, ntg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        // the staging buffer is reused by the next call: wait for this copy
+        TC_HIP(hipStreamSynchronize(s));
+    } else {
+        TC_HIP(hipMemcpyAsync(dtg.p, targets.data(), ntg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    }
+    k_task_bounds<<<grid_for(ntg + 1), kThreads, 0, s>>>(F, N, dtg.p, ntg, bnd);
+    TC_LAUNCH_CHECK();
+}
+
+int64_t unique_sorted_keys(const uint64_t *sorted, int64_t n, uint64_t *out, Allocator &tmp, hipStream_t s) {
+    if (n <= 0) return 0;
+    const int64_t nt = ceil_div(n, kSelTile);
+    DevBuf<int64_t> part(tmp, (size_t)nt + 1);
+    k_unique_count<<<(unsigned)nt, kThreads, 0, s>>>(sorted, n, part.p);
+    TC_LAUNCH_CHECK();
+    exclusive_scan(part.p, part.p, nt, true, tmp, s);
+    k_unique_write<<<(unsigned)nt, kThreads, 0, s>>>(sorted, n, part.p, out);
+    TC_LAUNCH_CHECK();
+    int64_t M = 0;
+    d2h(&M, part.p + nt, 1, s);
+    TC_HIP(hipStreamSynchronize(s));
+    return M;
+}
+
+void add_degrees(const uint64_t *ukeys, int64_t M, int gb, int32_t *deg, uint32_t *spare, Allocator &tmp,
+                 hipStream_t s) {
+    if (M <= 0) return;
+    uint32_t *hi = spare;  // 2 M words
+    uint32_t *hi_tmp = hi + M;
+    k_degrees_lo<<<grid_for(M, 4), kThreads, 0, s>>>(ukeys, M, gb, deg, hi);
+    TC_LAUNCH_CHECK();
+    uint32_t *hs = radix_sort_u32(hi, hi_tmp, M, 0, gb, tmp, s);
+    k_run_counts<<<grid_for(M, 4), kThreads, 0, s>>>(hs, M, deg);
+    TC_LAUNCH_CHECK();
+}
+
+void degree_rank(const int32_t *deg, int64_t N, const int64_t *node_base, int k, int32_t max_n, int32_t *perm,
+                 int32_t *rank, Allocator &tmp, hipStream_t s) {
+    const int vb = std::max(1, bits_for((uint64_t)std::max<int64_t>(max_n - 1, 1)));
+    const int db = vb;  // a degree is below n
+    const int kb_bits = bits_for((uint64_t)(k - 1));
+    if (kb_bits + db + vb > 64) throw Error(TC_ERR_TOO_LARGE, "too many graphs of this size in one handle");
+    if (N <= 0) return;
+    DevBuf<uint64_t> ra(tmp, (size_t)N), rb(tmp, (size_t)N);
+    k_rank_keys<<<grid_for(N, 4), kThreads, 0, s>>>(deg, N, node_base, k, db, vb, ra.p);
+    TC_LAUNCH_CHECK();
+    uint64_t *sorted = radix_sort_u64(ra.p, rb.p, N, 0, kb_bits + db + vb, tmp, s);
+    k_rank_from_sorted<<<grid_for(N, 4), kThreads, 0, s>>>(sorted, N, node_base, db, vb, perm, rank);
+    TC_LAUNCH_CHECK();
+}
 
 void reschedule_device(const Packing &pk, const BuildParams &bp, Allocator &al, hipStream_t s, Oriented &out) {
     const size_t arena_bytes = (size_t)pk.N * 48 + (size_t)bp.workers * 128 + (8u << 20);

@@ -125,6 +125,58 @@ struct DevBuf {
     size_t bytes() const { return n * sizeof(T); }
 };
 
+// Page-locked host buffer (hipHostMalloc), readable by kernels through its
+// device address.
+template <class T>
+struct HostBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    HostBuf() = default;
+    explicit HostBuf(size_t count) { reset(count); }
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    HostBuf(HostBuf &&o) noexcept : p(o.p), n(o.n) {
+        o.p = nullptr;
+        o.n = 0;
+    }
+    HostBuf &operator=(HostBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            n = o.n;
+            o.p = nullptr;
+            o.n = 0;
+        }
+        return *this;
+    }
+    ~HostBuf() { release(); }
+    void reset(size_t count) {
+        release();
+        const size_t bytes = (count ? count : 1) * sizeof(T);
+        if (hipHostMalloc((void **)&p, bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            throw Error(TC_ERR_OUT_OF_MEMORY, "page-locked host allocation of " + std::to_string(bytes) +
+                                                  " bytes failed");
+        }
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    T *device_ptr() const {
+        void *d = nullptr;
+        if (hipHostGetDevicePointer(&d, (void *)p, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(TC_ERR_DEVICE, "host buffer has no device address");
+        }
+        return (T *)d;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
 // -------------------------------------------------------- device helpers
 
 #ifdef __HIPCC__

@@ -257,12 +257,14 @@ struct alignas(16) SmallLds {
 };
 
 // One source s whose list (a entries, 2 <= a <= 128) is already in registers:
-// x0 = L[lane], x1 = L[64 + lane] (clamped copies beyond a).
-template <bool PER_NODE, bool IDX32>
+// x0 = L[lane], x1 = L[64 + lane] (clamped copies beyond a).  The first te
+// entries are the targets (te = a - 1 for a resident adjacency); their rows
+// are off[t - row_lo] .. off[t - row_lo + 1].
+template <bool PER_NODE, bool IDX32, bool SLICE>
 __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColReader<IDX32> &rd,
                                                  gptr_t<const int32_t> gcol, gptr_t<const int64_t> off,
-                                                 int64_t *__restrict__ tv, int32_t s, int32_t a, int32_t x0,
-                                                 int32_t x1, int lane) {
+                                                 int64_t *__restrict__ tv, int32_t s, int32_t a, int32_t te,
+                                                 int32_t row_lo, int32_t x0, int32_t x1, int lane) {
     const bool h0 = lane < a, h1 = lane + 64 < a;
     if (h0) {
         uint32_t sl = hash_slot(x0, kSmallHashBits);
@@ -274,12 +276,14 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
         while (atomicCAS(&S.key[sl], -1, x1) != -1) sl = (sl + 1) & (kSmallHash - 1);
         if (PER_NODE) S.pos[sl] = (uint8_t)(64 + lane);
     }
-    // rows of t_0 .. t_{a-2}; empty rows are dropped so row starts are distinct.
-    // Loads are unconditional (x0 / x1 hold valid labels in every lane).
-    const int64_t r0 = off[x0], e0r = off[x0 + 1];
-    const int64_t r1 = off[x1], e1r = off[x1 + 1];
-    const int32_t b0 = lane < a - 1 ? (int32_t)(e0r - r0) : 0;
-    const int32_t b1 = lane + 64 < a - 1 ? (int32_t)(e1r - r1) : 0;
+    // rows of t_0 .. t_{te-1}; empty rows are dropped so row starts are distinct.
+    // Loads are unconditional (every lane indexes a valid row).
+    const int32_t y0 = SLICE ? (lane < te ? x0 - row_lo : 0) : x0;
+    const int32_t y1 = SLICE ? (lane + 64 < te ? x1 - row_lo : 0) : x1;
+    const int64_t r0 = off[y0], e0r = off[y0 + 1];
+    const int64_t r1 = off[y1], e1r = off[y1 + 1];
+    const int32_t b0 = lane < te ? (int32_t)(e0r - r0) : 0;
+    const int32_t b1 = lane + 64 < te ? (int32_t)(e1r - r1) : 0;
     const uint64_t m0 = __ballot(b0 > 0), m1 = __ballot(b1 > 0);
     const int n0 = popc64(m0);
     const int32_t inc0 = wave_inclusive_sum(b0);
@@ -333,7 +337,7 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     return (uint64_t)hits;
 }
 
-template <bool PER_NODE, bool IDX32>
+template <bool PER_NODE, bool IDX32, bool SLICE>
 __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_count_small(
     const CountDesc *__restrict__ descs, int ndesc, int64_t total_tasks, uint32_t *__restrict__ head, int nworkers) {
     __shared__ SmallLds<IDX32> lds[kSmallWaves];
@@ -347,10 +351,14 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
     int64_t c = (int64_t)blockIdx.x * kSmallWaves + wave;
     while (c < total_tasks) {
         const int h = ndesc > 1 ? find_desc(descs, ndesc, c, 0) : 0;
-        const gptr_t<const int32_t> col = gview(descs[h].col);
+        // source lists (soff / scol) and target rows (off / col) are the same
+        // adjacency unless this is a slice launch
+        const gptr_t<const int32_t> col = gview(SLICE ? descs[h].scol : descs[h].col);
+        const gptr_t<const int64_t> soff = gview(SLICE ? descs[h].soff : descs[h].off);
         const gptr_t<const int64_t> off = gview(descs[h].off);
         const ColReader<IDX32> rd(descs[h].col, descs[h].m);
         int64_t *__restrict__ tv = descs[h].tv;
+        const int32_t row_lo = SLICE ? descs[h].row_lo : 0;
         const int64_t lt = c - descs[h].task_base;
         const int32_t v0 = descs[h].bnd[lt], v1 = descs[h].bnd[lt + 1];
         const int g = descs[h].gid ? descs[h].gid[lt] : 0;
@@ -358,9 +366,12 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
         uint64_t tri = 0;
         for (int32_t s0 = v0; s0 < v1; s0 += 64) {
             const int32_t sv = min(s0 + lane, v1 - 1);
-            const int64_t o0 = off[sv], o1 = off[sv + 1];
+            const int64_t o0 = soff[sv], o1 = soff[sv + 1];
             const int32_t al = s0 + lane < v1 ? (int32_t)(o1 - o0) : 0;
-            uint64_t work = __ballot(al >= 2 && al <= small_max);
+            // targets per source: all entries but the last, or the resident prefix
+            const int32_t tl = SLICE ? min(descs[h].tcnt[sv], al - 1) : al - 1;
+            const int32_t lab = SLICE ? descs[h].sid[sv] : sv;
+            uint64_t work = __ballot(al >= 2 && al <= small_max && tl > 0);
             if (!work) continue;
             // the list of the next source is loaded while the current one is counted;
             // indices are clamped into the list so every lane loads a valid label
@@ -380,7 +391,9 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
                 }
                 const int32_t nx0 = col[rn + min(lane, an - 1)];
                 const int32_t nx1 = col[rn + min(lane + 64, an - 1)];
-                tri += source_small<PER_NODE, IDX32>(S, rd, col, off, tv, s0 + j, a, x0, x1, lane);
+                const int32_t te = readlane32(tl, j);
+                const int32_t sl = SLICE ? readlane32(lab, j) : s0 + j;
+                tri += source_small<PER_NODE, IDX32, SLICE>(S, rd, col, off, tv, sl, a, te, row_lo, x0, x1, lane);
                 j = jn;
                 a = an;
                 rs = rn;
@@ -417,17 +430,19 @@ struct WideLds {
     int64_t item;
 };
 
-// Lays out the rows of targets i in [i0, i1) (positions in the source list)
-// into P / base / tpos (tpos relative to i0).  Returns (rows, total ids).
+// Lays out the rows of targets i in [i0, i1) (positions in the source list
+// `col` from rs; target t has row t - row_lo of off) into P / base / tpos
+// (tpos relative to i0).  Returns (rows, total ids).
 template <int WAVES, bool IDX32, class L>
 __device__ __forceinline__ void wide_rows(L &S, gptr_t<const int32_t> col, gptr_t<const int64_t> off, int64_t rs,
-                                          int32_t i0, int32_t i1, int32_t *nt_out, int32_t *total_out) {
+                                          int32_t i0, int32_t i1, int32_t row_lo, int32_t *nt_out,
+                                          int32_t *total_out) {
     constexpr int kThreadsW = WAVES * 64;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     int32_t carry_n = 0, carry_sum = 0;
     for (int32_t rb = i0; rb < i1; rb += kThreadsW) {
         const int32_t i = rb + (int32_t)threadIdx.x;
-        const int32_t t = col[rs + min(i, i1 - 1)];
+        const int32_t t = col[rs + min(i, i1 - 1)] - row_lo;
         const int64_t r = off[t], re = off[t + 1];
         const int32_t b = i < i1 ? (int32_t)(re - r) : 0;
         const int32_t inc = wave_inclusive_sum(b);
@@ -495,7 +510,7 @@ __device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &r
 }
 
 // tier 1: lists in big[0, nmed); tier 2: lists in big[nmed, nbig)
-template <bool PER_NODE, bool IDX32, int WAVES, int LMAX, int HBITS, int TIER>
+template <bool PER_NODE, bool IDX32, int WAVES, int LMAX, int HBITS, int TIER, bool SLICE>
 __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__restrict__ descs, int ndesc,
                                                            int64_t total_items, uint32_t *__restrict__ head,
                                                            int lds_max) {
@@ -514,18 +529,25 @@ __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__re
         const int64_t item = S.item;
         if (item >= total_items) break;
         const int h = ndesc > 1 ? find_desc(descs, ndesc, item, TIER) : 0;
-        const gptr_t<const int32_t> col = gview(descs[h].col);
+        // source list in col (= scol of a slice launch), target rows in off / rd
+        const gptr_t<const int32_t> col = gview(SLICE ? descs[h].scol : descs[h].col);
+        const gptr_t<const int64_t> soff = gview(SLICE ? descs[h].soff : descs[h].off);
         const gptr_t<const int64_t> off = gview(descs[h].off);
         const ColReader<IDX32> rd(descs[h].col, descs[h].m);
         int64_t *__restrict__ tv = descs[h].tv;
+        const int32_t row_lo = SLICE ? descs[h].row_lo : 0;
         const int64_t first = TIER == 1 ? 0 : descs[h].nmed;
         const int64_t count = TIER == 1 ? descs[h].nmed : descs[h].nbig - descs[h].nmed;
         const int64_t local = item - (TIER == 1 ? descs[h].med_base : descs[h].large_base);
-        const int32_t s = descs[h].big[first + (count - 1 - local)];
-        const int64_t rs = off[s];
-        const int32_t a = (int32_t)(off[s + 1] - rs);
+        const int32_t si = descs[h].big[first + (count - 1 - local)];
+        const int64_t rs = soff[si];
+        const int32_t a = (int32_t)(soff[si + 1] - rs);
+        const int32_t te = SLICE ? min(descs[h].tcnt[si], a - 1) : a - 1;
+        const int32_t s = SLICE ? descs[h].sid[si] : si;
         uint64_t hits = 0;
-        if (a <= cap) {
+        if (te <= 0) {
+            // no resident target (slice launches only)
+        } else if (a <= cap) {
             for (int32_t k = threadIdx.x; k < a; k += kThreadsW) {
                 const int32_t x = col[rs + k];
                 uint32_t sl = hash_slot(x, HBITS);
@@ -534,7 +556,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__re
             }
             __syncthreads();
             int32_t nt, total;
-            wide_rows<WAVES, IDX32>(S, col, off, rs, 0, a - 1, &nt, &total);
+            wide_rows<WAVES, IDX32>(S, col, off, rs, 0, te, row_lo, &nt, &total);
             hits = wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, 0, nt, total, true);
             __syncthreads();
             if (PER_NODE) {
@@ -548,10 +570,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__re
             }
             for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = -1;
         } else {
-            for (int32_t i0 = 0; i0 < a - 1; i0 += cap) {
-                const int32_t i1 = min(a - 1, i0 + cap);
+            for (int32_t i0 = 0; i0 < te; i0 += cap) {
+                const int32_t i1 = min(te, i0 + cap);
                 int32_t nt, total;
-                wide_rows<WAVES, IDX32>(S, col, off, rs, i0, i1, &nt, &total);
+                wide_rows<WAVES, IDX32>(S, col, off, rs, i0, i1, row_lo, &nt, &total);
                 hits += wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, i0, nt, total, false);
                 __syncthreads();
             }
@@ -579,33 +601,33 @@ __global__ void k_scatter(const int64_t *__restrict__ tv, const int32_t *__restr
         out[perm[i]] = tv[i];
 }
 
-template <bool PER_NODE, bool IDX32>
+template <bool PER_NODE, bool IDX32, bool SLICE>
 void launch_all(const CountLaunch &L, int lds_max, hipStream_t s) {
     const int cus = device_cu_count();
     if (L.total_tasks > 0) {
         // never launch more workers than can be resident at once: a worker that
         // starts late would hold its first task until the end
         int per_cu = 0;
-        TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count_small<PER_NODE, IDX32>,
+        TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count_small<PER_NODE, IDX32, SLICE>,
                                                             kSmallWaves * 64, 0));
         const int64_t resident = (int64_t)std::max(1, per_cu) * cus;
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(L.workers, kSmallWaves), resident));
-        k_count_small<PER_NODE, IDX32>
+        k_count_small<PER_NODE, IDX32, SLICE>
             <<<blocks, kSmallWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_tasks, L.heads, blocks * kSmallWaves);
         TC_LAUNCH_CHECK();
     }
     if (L.total_med > 0) {
         int per_cu = 0;
         TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, k_count_wide<PER_NODE, IDX32, kMedWaves, kMedMax, kMedHashBits, 1>, kMedWaves * 64, 0));
+            &per_cu, k_count_wide<PER_NODE, IDX32, kMedWaves, kMedMax, kMedHashBits, 1, SLICE>, kMedWaves * 64, 0));
         const int blocks = (int)std::min<int64_t>((int64_t)std::max(1, per_cu) * cus, L.total_med);
-        k_count_wide<PER_NODE, IDX32, kMedWaves, kMedMax, kMedHashBits, 1>
+        k_count_wide<PER_NODE, IDX32, kMedWaves, kMedMax, kMedHashBits, 1, SLICE>
             <<<blocks, kMedWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_med, L.heads + 1, lds_max);
         TC_LAUNCH_CHECK();
     }
     if (L.total_large > 0) {
         const int blocks = (int)std::min<int64_t>(cus, L.total_large);
-        k_count_wide<PER_NODE, IDX32, kBigWaves, kLdsMax, kBigHashBits, 2>
+        k_count_wide<PER_NODE, IDX32, kBigWaves, kLdsMax, kBigHashBits, 2, SLICE>
             <<<blocks, kBigThreads, 0, s>>>(L.descs, L.ndesc, L.total_large, L.heads + 2, lds_max);
         TC_LAUNCH_CHECK();
     }
@@ -623,10 +645,10 @@ int small_kernel_waves_per_cu(bool per_node) {
     if (!c) {
         int blocks = 0;
         if (per_node)
-            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<true, false>,
+            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<true, false, false>,
                                                                 kSmallWaves * 64, 0));
         else
-            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<false, false>,
+            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<false, false, false>,
                                                                 kSmallWaves * 64, 0));
         c = std::max(1, blocks) * kSmallWaves;
     }
@@ -654,16 +676,23 @@ void count_launch(const CountLaunch &L, hipStream_t s) {
         return e && e[0] == '1';
     }();
     const bool idx32 = !force64 && L.max_m < ((int64_t)1 << 29);
-    if (L.per_node) {
-        if (idx32)
-            launch_all<true, true>(L, lds_max, s);
+    if (L.slice) {
+        // slices are sized below 2^29 entries
+        if (L.max_m >= ((int64_t)1 << 29)) throw Error(TC_ERR_TOO_LARGE, "slice of 2^29 or more entries");
+        if (L.per_node)
+            launch_all<true, true, true>(L, lds_max, s);
         else
-            launch_all<true, false>(L, lds_max, s);
+            launch_all<false, true, true>(L, lds_max, s);
+    } else if (L.per_node) {
+        if (idx32)
+            launch_all<true, true, false>(L, lds_max, s);
+        else
+            launch_all<true, false, false>(L, lds_max, s);
     } else {
         if (idx32)
-            launch_all<false, true>(L, lds_max, s);
+            launch_all<false, true, false>(L, lds_max, s);
         else
-            launch_all<false, false>(L, lds_max, s);
+            launch_all<false, false, false>(L, lds_max, s);
     }
 }
 

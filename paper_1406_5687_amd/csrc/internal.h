@@ -67,10 +67,76 @@ void reschedule_device(const Packing &pk, const BuildParams &bp, Allocator &al, 
 // Fill helpers usable inside captured streams (no memset nodes).
 void fill_zero(void *p, size_t bytes, hipStream_t s);
 
+// Task table of an arbitrary set of N sources: f[i] = cost of source i (0 for
+// lists handled by workgroups), wmed / wlarge flag the workgroup lists.
+struct Schedule {
+    DevBuf<int32_t> bnd;  // tasks+1
+    DevBuf<int32_t> gid;  // tasks (k > 1 only)
+    DevBuf<int32_t> big;  // medium lists first, then large ones
+    int64_t tasks = 0;
+    int64_t total_cost = 0;
+    int64_t nmed = 0;
+    int64_t nbig = 0;
+};
+void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wlarge, int64_t N, int k,
+                      const int64_t *node_base, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
+                      Schedule &out, const int32_t *maxd_dev = nullptr, int32_t *maxd_host = nullptr);
+std::vector<int64_t> task_targets(int64_t total, int32_t W, int64_t min_chunk);
+// bnd[0] = 0, bnd[j+1] = first x in [0, N] with F[x] >= targets[j] (targets < 0: N)
+void task_bounds(const int64_t *F, int64_t N, const std::vector<int64_t> &targets, int32_t *bnd, Allocator &tmp,
+                 hipStream_t s);
+// Build steps shared by the resident and the partitioned builds.
+int64_t unique_sorted_keys(const uint64_t *sorted, int64_t n, uint64_t *out, Allocator &tmp,
+                           hipStream_t s);  // synchronises; returns the count
+void add_degrees(const uint64_t *ukeys, int64_t M, int gb, int32_t *deg, uint32_t *spare /* 2 M words */,
+                 Allocator &tmp, hipStream_t s);
+void degree_rank(const int32_t *deg, int64_t N, const int64_t *node_base, int k, int32_t max_n, int32_t *perm,
+                 int32_t *rank, Allocator &tmp, hipStream_t s);
+
+// partition.hip ----------------------------------------------------------
+
+// A graph counted in P consecutive node ranges ("slices") of the degree order
+// (Definition 1), with its oriented adjacency in page-locked host memory.
+// For slice j = [cut[j], cut[j+1]), the streamed ranges are records
+// rbase[j] .. rbase[j+1]: node rv, entries hcol[rpos .. rpos + rlen) (the part
+// of N_rv from its first entry at or after cut[j]), whose first rtc entries
+// lie inside the slice.
+struct Partitioned {
+    int64_t N = 0;
+    int64_t M = 0;
+    int32_t P = 0;
+    int32_t max_dhat = 0;
+    std::vector<int64_t> cut;   // P+1
+    std::vector<int64_t> ecut;  // P+1: off[cut[j]]
+    HostBuf<int64_t> off;       // N+1
+    HostBuf<int32_t> col;       // M
+    HostBuf<int32_t> rv, rtc, rlen;
+    HostBuf<int64_t> rpos;
+    std::vector<int64_t> rbase;  // P+1
+    std::vector<int64_t> batch;  // record batches: [batch[b], batch[b+1]) never spans two slices
+    DevBuf<int32_t> perm;        // N, device: caller label of each position
+    int64_t rows_max = 0;        // largest slice (rows, entries)
+    int64_t entries_max = 0;
+    int64_t msg_cap = 0;  // largest streamed ids / records of one batch
+    int64_t rec_cap = 0;
+    int64_t streamed_bytes = 0;  // host-to-device bytes of the last count
+};
+
+// Builds the partitioned form of one graph.  src/dst: host arrays, or device
+// arrays when on_device.  Every device allocation goes through `al`, whose
+// budget (if any) bounds the peak.  partitions: at least this many slices.
+void build_partitioned(const int32_t *src, const int32_t *dst, bool on_device, const Packing &pk,
+                       const BuildParams &bp, int32_t partitions, Allocator &al, hipStream_t s, Partitioned &out);
+
+// Counts a partitioned graph slice by slice; totals (1 entry) and tv (N
+// entries, degree-order labels, may be NULL) are device arrays, zeroed here.
+void count_partitioned(Partitioned &pg, const BuildParams &bp, int32_t lds_max, Allocator &al, hipStream_t s,
+                       int64_t *totals, int64_t *tv, uint32_t *heads);
+
 // count.hip --------------------------------------------------------------
 
 struct CountDesc {
-    const int64_t *off;
+    const int64_t *off;  // target rows: row of label t is off[t - row_lo] .. off[t - row_lo + 1] in col
     const int32_t *col;
     const int32_t *bnd;
     const int32_t *gid;        // NULL when k == 1
@@ -86,6 +152,14 @@ struct CountDesc {
     int64_t large_base;
     int32_t k;
     int32_t small_max;  // lists up to this length were scheduled for single waves
+    // Slice launches only (CountLaunch::slice): source i hashes the list
+    // scol[soff[i] .. soff[i+1]), is labelled sid[i], and its first
+    // min(tcnt[i], a - 1) entries are the targets whose rows are resident.
+    const int64_t *soff;
+    const int32_t *scol;
+    const int32_t *sid;
+    const int32_t *tcnt;
+    int32_t row_lo;
 };
 
 struct CountLaunch {
@@ -99,6 +173,7 @@ struct CountLaunch {
     int32_t workers;  // persistent waves for the small-list kernel
     int32_t lds_max;     // longest list kept in LDS by the workgroup kernels
     bool per_node;
+    bool slice;  // descriptors are slice launches (32-bit row addressing)
 };
 
 void count_launch(const CountLaunch &L, hipStream_t s);

@@ -63,7 +63,8 @@ class Options(ctypes.Structure):
         ("small_max", ctypes.c_int32),
         ("lds_list_max", ctypes.c_int32),
         ("time_kernels", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 7),
+        ("partitions", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -87,7 +88,9 @@ class GraphInfo(ctypes.Structure):
         ("last_count_ms", ctypes.c_double),
         ("small_max", ctypes.c_int32),
         ("cost_fn", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("streamed_bytes", ctypes.c_int64),
+        ("peak_device_bytes", ctypes.c_uint64),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -177,7 +180,7 @@ def _is_tensor(x) -> bool:
 
 def make_options(*, stream=None, inputs_on_device=False, outputs_on_device=False, hbm_budget_bytes=0, workers=0,
                  cost_fn=COST_PRIOR, min_chunk=0, small_max=0, lds_list_max=0, time_kernels=False,
-                 torch_allocator=True) -> Options:
+                 partitions=0, torch_allocator=True) -> Options:
     global _torch_alloc
     o = Options()
     load().tc_options_default(ctypes.byref(o))
@@ -190,6 +193,7 @@ def make_options(*, stream=None, inputs_on_device=False, outputs_on_device=False
     o.small_max = int(small_max)
     o.lds_list_max = int(lds_list_max)
     o.time_kernels = int(bool(time_kernels))
+    o.partitions = int(partitions)
     if stream is None:
         try:
             torch = _torch()
@@ -333,7 +337,7 @@ class Graph:
 
 
 def build_oriented(graphs: Sequence, *, stream=None, hbm_budget_bytes=0, workers=0, cost_fn=COST_PRIOR, min_chunk=0,
-                   small_max=0, lds_list_max=0, torch_allocator=True) -> Graph:
+                   small_max=0, lds_list_max=0, partitions=0, torch_allocator=True) -> Graph:
     """Builds one handle from graphs given as (n, src, dst) triples.  src/dst are
     numpy arrays (host) or torch tensors (all on the device, or all host)."""
     if not len(graphs):
@@ -351,7 +355,8 @@ def build_oriented(graphs: Sequence, *, stream=None, hbm_budget_bytes=0, workers
         arr[i].dst = dp
         ns.append(int(n))
     kw = dict(stream=stream, hbm_budget_bytes=hbm_budget_bytes, workers=workers, cost_fn=cost_fn,
-              min_chunk=min_chunk, small_max=small_max, lds_list_max=lds_list_max, torch_allocator=torch_allocator)
+              min_chunk=min_chunk, small_max=small_max, lds_list_max=lds_list_max, partitions=partitions,
+              torch_allocator=torch_allocator)
     o = make_options(inputs_on_device=on_dev, **kw)
     h = ctypes.c_void_p(0)
     _raise(load().tc_build_oriented(arr, len(graphs), ctypes.byref(o), ctypes.byref(h)))
