@@ -106,8 +106,11 @@ typedef struct tc_graph tc_graph;
 /* Builds the oriented, sorted adjacency of Fig. 1 for k graphs (k >= 1) in one
  * pass on the device: canonical edge set, degrees, degree order (Section
  * III-A), orientation and row sort, the per-node cost f (Section V-A), and the
- * task table of Eq. (1)/(2).  graphs[i] may have n = 0 or m = 0.  With a
- * budget, the oriented adjacency is kept in pinned host memory and streamed.
+ * task table of Eq. (1)/(2).  graphs[i] may have n = 0 or m = 0.  Device
+ * inputs laid out back to back (graph i's arrays at graphs[0].src/dst plus the
+ * sum of the earlier m) are read in place; others are first copied into that
+ * layout.  With a budget, or partitions > 0, a single graph may be built in the
+ * partitioned form, its oriented adjacency kept in pinned host memory.
  * Errors: TC_ERR_INVALID_ARG (NULL graphs/out, k < 1, negative n or m, NULL
  * src/dst with m > 0), TC_ERR_ID_RANGE, TC_ERR_TOO_LARGE (sum of n >= 2^31),
  * TC_ERR_OUT_OF_MEMORY, TC_ERR_DEVICE.  *out is written only on TC_OK. */

@@ -181,7 +181,7 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
         // the input (when copied in), its scratch, the adjacency and the count
         // buffers at once.
         const uint64_t budget = o.hbm_budget_bytes;
-        const bool copy_in = !(k == 1 && o.inputs_on_device);
+        const bool copy_in = !o.inputs_on_device;
         const uint64_t resident_need = (uint64_t)pk.M_in * (31 + (copy_in ? 8 : 0)) + (uint64_t)pk.N * 108 +
                                        (uint64_t)g->workers * 160 + ((uint64_t)32 << 20);
         const bool part = pk.N > 0 && (o.partitions > 0 || (budget > 0 && resident_need > budget));
@@ -200,7 +200,14 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
         // packed input edges on the device
         tc::DevBuf<int32_t> psrc, pdst;
         const int32_t *dsrc = nullptr, *ddst = nullptr;
-        if (k == 1 && o.inputs_on_device) {
+        // device inputs already laid out graph after graph (edge e of graph i
+        // at src[edge_base[i] + e]) are read in place
+        bool in_place = o.inputs_on_device != 0;
+        for (int32_t i = 0; i < k && in_place && k > 1; ++i)
+            if (graphs[i].m > 0)
+                in_place = (uintptr_t)graphs[i].src == (uintptr_t)graphs[0].src + 4 * (uintptr_t)pk.edge_base[i] &&
+                           (uintptr_t)graphs[i].dst == (uintptr_t)graphs[0].dst + 4 * (uintptr_t)pk.edge_base[i];
+        if (in_place) {
             dsrc = graphs[0].src;
             ddst = graphs[0].dst;
         } else if (pk.M_in > 0) {

@@ -8,6 +8,7 @@ missing it raises; there is no fallback computation.
 from __future__ import annotations
 
 import ctypes
+import threading
 import os
 from typing import Optional, Sequence
 
@@ -172,6 +173,7 @@ class _TorchAllocator:
 
 
 _torch_alloc = None
+_torch_alloc_lock = threading.Lock()
 
 
 def _is_tensor(x) -> bool:
@@ -207,7 +209,9 @@ def make_options(*, stream=None, inputs_on_device=False, outputs_on_device=False
             torch = _torch()
             if torch.cuda.is_available():
                 if _torch_alloc is None:
-                    _torch_alloc = _TorchAllocator()
+                    with _torch_alloc_lock:
+                        if _torch_alloc is None:
+                            _torch_alloc = _TorchAllocator()
                 o.alloc = _torch_alloc.alloc
                 o.free = _torch_alloc.free
         except ImportError:
@@ -362,6 +366,37 @@ def build_oriented(graphs: Sequence, *, stream=None, hbm_budget_bytes=0, workers
     _raise(load().tc_build_oriented(arr, len(graphs), ctypes.byref(o), ctypes.byref(h)))
     del keep
     return Graph(h.value, ns, kw)
+
+
+_EDGES_DTYPE = np.dtype({"names": ["n", "m", "src", "dst"], "formats": ["<i4", "<i8", "<u8", "<u8"],
+                         "offsets": [0, 8, 16, 24], "itemsize": 32})
+
+
+def build_packed_device(ns, ms, src_ptr: int, dst_ptr: int, *, stream=None, workers=0, cost_fn=COST_PRIOR,
+                        min_chunk=0, small_max=0, lds_list_max=0, torch_allocator=True) -> Graph:
+    """Builds one handle from k graphs whose edges already lie back to back in
+    two device arrays (graph i's edges start at the sum of the earlier m), read
+    in place.  ns / ms: node and edge counts per graph; src_ptr / dst_ptr:
+    device addresses of the int32 arrays."""
+    ns = np.asarray(ns, np.int64)
+    ms = np.asarray(ms, np.int64)
+    k = ns.shape[0]
+    if k < 1 or ms.shape[0] != k:
+        raise ValueError("ns and ms must have the same, non-zero length")
+    eb = np.zeros(k, np.int64)
+    np.cumsum(ms[:-1], out=eb[1:])
+    arr = np.zeros(k, _EDGES_DTYPE)
+    arr["n"] = ns
+    arr["m"] = ms
+    arr["src"] = np.uint64(src_ptr) + (eb * 4).astype(np.uint64)
+    arr["dst"] = np.uint64(dst_ptr) + (eb * 4).astype(np.uint64)
+    kw = dict(stream=stream, workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max,
+              lds_list_max=lds_list_max, torch_allocator=torch_allocator)
+    o = make_options(inputs_on_device=True, **kw)
+    h = ctypes.c_void_p(0)
+    _raise(load().tc_build_oriented(ctypes.cast(arr.ctypes.data, ctypes.POINTER(Edges)), k, ctypes.byref(o),
+                                    ctypes.byref(h)))
+    return Graph(h.value, ns.tolist(), kw)
 
 
 def count_batch(graphs: Sequence[Graph], per_node: bool = False, **over):
