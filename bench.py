@@ -311,6 +311,22 @@ def profile_counts(args) -> int:
     y.copy_(x)  # reads and writes exactly 1 GiB
     torch.cuda.synchronize()
     del x, y
+    if args.workload == "batch":
+        import graphgen
+
+        import concurrent.futures as cf
+
+        with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            graphs = list(ex.map(lambda sp: sp.make(), graphgen.batch_specs(args.batch_graphs, seed=1)))
+        log(f"generated {len(graphs)} graphs")
+        h = tc.build_oriented([(g.n, g.src, g.dst) for g in graphs])
+        tot = torch.zeros(len(graphs), dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            h.count_total(out=tot)
+        torch.cuda.synchronize()
+        log(f"batch of {len(graphs)}: T sum={int(tot.sum().item())}")
+        h.free()
+        return 0
     g, name = make_workload(args.workload)
     src = torch.from_numpy(g.src).cuda()
     dst = torch.from_numpy(g.dst).cuda()
@@ -360,12 +376,12 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     tc.load()
+    if args.profile_counts:
+        return profile_counts(args)
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
-    if args.profile_counts:
-        return profile_counts(args)
     if args.budget_gb:
         return bench_partitioned(args)
 

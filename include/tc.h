@@ -92,7 +92,11 @@ typedef struct {
     int32_t partitions;   /* build time: > 0 forces the partitioned form with at least this many
                              node-range partitions (one graph per handle); 0 = only when the
                              budget requires it */
-    int32_t reserved[6];
+    int32_t rounds;       /* schedule: the first half of the cost is cut into workers * rounds
+                             tasks (Eq. (1) with W = workers * rounds), so the tasks in flight
+                             cover 1 / (2 rounds) of the nodes at a time; 0 = automatic (1 for
+                             one graph, more for large packed batches) */
+    int32_t reserved[5];
 } tc_options;
 
 /* Fills *opt with the defaults (all zero except cost_fn = TC_COST_PRIOR). */
@@ -160,7 +164,8 @@ typedef struct {
     int32_t cost_fn;        /* cost function of the current task table */
     int64_t streamed_bytes; /* partitioned form: host-to-device bytes moved by the last count */
     uint64_t peak_device_bytes; /* largest device footprint of the handle so far (build included) */
-    int32_t reserved[4];
+    int32_t rounds;         /* rounds of the current task table (see tc_options.rounds) */
+    int32_t reserved[3];
 } tc_graph_info_t;
 
 tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info);

@@ -12,6 +12,8 @@ struct tc_graph {
     tc::Oriented o;
     std::unique_ptr<tc::Partitioned> part;  // set when counted in node-range partitions
     int64_t min_chunk = 0;
+    int64_t max_graph_m = 0;  // entries of the largest graph's rows (bounds graph-relative row addressing)
+    int32_t rounds = 0;       // as asked (0 = automatic)
     int32_t workers = 0;
     int32_t small_max = 128;
     int32_t lds_max = 4096;
@@ -71,7 +73,8 @@ void check_options(const tc_options *opt) {
     if (!opt) return;
     if ((opt->alloc == nullptr) != (opt->free == nullptr))
         throw tc::Error(TC_ERR_INVALID_ARG, "alloc and free callbacks must be given together");
-    if (opt->workers < 0 || opt->min_chunk < 0 || opt->small_max < 0 || opt->lds_list_max < 0)
+    if (opt->workers < 0 || opt->min_chunk < 0 || opt->small_max < 0 || opt->lds_list_max < 0 || opt->rounds < 0 ||
+        opt->partitions < 0)
         throw tc::Error(TC_ERR_INVALID_ARG, "negative option value");
     if (opt->cost_fn < TC_COST_ONE || opt->cost_fn > TC_COST_NEW)
         throw tc::Error(TC_ERR_INVALID_ARG, "unknown cost function");
@@ -171,11 +174,13 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
         g->lds_max = o.lds_list_max > 0 ? std::max(2, std::min(o.lds_list_max, tc::max_lds_list())) : tc::max_lds_list();
         g->cost_fn = o.cost_fn;
         g->min_chunk = o.min_chunk;
+        g->rounds = o.rounds;
         tc::BuildParams bp;
         bp.workers = g->workers;
         bp.cost_fn = o.cost_fn;
         bp.min_chunk = o.min_chunk;
         bp.small_max = g->small_max;
+        bp.rounds = o.rounds;
 
         // Resident unless forced or over the budget: the resident build holds
         // the input (when copied in), its scratch, the adjacency and the count
@@ -240,6 +245,13 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
         } else {
             tc::build_oriented_device(dsrc, ddst, pk, bp, g->al, s, g->o);
         }
+        // canonical rows of one graph never exceed its input edges
+        g->max_graph_m = g->o.M;
+        if (k > 1) {
+            g->max_graph_m = 0;
+            for (int32_t i = 0; i < k; ++i) g->max_graph_m = std::max<int64_t>(g->max_graph_m, graphs[i].m);
+            g->max_graph_m = std::min<int64_t>(g->max_graph_m, g->o.M);
+        }
     });
     if (st != TC_OK) return st;
     *out = g.release();
@@ -262,10 +274,12 @@ tc_status tc_graph_reschedule(tc_graph *g, const tc_options *opt) {
         bp.workers = o.workers > 0 ? o.workers : tc::small_kernel_waves_per_cu(true) * cus;
         bp.cost_fn = o.cost_fn;
         bp.min_chunk = o.min_chunk;
+        bp.rounds = o.rounds;
         bp.small_max = o.small_max > 0 ? std::min(o.small_max, tc::max_small_list()) : tc::max_small_list();
         // a partitioned handle builds its task tables at count time
         if (!g->part) tc::reschedule_device(g->pk, bp, g->al, s, g->o);
         g->min_chunk = bp.min_chunk;
+        g->rounds = bp.rounds;
         g->workers = bp.workers;
         g->small_max = bp.small_max;
         g->cost_fn = bp.cost_fn;
@@ -294,6 +308,7 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
             bp.cost_fn = g->cost_fn;
             bp.min_chunk = g->min_chunk;
             bp.small_max = g->small_max;
+            bp.rounds = g->rounds > 0 ? g->rounds : 1;
             const int32_t lds = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
             if (timing) TC_HIP(hipEventRecord(g->ev[0], s));
             tc::count_partitioned(*g->part, bp, lds, g->al, s, g->totals.p, want_tv ? g->tv.p : nullptr,
@@ -312,7 +327,7 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
             L.total_tasks = g->o.tasks;
             L.total_med = g->o.nmed;
             L.total_large = g->o.nbig - g->o.nmed;
-            L.max_m = g->o.M;
+            L.max_m = g->max_graph_m;
             L.heads = g->heads.p;
             L.workers = opt && opt->workers > 0 ? opt->workers : g->workers;
             L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
@@ -417,7 +432,7 @@ tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt,
         L.total_med = med_base;
         L.total_large = large_base;
         L.max_m = 0;
-        for (int32_t i = 0; i < ng; ++i) L.max_m = std::max<int64_t>(L.max_m, gs[i]->o.M);
+        for (int32_t i = 0; i < ng; ++i) L.max_m = std::max<int64_t>(L.max_m, gs[i]->max_graph_m);
         L.heads = heads;
         L.workers = opt && opt->workers > 0 ? opt->workers : workers;
         L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : lds_max;
@@ -455,6 +470,7 @@ tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info) {
     info->device_bytes = g->al.live;
     info->peak_device_bytes = g->al.peak;
     info->partitions = g->part ? g->part->P : 1;
+    info->rounds = g->part ? (g->rounds > 0 ? g->rounds : 1) : g->o.rounds;
     info->streamed_bytes = g->part ? g->part->streamed_bytes : 0;
     info->workers = g->workers;
     info->small_max = g->small_max;

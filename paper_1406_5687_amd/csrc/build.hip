@@ -591,7 +591,10 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
         TC_LAUNCH_CHECK();
     }
     Schedule sc;
-    schedule_sources(f.p, wmed.p, wlarge.p, N, pk.k, out.node_base.p, bp, al, tmp, s, sc, maxd.p, &out.max_dhat);
+    BuildParams bpr = bp;
+    bpr.rounds = bp.rounds > 0 ? bp.rounds : auto_rounds(pk.k, M);
+    out.rounds = bpr.rounds;
+    schedule_sources(f.p, wmed.p, wlarge.p, N, pk.k, out.node_base.p, bpr, al, tmp, s, sc, maxd.p, &out.max_dhat);
     out.bnd = std::move(sc.bnd);
     out.gid = std::move(sc.gid);
     out.big = std::move(sc.big);
@@ -636,7 +639,9 @@ void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wl
         // automatic floor: about 1/64 of an initial task's cost, at least 256
         min_chunk = std::max<int64_t>(256, out.total_cost / ((int64_t)bp.workers * 128 + 1));
     }
-    std::vector<int64_t> tg = task_targets(out.total_cost, bp.workers, min_chunk);
+    const int64_t W = (int64_t)bp.workers * std::max(1, bp.rounds);
+    if (W > INT32_MAX) throw Error(TC_ERR_INVALID_ARG, "workers * rounds too large");
+    std::vector<int64_t> tg = task_targets(out.total_cost, (int32_t)W, min_chunk);
     const int64_t ntg = (int64_t)tg.size();
     DevBuf<int32_t> bnd(al, (size_t)ntg + 1);
     task_bounds(F.p, N, tg, bnd.p, tmp, s);
@@ -655,6 +660,12 @@ void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wl
     }
     // Scratch buffers are released in stream order when this scope ends.
     TC_HIP(hipStreamSynchronize(s));
+}
+
+int32_t auto_rounds(int32_t k, int64_t M) {
+    if (k <= 1) return 1;
+    const int64_t r = ceil_div(M * 4, (int64_t)64 << 20);
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(r, 64));
 }
 
 void task_bounds(const int64_t *F, int64_t N, const std::vector<int64_t> &targets, int32_t *bnd, Allocator &tmp,

@@ -264,7 +264,7 @@ template <bool PER_NODE, bool IDX32, bool SLICE>
 __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColReader<IDX32> &rd,
                                                  gptr_t<const int32_t> gcol, gptr_t<const int64_t> off,
                                                  int64_t *__restrict__ tv, int32_t s, int32_t a, int32_t te,
-                                                 int32_t row_lo, int32_t x0, int32_t x1, int lane) {
+                                                 int32_t row_lo, int64_t ebase, int32_t x0, int32_t x1, int lane) {
     const bool h0 = lane < a, h1 = lane + 64 < a;
     if (h0) {
         uint32_t sl = hash_slot(x0, kSmallHashBits);
@@ -293,13 +293,13 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     if (b0 > 0) {
         const int j = mbcnt64(m0);
         S.P[j] = inc0 - b0;
-        S.base[j] = (idx_t<IDX32>)(r0 - (int64_t)(inc0 - b0));
+        S.base[j] = (idx_t<IDX32>)(r0 - ebase - (int64_t)(inc0 - b0));
         S.tpos[j] = (uint8_t)lane;
     }
     if (b1 > 0) {
         const int j = n0 + mbcnt64(m1);
         S.P[j] = inc1 - b1;
-        S.base[j] = (idx_t<IDX32>)(r1 - (int64_t)(inc1 - b1));
+        S.base[j] = (idx_t<IDX32>)(r1 - ebase - (int64_t)(inc1 - b1));
         S.tpos[j] = (uint8_t)(64 + lane);
     }
     const int nt = n0 + popc64(m1);
@@ -356,12 +356,18 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
         const gptr_t<const int32_t> col = gview(SLICE ? descs[h].scol : descs[h].col);
         const gptr_t<const int64_t> soff = gview(SLICE ? descs[h].soff : descs[h].off);
         const gptr_t<const int64_t> off = gview(descs[h].off);
-        const ColReader<IDX32> rd(descs[h].col, descs[h].m);
         int64_t *__restrict__ tv = descs[h].tv;
         const int32_t row_lo = SLICE ? descs[h].row_lo : 0;
         const int64_t lt = c - descs[h].task_base;
         const int32_t v0 = descs[h].bnd[lt], v1 = descs[h].bnd[lt + 1];
         const int g = descs[h].gid ? descs[h].gid[lt] : 0;
+        // rows are addressed from the first entry of the task's graph
+        int64_t ebase = 0, mg = descs[h].m;
+        if (!SLICE && descs[h].k > 1) {
+            ebase = off[descs[h].node_base[g]];
+            mg = off[descs[h].node_base[g + 1]] - ebase;
+        }
+        const ColReader<IDX32> rd(descs[h].col + ebase, mg);
         const int small_max = descs[h].small_max;
         uint64_t tri = 0;
         for (int32_t s0 = v0; s0 < v1; s0 += 64) {
@@ -393,7 +399,8 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
                 const int32_t nx1 = col[rn + min(lane + 64, an - 1)];
                 const int32_t te = readlane32(tl, j);
                 const int32_t sl = SLICE ? readlane32(lab, j) : s0 + j;
-                tri += source_small<PER_NODE, IDX32, SLICE>(S, rd, col, off, tv, sl, a, te, row_lo, x0, x1, lane);
+                tri += source_small<PER_NODE, IDX32, SLICE>(S, rd, col, off, tv, sl, a, te, row_lo, ebase, x0, x1,
+                                                            lane);
                 j = jn;
                 a = an;
                 rs = rn;
@@ -435,7 +442,7 @@ struct WideLds {
 // (tpos relative to i0).  Returns (rows, total ids).
 template <int WAVES, bool IDX32, class L>
 __device__ __forceinline__ void wide_rows(L &S, gptr_t<const int32_t> col, gptr_t<const int64_t> off, int64_t rs,
-                                          int32_t i0, int32_t i1, int32_t row_lo, int32_t *nt_out,
+                                          int32_t i0, int32_t i1, int32_t row_lo, int64_t ebase, int32_t *nt_out,
                                           int32_t *total_out) {
     constexpr int kThreadsW = WAVES * 64;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
@@ -467,7 +474,7 @@ __device__ __forceinline__ void wide_rows(L &S, gptr_t<const int32_t> col, gptr_
             const int j = carry_n + cb + mbcnt64(m);
             const int32_t p = carry_sum + sb + inc - b;
             S.P[j] = p;
-            S.base[j] = (idx_t<IDX32>)(r - (int64_t)p);
+            S.base[j] = (idx_t<IDX32>)(r - ebase - (int64_t)p);
             S.tpos[j] = (int16_t)(i - i0);
         }
         carry_n += ct;
@@ -533,7 +540,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__re
         const gptr_t<const int32_t> col = gview(SLICE ? descs[h].scol : descs[h].col);
         const gptr_t<const int64_t> soff = gview(SLICE ? descs[h].soff : descs[h].off);
         const gptr_t<const int64_t> off = gview(descs[h].off);
-        const ColReader<IDX32> rd(descs[h].col, descs[h].m);
         int64_t *__restrict__ tv = descs[h].tv;
         const int32_t row_lo = SLICE ? descs[h].row_lo : 0;
         const int64_t first = TIER == 1 ? 0 : descs[h].nmed;
@@ -544,6 +550,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__re
         const int32_t a = (int32_t)(soff[si + 1] - rs);
         const int32_t te = SLICE ? min(descs[h].tcnt[si], a - 1) : a - 1;
         const int32_t s = SLICE ? descs[h].sid[si] : si;
+        const int g = graph_of(descs[h].node_base, descs[h].k, s);
+        // rows are addressed from the first entry of the source's graph
+        int64_t ebase = 0, mg = descs[h].m;
+        if (!SLICE && descs[h].k > 1) {
+            ebase = off[descs[h].node_base[g]];
+            mg = off[descs[h].node_base[g + 1]] - ebase;
+        }
+        const ColReader<IDX32> rd(descs[h].col + ebase, mg);
         uint64_t hits = 0;
         if (te <= 0) {
             // no resident target (slice launches only)
@@ -556,7 +570,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__re
             }
             __syncthreads();
             int32_t nt, total;
-            wide_rows<WAVES, IDX32>(S, col, off, rs, 0, te, row_lo, &nt, &total);
+            wide_rows<WAVES, IDX32>(S, col, off, rs, 0, te, row_lo, ebase, &nt, &total);
             hits = wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, 0, nt, total, true);
             __syncthreads();
             if (PER_NODE) {
@@ -573,7 +587,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__re
             for (int32_t i0 = 0; i0 < te; i0 += cap) {
                 const int32_t i1 = min(te, i0 + cap);
                 int32_t nt, total;
-                wide_rows<WAVES, IDX32>(S, col, off, rs, i0, i1, row_lo, &nt, &total);
+                wide_rows<WAVES, IDX32>(S, col, off, rs, i0, i1, row_lo, ebase, &nt, &total);
                 hits += wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, i0, nt, total, false);
                 __syncthreads();
             }
@@ -585,7 +599,6 @@ __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__re
             uint64_t H = 0;
             for (int w = 0; w < WAVES; ++w) H += S.whits[w];
             if (H) {
-                const int g = graph_of(descs[h].node_base, descs[h].k, s);
                 add_u64(&descs[h].totals[g], H);
                 if (PER_NODE) add_u64(&tv[s], H);
             }

@@ -36,7 +36,12 @@ struct BuildParams {
     int32_t cost_fn = TC_COST_PRIOR;
     int64_t min_chunk = 0;
     int32_t small_max = 128;
+    int32_t rounds = 0;  // Eq. (1) with W = workers * rounds; 0 = automatic
 };
+
+// Automatic rounds: one for a single graph; for k packed graphs, enough that
+// the tasks in flight (1 / (2 rounds) of the edges) hold about 64 MiB of rows.
+int32_t auto_rounds(int32_t k, int64_t M);
 
 // Device-side product of a build (all in degree-order labels).
 struct Oriented {
@@ -54,6 +59,7 @@ struct Oriented {
     int64_t nbig = 0;
     int64_t nmed = 0;  // lists in big[0, nmed) have at most max_medium_list() entries
     int32_t max_dhat = 0;
+    int32_t rounds = 1;  // rounds of the task table
 };
 
 // src/dst: packed input edges on the device (edge e of graph g at edge_base[g] + i).

@@ -65,7 +65,8 @@ class Options(ctypes.Structure):
         ("lds_list_max", ctypes.c_int32),
         ("time_kernels", ctypes.c_int32),
         ("partitions", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("rounds", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -91,7 +92,8 @@ class GraphInfo(ctypes.Structure):
         ("cost_fn", ctypes.c_int32),
         ("streamed_bytes", ctypes.c_int64),
         ("peak_device_bytes", ctypes.c_uint64),
-        ("reserved", ctypes.c_int32 * 4),
+        ("rounds", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -166,7 +168,12 @@ class _TorchAllocator:
                 return 0
 
         def _free(ptr, nbytes, stream, ctx):
-            torch.cuda.caching_allocator_delete(ptr)
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:
+                # interpreter shutdown: torch is already torn down and the
+                # process releases the device memory itself
+                pass
 
         self.alloc = _ALLOC_FN(_alloc)
         self.free = _FREE_FN(_free)
@@ -182,7 +189,7 @@ def _is_tensor(x) -> bool:
 
 def make_options(*, stream=None, inputs_on_device=False, outputs_on_device=False, hbm_budget_bytes=0, workers=0,
                  cost_fn=COST_PRIOR, min_chunk=0, small_max=0, lds_list_max=0, time_kernels=False,
-                 partitions=0, torch_allocator=True) -> Options:
+                 partitions=0, rounds=0, torch_allocator=True) -> Options:
     global _torch_alloc
     o = Options()
     load().tc_options_default(ctypes.byref(o))
@@ -196,6 +203,7 @@ def make_options(*, stream=None, inputs_on_device=False, outputs_on_device=False
     o.lds_list_max = int(lds_list_max)
     o.time_kernels = int(bool(time_kernels))
     o.partitions = int(partitions)
+    o.rounds = int(rounds)
     if stream is None:
         try:
             torch = _torch()
@@ -285,10 +293,10 @@ class Graph:
                                      ctypes.c_void_p(tot.ctypes.data)))
         return tv[: self.n_total], tot[: self.k]
 
-    def reschedule(self, workers=0, cost_fn=COST_PRIOR, min_chunk=0, small_max=0):
+    def reschedule(self, workers=0, cost_fn=COST_PRIOR, min_chunk=0, small_max=0, rounds=0):
         """New task table for the same adjacency (tc_graph_reschedule); later
         counts use it."""
-        self._kw.update(workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max)
+        self._kw.update(workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max, rounds=rounds)
         o = self._opts()
         _raise(load().tc_graph_reschedule(self._h, ctypes.byref(o)))
 
@@ -341,7 +349,7 @@ class Graph:
 
 
 def build_oriented(graphs: Sequence, *, stream=None, hbm_budget_bytes=0, workers=0, cost_fn=COST_PRIOR, min_chunk=0,
-                   small_max=0, lds_list_max=0, partitions=0, torch_allocator=True) -> Graph:
+                   small_max=0, lds_list_max=0, partitions=0, rounds=0, torch_allocator=True) -> Graph:
     """Builds one handle from graphs given as (n, src, dst) triples.  src/dst are
     numpy arrays (host) or torch tensors (all on the device, or all host)."""
     if not len(graphs):
@@ -360,7 +368,7 @@ def build_oriented(graphs: Sequence, *, stream=None, hbm_budget_bytes=0, workers
         ns.append(int(n))
     kw = dict(stream=stream, hbm_budget_bytes=hbm_budget_bytes, workers=workers, cost_fn=cost_fn,
               min_chunk=min_chunk, small_max=small_max, lds_list_max=lds_list_max, partitions=partitions,
-              torch_allocator=torch_allocator)
+              rounds=rounds, torch_allocator=torch_allocator)
     o = make_options(inputs_on_device=on_dev, **kw)
     h = ctypes.c_void_p(0)
     _raise(load().tc_build_oriented(arr, len(graphs), ctypes.byref(o), ctypes.byref(h)))
@@ -373,7 +381,7 @@ _EDGES_DTYPE = np.dtype({"names": ["n", "m", "src", "dst"], "formats": ["<i4", "
 
 
 def build_packed_device(ns, ms, src_ptr: int, dst_ptr: int, *, stream=None, workers=0, cost_fn=COST_PRIOR,
-                        min_chunk=0, small_max=0, lds_list_max=0, torch_allocator=True) -> Graph:
+                        min_chunk=0, small_max=0, lds_list_max=0, rounds=0, torch_allocator=True) -> Graph:
     """Builds one handle from k graphs whose edges already lie back to back in
     two device arrays (graph i's edges start at the sum of the earlier m), read
     in place.  ns / ms: node and edge counts per graph; src_ptr / dst_ptr:
@@ -391,7 +399,7 @@ def build_packed_device(ns, ms, src_ptr: int, dst_ptr: int, *, stream=None, work
     arr["src"] = np.uint64(src_ptr) + (eb * 4).astype(np.uint64)
     arr["dst"] = np.uint64(dst_ptr) + (eb * 4).astype(np.uint64)
     kw = dict(stream=stream, workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max,
-              lds_list_max=lds_list_max, torch_allocator=torch_allocator)
+              lds_list_max=lds_list_max, rounds=rounds, torch_allocator=torch_allocator)
     o = make_options(inputs_on_device=True, **kw)
     h = ctypes.c_void_p(0)
     _raise(load().tc_build_oriented(ctypes.cast(arr.ctypes.data, ctypes.POINTER(Edges)), k, ctypes.byref(o),

@@ -184,6 +184,22 @@ def test_schedule_matches_oracle(tc, cost, W, floor):
     np.testing.assert_array_equal(tv, tv_ref)
 
 
+def test_schedule_rounds_matches_oracle(tc):
+    # rounds R: Eq. (1)/(2) with W * R workers; the automatic floor still uses W
+    g = graphgen.preferential_attachment(20_000, 8, 12)
+    m, off_o, col_o, deg = oracle.orient(g.n, g.src, g.dst)
+    perm = oracle.degree_order(deg)
+    f = oracle.costs(off_o, col_o, deg, oracle.COST_PRIOR)[perm].copy()
+    f[np.diff(off_o)[perm] > 128] = 0
+    total = int(f.sum())
+    W, R = 64, 5
+    bnd_ref = oracle.schedule(f, W * R, max(256, total // (W * 128 + 1)))
+    with tc.build_oriented([(g.n, g.src, g.dst)], workers=W, rounds=R) as h:
+        bnd, _ = h.export_schedule()
+        assert h.info()["rounds"] == R
+    np.testing.assert_array_equal(bnd, bnd_ref)
+
+
 # ------------------------------------------------------------ invariance (Section V-D)
 
 @pytest.mark.parametrize("kw", [
@@ -191,6 +207,7 @@ def test_schedule_matches_oracle(tc, cost, W, floor):
     dict(small_max=2), dict(small_max=16), dict(small_max=128),
     dict(lds_list_max=2), dict(lds_list_max=50), dict(small_max=4, lds_list_max=8),
     dict(cost_fn=0), dict(cost_fn=1), dict(cost_fn=3), dict(min_chunk=1), dict(min_chunk=10**12),
+    dict(rounds=7), dict(rounds=64), dict(workers=3, rounds=1000),
 ], ids=lambda kw: ",".join(f"{k}={v}" for k, v in kw.items()))
 def test_tuning_invariance(tc, kw):
     g = graphgen.rmat(13, 16, seed=13)
