@@ -108,8 +108,12 @@ struct ColReader;
 template <>
 struct ColReader<true> {
     __amdgpu_buffer_rsrc_t rsrc;
+    // col and m are the same in every lane; building the descriptor from
+    // first-lane copies keeps it in scalar registers (no per-load waterfall)
     __device__ __forceinline__ ColReader(const int32_t *col, int64_t m) {
-        rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)col, (short)0, (int)(m * 4), 0x00020000);
+        const uint64_t base = (uint64_t)uniform64((int64_t)(uintptr_t)col);
+        const int32_t bytes = uniform32((int32_t)(m * 4));
+        rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)(uintptr_t)base, (short)0, bytes, 0x00020000);
     }
     // offsets at or past the end read 0 (hardware range check); callers mask those lanes
     __device__ __forceinline__ int32_t load(int32_t idx, bool ok) const {
