@@ -158,34 +158,46 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
     uint32_t *flag_word = reinterpret_cast<uint32_t *>(flag);
     uint32_t hits = 0;
     for (int32_t e0 = e_begin; e0 < e_end; e0 += kStep) {
-        // row starts inside (e0, e0 + kStep); rows past the last read the total
-        for (int jb = cur + 1;; jb += 64) {
-            const int jj = min(jb + lane, nt);
-            const int32_t p = P[jj] - e0;  // >= 1
-            if (p < kStep) flag[((p & 63) << 2) + (p >> 6)] = 1;
-            if (readlane32(p, 63) >= kStep || jb + 63 >= nt) break;
-        }
-        wave_lds_sync();
-        const uint32_t fw = flag_word[lane];
-        flag_word[lane] = 0u;
-        uint64_t M[kWin];
-        int pre[kWin];
-        int acc = 0;
-#pragma unroll
-        for (int q = 0; q < kWin; ++q) {
-            M[q] = __ballot(((fw >> (8 * q)) & 0xffu) != 0u);
-            pre[q] = acc;
-            acc += popc64(M[q]);
-        }
         int seg[kWin];
         int32_t w[kWin];
         bool ok[kWin];
+        int acc = 0;
+        if (uniform32(P[cur + 1]) >= e0 + kStep) {
+            // no row starts inside the step: every id lies in row cur
+            const idx_t<IDX32> b = base[cur];
 #pragma unroll
-        for (int q = 0; q < kWin; ++q) {
-            seg[q] = min(cur + pre[q] + mbcnt64(M[q]) + (int)((fw >> (8 * q)) & 1u), nt - 1);
-            const int32_t e = e0 + 64 * q + lane;
-            ok[q] = e < total;
-            w[q] = rd.load(base[seg[q]] + e, ok[q]);
+            for (int q = 0; q < kWin; ++q) {
+                seg[q] = cur;
+                const int32_t e = e0 + 64 * q + lane;
+                ok[q] = e < total;
+                w[q] = rd.load(b + e, ok[q]);
+            }
+        } else {
+            // row starts inside (e0, e0 + kStep); rows past the last read the total
+            for (int jb = cur + 1;; jb += 64) {
+                const int jj = min(jb + lane, nt);
+                const int32_t p = P[jj] - e0;  // >= 1
+                if (p < kStep) flag[((p & 63) << 2) + (p >> 6)] = 1;
+                if (readlane32(p, 63) >= kStep || jb + 63 >= nt) break;
+            }
+            wave_lds_sync();
+            const uint32_t fw = flag_word[lane];
+            flag_word[lane] = 0u;
+            uint64_t M[kWin];
+            int pre[kWin];
+#pragma unroll
+            for (int q = 0; q < kWin; ++q) {
+                M[q] = __ballot(((fw >> (8 * q)) & 0xffu) != 0u);
+                pre[q] = acc;
+                acc += popc64(M[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < kWin; ++q) {
+                seg[q] = min(cur + pre[q] + mbcnt64(M[q]) + (int)((fw >> (8 * q)) & 1u), nt - 1);
+                const int32_t e = e0 + 64 * q + lane;
+                ok[q] = e < total;
+                w[q] = rd.load(base[seg[q]] + e, ok[q]);
+            }
         }
 #pragma unroll
         for (int q = 0; q < kWin; ++q) w[q] = ok[q] ? w[q] : -1;
@@ -240,7 +252,7 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
             }
         }
         int nc = cur + acc;
-        if (nc + 1 < nt && P[nc + 1] == e0 + kStep) ++nc;
+        if (nc + 1 < nt && uniform32(P[nc + 1]) == e0 + kStep) ++nc;
         cur = nc;
         wave_lds_sync();
     }
