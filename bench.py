@@ -25,6 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "count_pa1e6_d50_counters.json")
+COUNT_SOURCE = os.path.join(ROOT, "paper_1406_5687_amd", "csrc", "count.hip")
 
 
 def log(msg: str):
@@ -53,6 +55,27 @@ def algorithmic_bytes(off, col, n: int, per_node: bool) -> tuple[int, int]:
     sum_dt = int(dh[col].sum()) if len(col) else 0
     m = len(col)
     return 4 * m + 4 * sum_dt + 8 * (n + 1) + (8 * n if per_node else 0), sum_dt
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per per-node count launch from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by
+    what the same counters read for a plain copy of known size), or None when
+    there is no summary for this workload or the count kernel source has
+    changed since the counters were taken."""
+    import hashlib
+
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+        with open(COUNT_SOURCE, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if c.get("workload") != workload or c.get("count_source_sha256") != sha:
+        return None
+    return (c["fetch_kib_per_dispatch"] * 1024 * c["fetch_factor"]
+            + c["write_kib_per_dispatch"] * 1024 * c["write_factor"])
 
 
 def cpu_baseline(seconds_hint: float = 20.0) -> dict:
@@ -455,8 +478,9 @@ def main() -> int:
         "config": {"workload": wl_name, "n": g.n, "m": m, "m_input": g.m, "per_node": True,
                    "step": "tc_build_oriented + tc_count_per_node, edge list resident in HBM"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "k_count_small (+ k_count_big when lists exceed 128)",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(args.workload),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.00 + WRITE_SIZE x1.00)",
+                     "kernel": "k_count_small (+ k_count_wide when lists exceed 128 entries)",
                      "alg_bytes_per_launch": b_alg, "kernel_ms": k_ms},
         "detail": {"triangles": T, "count_kernel_ms": k_ms, "build_ms_single": build_ms,
                    "count_only_edges_per_s": m / (k_ms * 1e-3), "sum_target_list_len": sum_dt},
