@@ -321,6 +321,111 @@ def bench_serve(args) -> int:
     return 0 if (alone_ok and same_runs) else 1
 
 
+def bench_ablation_surrogate(args) -> int:
+    """Direct vs surrogate streaming in the partitioned form (Section IV-C):
+    the same graph in P node-range slices, with each list streamed once per
+    slice (surrogate) or once per stored edge (direct).  Both must equal the
+    resident counts; prints one JSON line per scheme."""
+    import numpy as np
+    import torch
+
+    import paper_1406_5687_amd as tc
+
+    g, wl_name = make_workload(args.workload)
+    out = torch.zeros(g.n, dtype=torch.int64, device="cuda")
+    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with tc.build_oriented([(g.n, g.src, g.dst)]) as h:
+        h.count_per_node(out=out, totals=tot, time_kernels=True)
+        res_ms = h.info()["last_count_ms"]
+        m = h.info()["m"]
+    ref = out.clone()
+    T_ref = int(tot.item())
+    rc = 0
+    for direct in (False, True):
+        tb = time.perf_counter()
+        h = tc.build_oriented([(g.n, g.src, g.dst)], partitions=args.partitions, direct=direct)
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - tb) * 1e3
+        ms = []
+        for i in range(args.warmup + args.steps):
+            out.fill_(-1)
+            h.count_per_node(out=out, totals=tot, time_kernels=True)
+            if i >= args.warmup:
+                ms.append(h.info()["last_count_ms"])
+        info = h.info()
+        h.free()
+        same = int(tot.item()) == T_ref and bool(torch.equal(out, ref))
+        rc |= 0 if same else 1
+        c_ms = float(np.median(ms))
+        scheme = "direct" if direct else "surrogate"
+        log(f"{scheme}: P={info['partitions']} count {c_ms:.1f} ms streamed {info['streamed_bytes'] / 1e9:.3f} GB "
+            f"identical={same}")
+        print(json.dumps({
+            "metric": "oriented edges/s", "value": m / (c_ms * 1e-3), "unit": "oriented edges/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": c_ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32 ids, int64 counts", "data": "synthetic",
+            "config": {"workload": wl_name, "n": g.n, "m": m, "per_node": True, "scheme": scheme,
+                       "partitions": info["partitions"],
+                       "step": "tc_count_per_node of a partitioned handle (lists streamed from pinned host memory)"},
+            "detail": {"streamed_bytes": info["streamed_bytes"], "build_ms": build_ms, "resident_count_ms": res_ms,
+                       "identical_to_resident": same, "triangles": int(tot.item())}}), flush=True)
+    return rc
+
+
+def bench_ablation_idle(args) -> int:
+    """Idle time of the persistent workers with equal-cost tasks against the
+    shrinking tasks of Eq. (1)/(2) (the comparison of Fig. 13): per-node counts
+    of one handle under both schedules, each worker's start and stop recorded
+    on the device.  Idle time of a wave taking node-range tasks = last stop
+    over those waves - its own stop (the long-list workgroups, handed out
+    longest first, are not part of the schedule).  One JSON line per schedule."""
+    import numpy as np
+    import torch
+
+    import paper_1406_5687_amd as tc
+
+    g, wl_name = make_workload(args.workload)
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    out = torch.zeros(g.n, dtype=torch.int64, device="cuda")
+    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+    h = tc.build_oriented([(g.n, src, dst)])
+    m = h.info()["m"]
+    ref = None
+    rc = 0
+    for static in (True, False):
+        h.reschedule(static_chunks=static)
+        rows = []
+        for i in range(args.warmup + args.steps):
+            h.count_per_node(out=out, totals=tot, time_kernels=2)
+            ms = h.info()["last_count_ms"]
+            t = h.worker_times()
+            t = t[t[:, 2] == 0]  # the waves taking node-range tasks
+            if i >= args.warmup:
+                span = float(t[:, 1].max() - t[:, 0].min())
+                idle = float((t[:, 1].max() - t[:, 1]).mean())
+                rows.append((ms, idle / span if span > 0 else 0.0, idle * 1e-6, len(t)))
+        if ref is None:
+            ref = out.clone()
+        same = bool(torch.equal(out, ref))
+        rc |= 0 if same else 1
+        ms, frac, idle_ms, nw = (float(np.median([r[k] for r in rows])) for k in range(4))
+        sched = "equal-cost tasks" if static else "Eq. (1)/(2)"
+        info = h.info()
+        log(f"{sched}: count {ms:.3f} ms, node-range waves idle {idle_ms:.3f} ms on average = {100 * frac:.1f}% of their span, "
+            f"{int(nw)} workers, {info['tasks']} tasks")
+        print(json.dumps({
+            "metric": "oriented edges/s", "value": m / (ms * 1e-3), "unit": "oriented edges/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32 ids, int64 counts", "data": "synthetic",
+            "config": {"workload": wl_name, "n": g.n, "m": m, "per_node": True, "schedule": sched,
+                       "step": "tc_count_per_node (resident), per-worker start and stop recorded"},
+            "detail": {"mean_idle_ms": idle_ms, "idle_fraction": frac, "workers": int(nw), "tasks": info["tasks"],
+                       "identical_counts": same}}), flush=True)
+    h.free()
+    return rc
+
+
 def profile_counts(args) -> int:
     """Short, fixed sequence of launches for hardware-counter runs."""
     import torch
@@ -379,6 +484,10 @@ def main() -> int:
     ap.add_argument("--batch-graphs", type=int, default=4096, help="graphs in the batch workload")
     ap.add_argument("--tune", action="store_true", help="autotune the batch schedule before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ablation", choices=["surrogate", "idle"], default=None,
+                    help="surrogate: direct vs surrogate streaming of the partitioned form (--partitions slices); "
+                         "idle: worker idle time with equal-cost tasks vs Eq. (1)/(2)")
+    ap.add_argument("--partitions", type=int, default=8, help="slices for --ablation surrogate")
     ap.add_argument("--budget-gb", type=float, nargs="+", default=None,
                     help="partitioned form: build and count the workload under each device budget (GiB), "
                          "edge list in host memory, and compare with the resident counts")
@@ -407,6 +516,10 @@ def main() -> int:
         return bench_serve(args)
     if args.budget_gb:
         return bench_partitioned(args)
+    if args.ablation == "surrogate":
+        return bench_ablation_surrogate(args)
+    if args.ablation == "idle":
+        return bench_ablation_idle(args)
 
     t0 = time.time()
     g, wl_name = make_workload(args.workload)

@@ -88,7 +88,8 @@ typedef struct {
     int32_t lds_list_max; /* longest list a workgroup stages in LDS; longer lists are probed by
                              binary search in device memory; 0 = automatic (4096, the maximum) */
     int32_t time_kernels; /* 1: record device events around the counting kernels of each count
-                             call; the elapsed time is reported by tc_graph_info */
+                             call; the elapsed time is reported by tc_graph_info.  2: also record
+                             when each worker starts and stops (tc_worker_times) */
     int32_t partitions;   /* build time: > 0 forces the partitioned form with at least this many
                              node-range partitions (one graph per handle); 0 = only when the
                              budget requires it */
@@ -96,7 +97,12 @@ typedef struct {
                              tasks (Eq. (1) with W = workers * rounds), so the tasks in flight
                              cover 1 / (2 rounds) of the nodes at a time; 0 = automatic (1 for
                              one graph, more for large packed batches) */
-    int32_t reserved[5];
+    int32_t direct;       /* partitioned form, build time: 1 streams the list of v once per stored
+                             edge (v, u) (the direct scheme of Section IV-C) instead of once per
+                             partition (the surrogate scheme); same results, for comparison */
+    int32_t static_chunks; /* schedule: 1 = W tasks of equal cost instead of the shrinking tasks of
+                              Eq. (1)/(2); same results, for comparison */
+    int32_t reserved[3];
 } tc_options;
 
 /* Fills *opt with the defaults (all zero except cost_fn = TC_COST_PRIOR). */
@@ -182,6 +188,18 @@ tc_status tc_export_csr(const tc_graph *g, const tc_options *opt, int64_t *off, 
  * capacity of bnd; *tasks receives the number of tasks. */
 tc_status tc_export_schedule(const tc_graph *g, const tc_options *opt, int32_t *bnd, int32_t *gid, int64_t cap,
                              int64_t *tasks);
+
+/* Worker timeline of the last count of g made with time_kernels = 2 (resident
+ * handles): for each persistent worker i, times[3i] and times[3i+1] receive when
+ * it started and when it stopped, in nanoseconds from the earliest start, and
+ * times[3i+2] its kind: 0 = a wave taking node-range tasks (Eq. (1)/(2)),
+ * 1 = a workgroup taking lists of up to 1024 entries, 2 = a workgroup taking
+ * longer lists.  cap is the number of workers times can hold; *nworkers
+ * receives the number of workers (0 if no such count).  Synchronises the
+ * stream.  Errors: TC_ERR_INVALID_ARG (NULL g or nworkers, cap below
+ * *nworkers with times non-NULL), TC_ERR_DEVICE. */
+tc_status tc_worker_times(const tc_graph *g, const tc_options *opt, int64_t *times, int64_t cap,
+                          int64_t *nworkers);
 
 /* Releases the handle and its device memory.  NULL is a no-op. */
 void tc_graph_free(tc_graph *g);

@@ -27,6 +27,11 @@ struct tc_graph {
     // optional device timing of the counting kernels
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool timed = false;
+    // per-worker (start, stop) wall-clock ticks of the last count with time_kernels = 2
+    tc::DevBuf<unsigned long long> times;
+    int64_t times_used = 0;
+    int64_t times_tier[3] = {0, 0, 0};
+    int32_t static_chunks = 0;
     ~tc_graph() {
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -74,7 +79,7 @@ void check_options(const tc_options *opt) {
     if ((opt->alloc == nullptr) != (opt->free == nullptr))
         throw tc::Error(TC_ERR_INVALID_ARG, "alloc and free callbacks must be given together");
     if (opt->workers < 0 || opt->min_chunk < 0 || opt->small_max < 0 || opt->lds_list_max < 0 || opt->rounds < 0 ||
-        opt->partitions < 0)
+        opt->partitions < 0 || opt->direct < 0)
         throw tc::Error(TC_ERR_INVALID_ARG, "negative option value");
     if (opt->cost_fn < TC_COST_ONE || opt->cost_fn > TC_COST_NEW)
         throw tc::Error(TC_ERR_INVALID_ARG, "unknown cost function");
@@ -181,6 +186,9 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
         bp.min_chunk = o.min_chunk;
         bp.small_max = g->small_max;
         bp.rounds = o.rounds;
+        bp.direct = o.direct;
+        bp.static_chunks = o.static_chunks;
+        g->static_chunks = o.static_chunks;
 
         // Resident unless forced or over the budget: the resident build holds
         // the input (when copied in), its scratch, the adjacency and the count
@@ -275,11 +283,13 @@ tc_status tc_graph_reschedule(tc_graph *g, const tc_options *opt) {
         bp.cost_fn = o.cost_fn;
         bp.min_chunk = o.min_chunk;
         bp.rounds = o.rounds;
+        bp.static_chunks = o.static_chunks;
         bp.small_max = o.small_max > 0 ? std::min(o.small_max, tc::max_small_list()) : tc::max_small_list();
         // a partitioned handle builds its task tables at count time
         if (!g->part) tc::reschedule_device(g->pk, bp, g->al, s, g->o);
         g->min_chunk = bp.min_chunk;
         g->rounds = bp.rounds;
+        g->static_chunks = bp.static_chunks;
         g->workers = bp.workers;
         g->small_max = bp.small_max;
         g->cost_fn = bp.cost_fn;
@@ -309,6 +319,7 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
             bp.min_chunk = g->min_chunk;
             bp.small_max = g->small_max;
             bp.rounds = g->rounds > 0 ? g->rounds : 1;
+            bp.static_chunks = g->static_chunks;
             const int32_t lds = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
             if (timing) TC_HIP(hipEventRecord(g->ev[0], s));
             tc::count_partitioned(*g->part, bp, lds, g->al, s, g->totals.p, want_tv ? g->tv.p : nullptr,
@@ -332,8 +343,18 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
             L.workers = opt && opt->workers > 0 ? opt->workers : g->workers;
             L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
             L.per_node = want_tv;
+            g->times_used = 0;
+            if (opt && opt->time_kernels == 2) {
+                const int64_t cap = tc::max_timed_workers();
+                if (!g->times.p) g->times = tc::DevBuf<unsigned long long>(g->al, (size_t)(2 * cap));
+                tc::fill_zero(g->times.p, g->times.bytes(), s);
+                L.times = g->times.p;
+                L.times_cap = cap;
+            }
             if (timing) TC_HIP(hipEventRecord(g->ev[0], s));
             tc::count_launch(L, s);
+            g->times_used = L.times_used;
+            for (int t = 0; t < 3; ++t) g->times_tier[t] = L.times_tier[t];
             if (timing) {
                 TC_HIP(hipEventRecord(g->ev[1], s));
                 g->timed = true;
@@ -516,6 +537,35 @@ tc_status tc_export_schedule(const tc_graph *g, const tc_options *opt, int32_t *
         if (gid && g->pk.k > 1) copy_out(gid, g->o.gid.p, (size_t)g->o.tasks * 4, false, s);
         if (gid && g->pk.k == 1) std::fill(gid, gid + g->o.tasks, 0);
         TC_HIP(hipStreamSynchronize(s));
+    });
+}
+
+tc_status tc_worker_times(const tc_graph *g, const tc_options *opt, int64_t *times, int64_t cap,
+                          int64_t *nworkers) {
+    if (!g || !nworkers) return fail(TC_ERR_INVALID_ARG, "graph and nworkers must be non-NULL");
+    *nworkers = g->times_used;
+    if (!times || g->times_used == 0) return TC_OK;
+    if (cap < g->times_used) return fail(TC_ERR_INVALID_ARG, "times capacity below the number of workers");
+    return guarded([&] {
+        hipStream_t s = opt ? (hipStream_t)opt->stream : nullptr;
+        std::vector<unsigned long long> h((size_t)(2 * g->times_used));
+        TC_HIP(hipMemcpyAsync(h.data(), g->times.p, h.size() * 8, hipMemcpyDeviceToHost, s));
+        TC_HIP(hipStreamSynchronize(s));
+        int dev = 0, khz = 0;
+        TC_HIP(hipGetDevice(&dev));
+        TC_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        if (khz <= 0) throw tc::Error(TC_ERR_DEVICE, "no wall-clock rate");
+        unsigned long long t0 = ~0ull;
+        for (size_t i = 0; i < h.size(); i += 2)
+            if (h[i]) t0 = std::min(t0, h[i]);
+        int64_t w = 0;
+        for (int t = 0; t < 3; ++t)
+            for (int64_t i = 0; i < g->times_tier[t]; ++i, ++w)
+                for (int c = 0; c < 2; ++c) {
+                    const unsigned long long v = h[2 * w + c];
+                    times[3 * w + c] = v ? (int64_t)((double)(v - t0) * 1e6 / (double)khz) : -1;
+                    times[3 * w + 2] = t;
+                }
     });
 }
 

@@ -418,8 +418,15 @@ void fill_zero(void *p, size_t bytes, hipStream_t s) {
 // H = ceil(total/2); then C += max(ceil((total - C) / W), min_chunk) until C
 // reaches total, which ends the last task at the end of the node range
 // (encoded as -1).  The division by W uses a precomputed reciprocal.
-std::vector<int64_t> task_targets(int64_t total, int32_t W, int64_t min_chunk) {
+std::vector<int64_t> task_targets(int64_t total, int32_t W, int64_t min_chunk, bool static_chunks) {
     std::vector<int64_t> t;
+    if (static_chunks) {
+        // comparison schedule: W tasks of equal cost, no shrinking tail
+        for (int32_t i = 0; i + 1 < W; ++i)
+            t.push_back((int64_t)(((unsigned __int128)(i + 1) * (uint64_t)total + W - 1) / W));
+        t.push_back(-1);
+        return t;
+    }
     const int64_t H = (total + 1) / 2;
     const uint64_t w = (uint64_t)W;
     const uint64_t magic = ~0ull / w;  // floor((2^64 - 1) / W)
@@ -641,7 +648,7 @@ void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wl
     }
     const int64_t W = (int64_t)bp.workers * std::max(1, bp.rounds);
     if (W > INT32_MAX) throw Error(TC_ERR_INVALID_ARG, "workers * rounds too large");
-    std::vector<int64_t> tg = task_targets(out.total_cost, (int32_t)W, min_chunk);
+    std::vector<int64_t> tg = task_targets(out.total_cost, (int32_t)W, min_chunk, bp.static_chunks != 0);
     const int64_t ntg = (int64_t)tg.size();
     DevBuf<int32_t> bnd(al, (size_t)ntg + 1);
     task_bounds(F.p, N, tg, bnd.p, tmp, s);

@@ -355,9 +355,12 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
 
 template <bool PER_NODE, bool IDX32, bool SLICE>
 __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_count_small(
-    const CountDesc *__restrict__ descs, int ndesc, int64_t total_tasks, uint32_t *__restrict__ head, int nworkers) {
+    const CountDesc *__restrict__ descs, int ndesc, int64_t total_tasks, uint32_t *__restrict__ head, int nworkers,
+    unsigned long long *__restrict__ times) {
     __shared__ SmallLds<IDX32> lds[kSmallWaves];
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const int64_t me = (int64_t)blockIdx.x * kSmallWaves + wave;
+    if (times && lane == 0) times[2 * me] = wall_clock64();
     SmallLds<IDX32> &S = lds[wave];
     for (int i = lane; i < kSmallHash; i += 64) S.key[i] = -1;
     for (int i = lane; i < kSmallMax; i += 64) S.cnt[i] = 0;
@@ -430,6 +433,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
         if (lane == 0) nxt = atomicAdd(head, 1u);
         c = (int64_t)nworkers + (int64_t)(uint32_t)readlane32((int32_t)nxt, 0);
     }
+    if (times && lane == 0) times[2 * me + 1] = wall_clock64();
 }
 
 // ---------------------------------------------------------- one workgroup
@@ -536,7 +540,7 @@ __device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &r
 template <bool PER_NODE, bool IDX32, int WAVES, int LMAX, int HBITS, int TIER, bool SLICE>
 __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__restrict__ descs, int ndesc,
                                                            int64_t total_items, uint32_t *__restrict__ head,
-                                                           int lds_max) {
+                                                           int lds_max, unsigned long long *__restrict__ times) {
     constexpr int kThreadsW = WAVES * 64;
     constexpr int kHash = 1 << HBITS;
     __shared__ WideLds<WAVES, LMAX, HBITS, IDX32> S;
@@ -545,7 +549,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__re
     for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = -1;
     for (int i = threadIdx.x; i < LMAX; i += kThreadsW) S.cnt[i] = 0;
     for (int i = threadIdx.x; i < WAVES * kFlagBytes; i += kThreadsW) (&S.flag[0][0])[i] = 0;
-    if (threadIdx.x == 0) S.item = blockIdx.x;
+    if (threadIdx.x == 0) {
+        S.item = blockIdx.x;
+        if (times) times[2 * blockIdx.x] = wall_clock64();
+    }
     __syncthreads();
 
     for (;;) {
@@ -622,6 +629,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__re
         }
         __syncthreads();
     }
+    if (times && threadIdx.x == 0) times[2 * blockIdx.x + 1] = wall_clock64();
 }
 
 __global__ void k_scatter(const int64_t *__restrict__ tv, const int32_t *__restrict__ perm, int64_t n,
@@ -631,8 +639,16 @@ __global__ void k_scatter(const int64_t *__restrict__ tv, const int32_t *__restr
 }
 
 template <bool PER_NODE, bool IDX32, bool SLICE>
-void launch_all(const CountLaunch &L, int lds_max, hipStream_t s) {
+void launch_all(CountLaunch &L, int lds_max, hipStream_t s) {
     const int cus = device_cu_count();
+    // per-worker timestamps: each launch gets its own slice of L.times
+    int64_t used = 0;
+    auto times_for = [&](int64_t workers) -> unsigned long long * {
+        if (!L.times || used + workers > L.times_cap) return nullptr;
+        unsigned long long *p = L.times + 2 * used;
+        used += workers;
+        return p;
+    };
     if (L.total_tasks > 0) {
         // never launch more workers than can be resident at once: a worker that
         // starts late would hold its first task until the end
@@ -641,8 +657,10 @@ void launch_all(const CountLaunch &L, int lds_max, hipStream_t s) {
                                                             kSmallWaves * 64, 0));
         const int64_t resident = (int64_t)std::max(1, per_cu) * cus;
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(L.workers, kSmallWaves), resident));
-        k_count_small<PER_NODE, IDX32, SLICE>
-            <<<blocks, kSmallWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_tasks, L.heads, blocks * kSmallWaves);
+        unsigned long long *tm = times_for((int64_t)blocks * kSmallWaves);
+        L.times_tier[0] = tm ? (int64_t)blocks * kSmallWaves : 0;
+        k_count_small<PER_NODE, IDX32, SLICE><<<blocks, kSmallWaves * 64, 0, s>>>(
+            L.descs, L.ndesc, L.total_tasks, L.heads, blocks * kSmallWaves, tm);
         TC_LAUNCH_CHECK();
     }
     if (L.total_med > 0) {
@@ -650,16 +668,21 @@ void launch_all(const CountLaunch &L, int lds_max, hipStream_t s) {
         TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per_cu, k_count_wide<PER_NODE, IDX32, kMedWaves, kMedMax, kMedHashBits, 1, SLICE>, kMedWaves * 64, 0));
         const int blocks = (int)std::min<int64_t>((int64_t)std::max(1, per_cu) * cus, L.total_med);
+        unsigned long long *tm = times_for(blocks);
+        L.times_tier[1] = tm ? blocks : 0;
         k_count_wide<PER_NODE, IDX32, kMedWaves, kMedMax, kMedHashBits, 1, SLICE>
-            <<<blocks, kMedWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_med, L.heads + 1, lds_max);
+            <<<blocks, kMedWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_med, L.heads + 1, lds_max, tm);
         TC_LAUNCH_CHECK();
     }
     if (L.total_large > 0) {
         const int blocks = (int)std::min<int64_t>(cus, L.total_large);
+        unsigned long long *tm = times_for(blocks);
+        L.times_tier[2] = tm ? blocks : 0;
         k_count_wide<PER_NODE, IDX32, kBigWaves, kLdsMax, kBigHashBits, 2, SLICE>
-            <<<blocks, kBigThreads, 0, s>>>(L.descs, L.ndesc, L.total_large, L.heads + 2, lds_max);
+            <<<blocks, kBigThreads, 0, s>>>(L.descs, L.ndesc, L.total_large, L.heads + 2, lds_max, tm);
         TC_LAUNCH_CHECK();
     }
+    L.times_used = used;
 }
 
 }  // namespace
@@ -696,7 +719,12 @@ int device_cu_count() {
     return cus;
 }
 
-void count_launch(const CountLaunch &L, hipStream_t s) {
+int64_t max_timed_workers() {
+    // resident small-list waves plus one workgroup tier's resident blocks each
+    return (int64_t)device_cu_count() * (8 * kSmallWaves + 16 + 1);
+}
+
+void count_launch(CountLaunch &L, hipStream_t s) {
     const int lds_max = L.lds_max < 2 ? kLdsMax : (L.lds_max > kLdsMax ? kLdsMax : L.lds_max);
     // 32-bit row addressing needs every descriptor's adjacency below 2^29
     // entries; TC_FORCE_INDEX64=1 selects the 64-bit path anyway (testing)

@@ -37,6 +37,8 @@ struct BuildParams {
     int64_t min_chunk = 0;
     int32_t small_max = 128;
     int32_t rounds = 0;  // Eq. (1) with W = workers * rounds; 0 = automatic
+    int32_t direct = 0;  // partitioned form: one streamed range per stored edge
+    int32_t static_chunks = 0;  // W equal-cost tasks instead of Eq. (1)/(2)
 };
 
 // Automatic rounds: one for a single graph; for k packed graphs, enough that
@@ -87,7 +89,7 @@ struct Schedule {
 void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wlarge, int64_t N, int k,
                       const int64_t *node_base, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
                       Schedule &out, const int32_t *maxd_dev = nullptr, int32_t *maxd_host = nullptr);
-std::vector<int64_t> task_targets(int64_t total, int32_t W, int64_t min_chunk);
+std::vector<int64_t> task_targets(int64_t total, int32_t W, int64_t min_chunk, bool static_chunks = false);
 // bnd[0] = 0, bnd[j+1] = first x in [0, N] with F[x] >= targets[j] (targets < 0: N)
 void task_bounds(const int64_t *F, int64_t N, const std::vector<int64_t> &targets, int32_t *bnd, Allocator &tmp,
                  hipStream_t s);
@@ -126,6 +128,7 @@ struct Partitioned {
     int64_t msg_cap = 0;  // largest streamed ids / records of one batch
     int64_t rec_cap = 0;
     int64_t streamed_bytes = 0;  // host-to-device bytes of the last count
+    bool direct = false;         // records follow the direct scheme
 };
 
 // Builds the partitioned form of one graph.  src/dst: host arrays, or device
@@ -180,9 +183,16 @@ struct CountLaunch {
     int32_t lds_max;     // longest list kept in LDS by the workgroup kernels
     bool per_node;
     bool slice;  // descriptors are slice launches (32-bit row addressing)
+    // optional per-worker (start, finish) timestamps, wall-clock ticks: small-list
+    // waves first, then the workgroups of each tier; capacity in pairs
+    unsigned long long *times = nullptr;
+    int64_t times_cap = 0;
+    int64_t times_used = 0;  // set by count_launch: workers that wrote a pair
+    int64_t times_tier[3] = {0, 0, 0};  // set by count_launch: workers of each kernel
 };
 
-void count_launch(const CountLaunch &L, hipStream_t s);
+void count_launch(CountLaunch &L, hipStream_t s);
+int64_t max_timed_workers();  // upper bound on the workers of one count_launch
 
 // out[perm[i]] = tv[i] for i < n
 void scatter_per_node(const int64_t *tv, const int32_t *perm, int64_t n, int64_t *out, hipStream_t s);

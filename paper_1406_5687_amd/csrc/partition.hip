@@ -549,12 +549,20 @@ void build_partitioned(const int32_t *src, const int32_t *dst, bool on_device, c
     }
     U.release();
 
-    // records grouped by destination slice, then batches that fit the count's room
+    // Records grouped by destination slice, then batches that fit the count's
+    // room.  The direct scheme (Section IV-C, for comparison) sends a list once
+    // per stored edge instead of once per slice: record (v, pos, c, len) becomes
+    // c records (v, pos + k, 1, len - k), the part of N_v from its k-th target on.
     int64_t R = 0;
+    out.direct = bp.direct != 0;
     out.rbase.assign((size_t)P + 1, 0);
     for (int j = 0; j < P; ++j) {
         out.rbase[j] = R;
-        R += (int64_t)hv[j].size();
+        if (out.direct) {
+            for (const int32_t c : htc[j]) R += c;
+        } else {
+            R += (int64_t)hv[j].size();
+        }
     }
     out.rbase[P] = R;
     out.rv.reset((size_t)std::max<int64_t>(R, 1));
@@ -564,10 +572,21 @@ void build_partitioned(const int32_t *src, const int32_t *dst, bool on_device, c
     for (int j = 0; j < P; ++j) {
         const size_t n = hv[j].size();
         if (!n) continue;
-        std::memcpy(out.rv.p + out.rbase[j], hv[j].data(), n * 4);
-        std::memcpy(out.rtc.p + out.rbase[j], htc[j].data(), n * 4);
-        std::memcpy(out.rlen.p + out.rbase[j], hlen[j].data(), n * 4);
-        std::memcpy(out.rpos.p + out.rbase[j], hpos[j].data(), n * 8);
+        if (out.direct) {
+            int64_t o = out.rbase[j];
+            for (size_t r = 0; r < n; ++r)
+                for (int32_t k = 0; k < htc[j][r]; ++k, ++o) {
+                    out.rv.p[o] = hv[j][r];
+                    out.rtc.p[o] = 1;
+                    out.rlen.p[o] = hlen[j][r] - k;
+                    out.rpos.p[o] = hpos[j][r] + k;
+                }
+        } else {
+            std::memcpy(out.rv.p + out.rbase[j], hv[j].data(), n * 4);
+            std::memcpy(out.rtc.p + out.rbase[j], htc[j].data(), n * 4);
+            std::memcpy(out.rlen.p + out.rbase[j], hlen[j].data(), n * 4);
+            std::memcpy(out.rpos.p + out.rbase[j], hpos[j].data(), n * 8);
+        }
         std::vector<int32_t>().swap(hv[j]);
         std::vector<int32_t>().swap(htc[j]);
         std::vector<int32_t>().swap(hlen[j]);

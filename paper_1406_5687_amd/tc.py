@@ -23,7 +23,7 @@ COST_ONE, COST_DEGREE, COST_PRIOR, COST_NEW = range(4)
 EXPORTED = [
     "tc_options_default", "tc_build_oriented", "tc_count_total", "tc_count_per_node", "tc_count_batch",
     "tc_graph_info", "tc_export_csr", "tc_export_schedule", "tc_graph_free", "tc_status_str", "tc_last_error",
-    "tc_graph_reschedule",
+    "tc_graph_reschedule", "tc_worker_times",
 ]
 
 
@@ -66,7 +66,9 @@ class Options(ctypes.Structure):
         ("time_kernels", ctypes.c_int32),
         ("partitions", ctypes.c_int32),
         ("rounds", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("direct", ctypes.c_int32),
+        ("static_chunks", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -123,6 +125,8 @@ def load(path: str = LIB_PATH):
     lib.tc_export_csr.argtypes = [P, ctypes.POINTER(Options), P, P, P]
     lib.tc_export_schedule.argtypes = [P, ctypes.POINTER(Options), P, P, ctypes.c_int64,
                                        ctypes.POINTER(ctypes.c_int64)]
+    lib.tc_worker_times.argtypes = [P, ctypes.POINTER(Options), P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.tc_worker_times.restype = ctypes.c_int
     lib.tc_graph_free.argtypes = [P]
     lib.tc_graph_free.restype = None
     lib.tc_status_str.argtypes = [ctypes.c_int]
@@ -189,7 +193,8 @@ def _is_tensor(x) -> bool:
 
 def make_options(*, stream=None, inputs_on_device=False, outputs_on_device=False, hbm_budget_bytes=0, workers=0,
                  cost_fn=COST_PRIOR, min_chunk=0, small_max=0, lds_list_max=0, time_kernels=False,
-                 partitions=0, rounds=0, torch_allocator=True) -> Options:
+                 partitions=0, rounds=0, direct=False, static_chunks=False,
+                 torch_allocator=True) -> Options:
     global _torch_alloc
     o = Options()
     load().tc_options_default(ctypes.byref(o))
@@ -201,9 +206,11 @@ def make_options(*, stream=None, inputs_on_device=False, outputs_on_device=False
     o.min_chunk = int(min_chunk)
     o.small_max = int(small_max)
     o.lds_list_max = int(lds_list_max)
-    o.time_kernels = int(bool(time_kernels))
+    o.time_kernels = int(time_kernels)
     o.partitions = int(partitions)
     o.rounds = int(rounds)
+    o.direct = int(bool(direct))
+    o.static_chunks = int(bool(static_chunks))
     if stream is None:
         try:
             torch = _torch()
@@ -293,12 +300,27 @@ class Graph:
                                      ctypes.c_void_p(tot.ctypes.data)))
         return tv[: self.n_total], tot[: self.k]
 
-    def reschedule(self, workers=0, cost_fn=COST_PRIOR, min_chunk=0, small_max=0, rounds=0):
+    def reschedule(self, workers=0, cost_fn=COST_PRIOR, min_chunk=0, small_max=0, rounds=0, static_chunks=False):
         """New task table for the same adjacency (tc_graph_reschedule); later
         counts use it."""
-        self._kw.update(workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max, rounds=rounds)
+        self._kw.update(workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max, rounds=rounds,
+                        static_chunks=static_chunks)
         o = self._opts()
         _raise(load().tc_graph_reschedule(self._h, ctypes.byref(o)))
+
+    def worker_times(self):
+        """(start ns, stop ns, kind) of every worker of the last count made with
+        time_kernels=2, as an int64 array of shape (workers, 3); kind 0 = node-range
+        task wave, 1 / 2 = workgroup of the medium / long list tier."""
+        lib = load()
+        nw = ctypes.c_int64(0)
+        o = self._opts()
+        _raise(lib.tc_worker_times(self._h, ctypes.byref(o), None, 0, ctypes.byref(nw)))
+        out = np.zeros((max(nw.value, 1), 3), np.int64)
+        if nw.value:
+            _raise(lib.tc_worker_times(self._h, ctypes.byref(o), ctypes.c_void_p(out.ctypes.data), nw.value,
+                                       ctypes.byref(nw)))
+        return out[: nw.value]
 
     # -- inspection
     def info(self) -> dict:
@@ -349,7 +371,8 @@ class Graph:
 
 
 def build_oriented(graphs: Sequence, *, stream=None, hbm_budget_bytes=0, workers=0, cost_fn=COST_PRIOR, min_chunk=0,
-                   small_max=0, lds_list_max=0, partitions=0, rounds=0, torch_allocator=True) -> Graph:
+                   small_max=0, lds_list_max=0, partitions=0, rounds=0, direct=False, static_chunks=False,
+                   torch_allocator=True) -> Graph:
     """Builds one handle from graphs given as (n, src, dst) triples.  src/dst are
     numpy arrays (host) or torch tensors (all on the device, or all host)."""
     if not len(graphs):
@@ -368,7 +391,7 @@ def build_oriented(graphs: Sequence, *, stream=None, hbm_budget_bytes=0, workers
         ns.append(int(n))
     kw = dict(stream=stream, hbm_budget_bytes=hbm_budget_bytes, workers=workers, cost_fn=cost_fn,
               min_chunk=min_chunk, small_max=small_max, lds_list_max=lds_list_max, partitions=partitions,
-              rounds=rounds, torch_allocator=torch_allocator)
+              rounds=rounds, direct=direct, static_chunks=static_chunks, torch_allocator=torch_allocator)
     o = make_options(inputs_on_device=on_dev, **kw)
     h = ctypes.c_void_p(0)
     _raise(load().tc_build_oriented(arr, len(graphs), ctypes.byref(o), ctypes.byref(h)))

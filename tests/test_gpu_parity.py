@@ -200,6 +200,30 @@ def test_schedule_rounds_matches_oracle(tc):
     np.testing.assert_array_equal(bnd, bnd_ref)
 
 
+def test_static_chunks_schedule(tc):
+    # comparison schedule: W tasks of equal cost (boundary i at the first node
+    # whose cost prefix reaches ceil(i * total / W))
+    g = graphgen.preferential_attachment(20_000, 8, 13)
+    m, off_o, col_o, deg = oracle.orient(g.n, g.src, g.dst)
+    perm = oracle.degree_order(deg)
+    f = oracle.costs(off_o, col_o, deg, oracle.COST_PRIOR)[perm].copy()
+    f[np.diff(off_o)[perm] > 128] = 0
+    F = np.concatenate([[0], np.cumsum(f)])
+    total = int(F[-1])
+    W = 50
+    expect = [0] + [int(np.searchsorted(F, -(-(i * total) // W), side="left")) for i in range(1, W)] + [g.n]
+    with tc.build_oriented([(g.n, g.src, g.dst)], workers=W, static_chunks=True) as h:
+        bnd, _ = h.export_schedule()
+        tv, tot = h.count_per_node(time_kernels=2)
+        times = h.worker_times()
+    np.testing.assert_array_equal(bnd, expect)
+    T_ref, tv_ref, _ = oracle.count(g.n, g.src, g.dst)
+    assert tot[0] == T_ref
+    np.testing.assert_array_equal(tv, tv_ref)
+    assert times.shape[0] >= 1 and (times[:, 0] >= 0).all() and (times[:, 1] >= times[:, 0]).all()
+    assert set(times[:, 2].tolist()) <= {0, 1, 2} and (times[:, 2] == 0).any()
+
+
 # ------------------------------------------------------------ invariance (Section V-D)
 
 @pytest.mark.parametrize("kw", [

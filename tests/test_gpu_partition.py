@@ -181,3 +181,19 @@ def test_partitioned_batch_form_rejects_several_graphs(tc):
     a = graphgen.rmat(8, 8, seed=1)
     with pytest.raises(tc.tc.InvalidArgument):
         tc.build_oriented([(a.n, a.src, a.dst), (a.n, a.src, a.dst)], partitions=2)
+
+
+@pytest.mark.parametrize("P", [2, 5])
+def test_direct_scheme_equals_surrogate(tc, P):
+    # one streamed range per stored edge instead of one per slice: same counts,
+    # more bytes over the host link
+    g = graphgen.chung_lu(4000, 40000, 2.1, 9)
+    T_ref, tv_ref, _ = oracle.count(g.n, g.src, g.dst)
+    got = {}
+    for direct in (False, True):
+        with tc.build_oriented([(g.n, g.src, g.dst)], partitions=P, direct=direct) as h:
+            T, tv = counts(h)
+            got[direct] = h.info()["streamed_bytes"]
+        assert T == T_ref
+        np.testing.assert_array_equal(tv, tv_ref)
+    assert got[True] > got[False]
