@@ -53,6 +53,8 @@ def _load():
     lib.orc_count_oriented.argtypes = [ctypes.c_int32, _I64P, _I32P, _I64P, _I64P]
     lib.orc_count.argtypes = [ctypes.c_int32, ctypes.c_int64, _I32P, _I32P, _I64P, _I64P, _I64P]
     lib.orc_degree_order.argtypes = [ctypes.c_int32, _I32P, _I32P]
+    _DP = ctypes.POINTER(ctypes.c_double)
+    lib.orc_clustering.argtypes = [ctypes.c_int32, ctypes.c_int64, _I32P, _I32P, _DP, _DP, _I64P]
     lib.orc_costs.argtypes = [ctypes.c_int32, _I64P, _I32P, _I32P, ctypes.c_int, _I64P]
     lib.orc_schedule.argtypes = [ctypes.c_int32, _I64P, ctypes.c_int32, ctypes.c_int64, _I32P, ctypes.c_int64,
                                  _I64P]
@@ -96,6 +98,20 @@ def count(n: int, src, dst, per_node: bool = True):
     Tv = np.zeros(max(n, 1), np.int64) if per_node else None
     _rc(lib.orc_count(n, s.shape[0], _p32(s), _p32(d), _p64(T), _p64(Tv) if per_node else None, _p64(m)), "count")
     return int(T[0]), (Tv[:n] if per_node else None), int(m[0])
+
+
+def clustering(n: int, src, dst):
+    """Local clustering coefficients T_v / C(d_v, 2) and the transitivity
+    3T / sum C(d_v, 2) (Section I applications, textbook definitions), fp64.
+    Returns (coeff[n], transitivity, paths of length two)."""
+    lib = _load()
+    s, d = _i32(src), _i32(dst)
+    coeff = np.zeros(max(n, 1), np.float64)
+    tr = np.zeros(1, np.float64)
+    w = np.zeros(1, np.int64)
+    _rc(lib.orc_clustering(n, s.shape[0], _p32(s), _p32(d), coeff.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           tr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _p64(w)), "clustering")
+    return coeff[:n], float(tr[0]), int(w[0])
 
 
 def orient(n: int, src, dst):

@@ -190,6 +190,47 @@ int orc_count(int32_t n, int64_t m_in, const int32_t *src, const int32_t *dst, i
     return rc;
 }
 
+/* Clustering coefficients, the applications named in Section I, by their
+ * textbook definitions over the canonical simple graph: the local coefficient
+ * of v is T_v divided by the number of pairs of its neighbours, C(d_v, 2)
+ * (0 when d_v < 2); the transitivity is 3T divided by the number of paths of
+ * length two, sum over v of C(d_v, 2) (0 when there is none).  Each is one
+ * floating-point division of two exact integers. */
+int orc_clustering(int32_t n, int64_t m_in, const int32_t *src, const int32_t *dst, double *coeff, double *trans,
+                   int64_t *wedges_out) {
+    if (n < 0 || m_in < 0 || !trans) return ORC_EINVAL;
+    int64_t *off = (int64_t *)malloc((size_t)(n + 1) * sizeof(int64_t));
+    int32_t *col = (int32_t *)malloc((size_t)(m_in > 0 ? m_in : 1) * sizeof(int32_t));
+    int32_t *deg = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int64_t *Tv = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    if (!off || !col || !deg || !Tv) {
+        free(off);
+        free(col);
+        free(deg);
+        free(Tv);
+        return ORC_ENOMEM;
+    }
+    int64_t m = 0, T = 0;
+    int rc = orc_orient(n, m_in, src, dst, &m, off, col, deg);
+    if (!rc) rc = orc_count_oriented(n, off, col, &T, Tv);
+    if (!rc) {
+        int64_t W = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            const int64_t d = deg[v];
+            const int64_t pairs = d * (d - 1) / 2;
+            W += pairs;
+            if (coeff) coeff[v] = pairs > 0 ? (double)Tv[v] / (double)pairs : 0.0;
+        }
+        *trans = W > 0 ? (double)(3 * T) / (double)W : 0.0;
+        if (wedges_out) *wedges_out = W;
+    }
+    free(off);
+    free(col);
+    free(deg);
+    free(Tv);
+    return rc;
+}
+
 /* The degree order written out as a sequence: perm[r] is the node in place r
  * when all nodes are listed from first to last under the order of Section
  * III-A (a stable sort by degree of the id-ordered list). */

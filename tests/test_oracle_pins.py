@@ -398,3 +398,53 @@ def test_er_expected_count_band():
     N = g.n * (g.n - 1) // 2
     ET = math.comb(g.n, 3) * m * (m - 1) * (m - 2) / (N * (N - 1) * (N - 2))
     assert abs(T - ET) < 6 * math.sqrt(ET)
+
+
+# ------------------------------------------------------------ clustering coefficients (Section I applications)
+
+@pytest.mark.parametrize("n", [3, 4, 7, 20])
+def test_clustering_complete(n):
+    coeff, tr, w = oracle.clustering(*gs.complete(n))
+    assert (coeff == 1.0).all() and tr == 1.0 and w == n * math.comb(n - 1, 2)
+
+
+@pytest.mark.parametrize("g", [gs.complete_bipartite(3, 5), gs.grid(6, 7), gs.cycle(10), gs.star(9)])
+def test_clustering_triangle_free(g):
+    coeff, tr, w = oracle.clustering(*g)
+    assert not coeff.any() and tr == 0.0 and w > 0
+
+
+@pytest.mark.parametrize("n", [5, 8, 31])
+def test_clustering_wheel(n):
+    # hub: n-1 triangles over C(n-1, 2) pairs; rim: 2 triangles over 3 pairs
+    coeff, tr, w = oracle.clustering(*gs.wheel(n))
+    assert coeff[0] == (n - 1) / math.comb(n - 1, 2)
+    assert (coeff[1:] == 2 / 3).all()
+    assert w == math.comb(n - 1, 2) + 3 * (n - 1)
+    assert tr == 3 * (n - 1) / w
+
+
+@pytest.mark.parametrize("k", [1, 2, 6])
+def test_clustering_friendship(k):
+    coeff, tr, w = oracle.clustering(*gs.friendship(k))
+    assert coeff[0] == 1 / (2 * k - 1) and (coeff[1:] == 1.0).all()
+    assert tr == 3 * k / (math.comb(2 * k, 2) + 2 * k)
+
+
+def test_clustering_isolated_and_empty():
+    coeff, tr, w = oracle.clustering(5, np.zeros(0, np.int32), np.zeros(0, np.int32))
+    assert coeff.shape == (5,) and not coeff.any() and tr == 0.0 and w == 0
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_clustering_networkx(seed):
+    nx = pytest.importorskip("networkx")
+    rng = np.random.default_rng(seed)
+    n, s, d = gs.gnp(120, 0.15, rng)
+    coeff, tr, _ = oracle.clustering(n, s, d)
+    G = nx.Graph()
+    G.add_nodes_from(range(n))
+    G.add_edges_from(zip(s.tolist(), d.tolist()))
+    ref = nx.clustering(G)
+    np.testing.assert_allclose(coeff, [ref[v] for v in range(n)], rtol=1e-13, atol=0)
+    assert abs(tr - nx.transitivity(G)) <= 1e-13 * max(tr, 1e-300)
