@@ -152,6 +152,16 @@ tc_status tc_count_per_node(tc_graph *g, const tc_options *opt, int64_t *per_nod
 tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, int64_t *totals,
                          int64_t *const *per_node);
 
+/* Clustering coefficients from the per-node counts (Section I names them as
+ * applications; textbook definitions): coeff[v] = T_v / C(d_v, 2), 0 when
+ * d_v < 2, in the caller's labels, packed graph after graph (sum of n_i
+ * entries); transitivity[g] = 3 T_g / (sum over v of C(d_v, 2)), 0 when graph g
+ * has no path of length two (k entries).  Each value is one fp64 division of
+ * two exact integers.  coeff, transitivity and totals (k triangle counts) may
+ * each be NULL; host or device per opt->outputs_on_device.  Resident handles
+ * only (TC_ERR_INVALID_ARG for a partitioned one). */
+tc_status tc_clustering(tc_graph *g, const tc_options *opt, double *coeff, double *transitivity, int64_t *totals);
+
 typedef struct {
     int32_t k;              /* graphs in the handle */
     int64_t n;              /* sum of node counts */

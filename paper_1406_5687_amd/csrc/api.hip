@@ -540,6 +540,46 @@ tc_status tc_export_schedule(const tc_graph *g, const tc_options *opt, int32_t *
     });
 }
 
+tc_status tc_clustering(tc_graph *g, const tc_options *opt, double *coeff, double *transitivity, int64_t *totals) {
+    if (!g) return fail(TC_ERR_INVALID_ARG, "graph must be non-NULL");
+    if (g->part) return fail(TC_ERR_INVALID_ARG, "clustering needs a resident handle");
+    const int64_t N = g->pk.N;
+    const int k = g->pk.k;
+    return guarded([&] {
+        check_options(opt);
+        const bool on_dev = opt && opt->outputs_on_device;
+        hipStream_t s = opt ? (hipStream_t)opt->stream : nullptr;
+        // per-node counts into the handle's accumulators (degree-order labels)
+        tc::DevBuf<int64_t> caller_tv(g->al, (size_t)std::max<int64_t>(N, 1));
+        tc_options o;
+        if (opt)
+            o = *opt;
+        else
+            tc_options_default(&o);
+        o.outputs_on_device = 1;
+        const tc_status st = N > 0 ? count_one(g, &o, caller_tv.p, nullptr) : count_one(g, &o, nullptr, nullptr);
+        if (st != TC_OK) throw tc::Error(st, g_last_error);
+        tc::DevBuf<unsigned long long> wedges(g->al, (size_t)std::max(k, 1));
+        tc::DevBuf<double> dcoeff, dtrans;
+        double *c = coeff, *t = transitivity;
+        if (!on_dev) {
+            if (coeff && N > 0) dcoeff = tc::DevBuf<double>(g->al, (size_t)N);
+            if (transitivity) dtrans = tc::DevBuf<double>(g->al, (size_t)k);
+            c = coeff ? dcoeff.p : nullptr;
+            t = transitivity ? dtrans.p : nullptr;
+        }
+        if (N > 0 || t)
+            tc::clustering_epilogue(g->tv.p, g->o.deg.p, g->o.perm.p, N, g->o.node_base.p, k, g->totals.p,
+                                    N > 0 ? c : nullptr, t, wedges.p, s);
+        if (!on_dev) {
+            if (coeff && N > 0) copy_out(coeff, dcoeff.p, (size_t)N * 8, false, s);
+            if (transitivity) copy_out(transitivity, dtrans.p, (size_t)k * 8, false, s);
+        }
+        if (totals) copy_out(totals, g->totals.p, (size_t)k * 8, on_dev, s);
+        if (!on_dev) TC_HIP(hipStreamSynchronize(s));
+    });
+}
+
 tc_status tc_worker_times(const tc_graph *g, const tc_options *opt, int64_t *times, int64_t cap,
                           int64_t *nworkers) {
     if (!g || !nworkers) return fail(TC_ERR_INVALID_ARG, "graph and nworkers must be non-NULL");

@@ -638,6 +638,44 @@ __global__ void k_scatter(const int64_t *__restrict__ tv, const int32_t *__restr
         out[perm[i]] = tv[i];
 }
 
+// Clustering coefficients from the per-node counts: coeff[perm[i]] =
+// tv[i] / C(deg[i], 2) (0 below two neighbours) and, per graph, the number of
+// paths of length two, sum of C(deg, 2), added into wedges (one atomic per run
+// of equal graphs in a wave).
+__global__ void k_clustering(const int64_t *__restrict__ tv, const int32_t *__restrict__ deg,
+                             const int32_t *__restrict__ perm, int64_t N, const int64_t *__restrict__ node_base,
+                             int k, double *__restrict__ coeff, unsigned long long *__restrict__ wedges) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < N; b0 += stride) {
+        const int64_t i = b0 + threadIdx.x;
+        int64_t pairs = 0;
+        int g = -1;
+        if (i < N) {
+            const int64_t d = deg[i];
+            pairs = d * (d - 1) / 2;
+            if (coeff) coeff[perm[i]] = pairs > 0 ? (double)tv[i] / (double)pairs : 0.0;
+            g = graph_of(node_base, k, i);
+        }
+        // sum pairs over lanes of the same graph (graphs are label ranges)
+        uint64_t sum = (uint64_t)pairs;
+#pragma unroll
+        for (int dlt = 1; dlt < 64; dlt <<= 1) {
+            const uint64_t y = __shfl_up(sum, dlt, 64);
+            const int gy = __shfl_up(g, dlt, 64);
+            if (__lane_id() >= dlt && gy == g) sum += y;
+        }
+        const int gn = __shfl_down(g, 1, 64);
+        const bool end = __lane_id() == 63 || gn != g;
+        if (i < N && end && sum) atomicAdd(&wedges[g], (unsigned long long)sum);
+    }
+}
+
+__global__ void k_transitivity(const int64_t *__restrict__ totals, const unsigned long long *__restrict__ wedges,
+                               int k, double *__restrict__ trans) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < k; g += gridDim.x * blockDim.x)
+        trans[g] = wedges[g] ? (double)(3 * totals[g]) / (double)wedges[g] : 0.0;
+}
+
 template <bool PER_NODE, bool IDX32, bool SLICE>
 void launch_all(CountLaunch &L, int lds_max, hipStream_t s) {
     const int cus = device_cu_count();
@@ -750,6 +788,21 @@ void count_launch(CountLaunch &L, hipStream_t s) {
             launch_all<false, true, false>(L, lds_max, s);
         else
             launch_all<false, false, false>(L, lds_max, s);
+    }
+}
+
+void clustering_epilogue(const int64_t *tv, const int32_t *deg, const int32_t *perm, int64_t N,
+                         const int64_t *node_base, int k, const int64_t *totals, double *coeff, double *trans,
+                         unsigned long long *wedges, hipStream_t s) {
+    fill_zero(wedges, (size_t)std::max(k, 1) * 8, s);
+    if (N > 0) {
+        const int64_t b = std::min<int64_t>(ceil_div(N, 256 * 4), 1 << 20);
+        k_clustering<<<(unsigned)b, 256, 0, s>>>(tv, deg, perm, N, node_base, k, coeff, wedges);
+        TC_LAUNCH_CHECK();
+    }
+    if (trans) {
+        k_transitivity<<<(unsigned)ceil_div(std::max(k, 1), 256), 256, 0, s>>>(totals, wedges, k, trans);
+        TC_LAUNCH_CHECK();
     }
 }
 

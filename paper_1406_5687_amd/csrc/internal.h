@@ -194,6 +194,12 @@ struct CountLaunch {
 void count_launch(CountLaunch &L, hipStream_t s);
 int64_t max_timed_workers();  // upper bound on the workers of one count_launch
 
+// coeff[perm[i]] = tv[i] / C(deg[i], 2); trans[g] = 3 totals[g] / (sum of C(deg, 2)
+// over graph g); wedges: k scratch words.  coeff or trans may be NULL.
+void clustering_epilogue(const int64_t *tv, const int32_t *deg, const int32_t *perm, int64_t N,
+                         const int64_t *node_base, int k, const int64_t *totals, double *coeff, double *trans,
+                         unsigned long long *wedges, hipStream_t s);
+
 // out[perm[i]] = tv[i] for i < n
 void scatter_per_node(const int64_t *tv, const int32_t *perm, int64_t n, int64_t *out, hipStream_t s);
 

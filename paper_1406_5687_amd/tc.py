@@ -23,7 +23,7 @@ COST_ONE, COST_DEGREE, COST_PRIOR, COST_NEW = range(4)
 EXPORTED = [
     "tc_options_default", "tc_build_oriented", "tc_count_total", "tc_count_per_node", "tc_count_batch",
     "tc_graph_info", "tc_export_csr", "tc_export_schedule", "tc_graph_free", "tc_status_str", "tc_last_error",
-    "tc_graph_reschedule", "tc_worker_times",
+    "tc_graph_reschedule", "tc_worker_times", "tc_clustering",
 ]
 
 
@@ -127,6 +127,8 @@ def load(path: str = LIB_PATH):
                                        ctypes.POINTER(ctypes.c_int64)]
     lib.tc_worker_times.argtypes = [P, ctypes.POINTER(Options), P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.tc_worker_times.restype = ctypes.c_int
+    lib.tc_clustering.argtypes = [P, ctypes.POINTER(Options), P, P, P]
+    lib.tc_clustering.restype = ctypes.c_int
     lib.tc_graph_free.argtypes = [P]
     lib.tc_graph_free.restype = None
     lib.tc_status_str.argtypes = [ctypes.c_int]
@@ -307,6 +309,24 @@ class Graph:
                         static_chunks=static_chunks)
         o = self._opts()
         _raise(load().tc_graph_reschedule(self._h, ctypes.byref(o)))
+
+    def clustering(self, coeff=None, transitivity=None, totals=None, **over):
+        """Local clustering coefficients (caller labels) and the transitivity
+        of each graph, fp64 (tc_clustering).  Host numpy by default; with device
+        tensors given, written asynchronously."""
+        lib = load()
+        if coeff is not None or transitivity is not None:
+            o = self._opts(outputs_on_device=True, **over)
+            ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+            _raise(lib.tc_clustering(self._h, ctypes.byref(o), ptr(coeff), ptr(transitivity), ptr(totals)))
+            return coeff, transitivity, totals
+        c = np.zeros(max(self.n_total, 1), np.float64)
+        t = np.zeros(max(self.k, 1), np.float64)
+        tot = np.zeros(max(self.k, 1), np.int64)
+        o = self._opts(outputs_on_device=False, **over)
+        _raise(lib.tc_clustering(self._h, ctypes.byref(o), ctypes.c_void_p(c.ctypes.data),
+                                 ctypes.c_void_p(t.ctypes.data), ctypes.c_void_p(tot.ctypes.data)))
+        return c[: self.n_total], t[: self.k], tot[: self.k]
 
     def worker_times(self):
         """(start ns, stop ns, kind) of every worker of the last count made with

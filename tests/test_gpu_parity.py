@@ -336,3 +336,38 @@ def test_full_pa_config(tc):
         assert h.info()["m"] == m
     assert int(tot.item()) == T_ref
     np.testing.assert_array_equal(out.cpu().numpy(), tv_ref)
+
+
+# ------------------------------------------------------------ clustering epilogue (Section I applications)
+
+@pytest.mark.parametrize("maker", [
+    lambda: graphgen.workload_er(1),
+    lambda: graphgen.rmat(13, 16, seed=3),
+    lambda: graphgen.preferential_attachment(20_000, 12, 5),
+    lambda: gs.wheel(50),
+    lambda: gs.complete(40),
+    lambda: gs.grid(20, 30),
+], ids=["er", "rmat13", "pa20k", "wheel", "k40", "grid"])
+def test_clustering_matches_oracle(tc, maker):
+    g = maker()
+    n, s, d = (g.n, g.src, g.dst) if hasattr(g, "src") else g
+    coeff_ref, tr_ref, _ = oracle.clustering(n, s, d)
+    T_ref, _, _ = oracle.count(n, s, d, per_node=False)
+    with tc.build_oriented([(n, s, d)]) as h:
+        coeff, tr, tot = h.clustering()
+    # one fp64 division of the same two integers on both sides: bit-exact
+    np.testing.assert_array_equal(coeff, coeff_ref)
+    assert tr[0] == tr_ref and tot[0] == T_ref
+
+
+def test_clustering_packed_graphs(tc):
+    parts = [graphgen.rmat(10, 16, seed=1), graphgen.EdgeList(3, np.zeros(0, np.int32), np.zeros(0, np.int32)),
+             graphgen.erdos_renyi(800, 6000, 2), graphgen.chung_lu(2000, 30000, 2.1, 4)]
+    with tc.build_oriented([(p.n, p.src, p.dst) for p in parts]) as h:
+        coeff, tr, tot = h.clustering()
+    b = 0
+    for i, p in enumerate(parts):
+        c_ref, t_ref, _ = oracle.clustering(p.n, p.src, p.dst)
+        np.testing.assert_array_equal(coeff[b:b + p.n], c_ref)
+        assert tr[i] == t_ref
+        b += p.n
