@@ -31,11 +31,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K *__restrict
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t tile = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
+    // all of the lane's keys are loaded before any is ranked
+    K kk[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+        const int64_t i = key_index(tile, wave, r, lane);
+        kk[r] = i < n ? keys[i] : (K)0;
+    }
+#pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         const int64_t i = key_index(tile, wave, r, lane);
         uint32_t d = 256u;  // inactive
-        if (i < n) d = (uint32_t)(keys[i] >> shift) & 0xffu;
+        if (i < n) d = (uint32_t)(kk[r] >> shift) & 0xffu;
         const uint64_t peers = match_peers9(d);
         const int leader = __ffsll((unsigned long long)peers) - 1;
         if (d < 256u && leader == lane) atomicAdd(&h[d], (uint32_t)popc64(peers));
