@@ -10,8 +10,9 @@
 //   3. degree order        -- sort (g, d_x, v): position r in the sorted list is the
 //                             new label of x (Section III-A order, ties by id)
 //   4. orientation         -- edge {a, b} stored at the lower label s as (s, t);
-//                             radix sort of (s << GB) | t gives rows sorted ascending
-//   5. CSR                 -- col = t, off = exclusive scan of row lengths
+//                             a stable radix sort of (s << GB) | t by s groups the rows
+//   5. CSR                 -- col = t, off = exclusive scan of row lengths; each row
+//                             then sorted ascending on its own
 //   6. costs and tasks     -- f per node (Sections IV-B, IV-F, V-A), prefix sums,
 //                             Eq. (1)/(2) targets, one binary search per task boundary
 #include <algorithm>
@@ -242,6 +243,148 @@ __global__ void k_csr_rows(const uint64_t *__restrict__ okeys, int64_t m, int gb
         bool end;
         const int32_t cnt = run_sum_at_end<int32_t>(s, i < m ? 1 : 0, &end);
         if (i < m && end) atomicAdd(&rowlen[s], cnt);
+    }
+}
+
+// Step 5b: rows sorted ascending.  The pair sort above orders by s only, so
+// each row holds its entries in input order.  A wave takes 64 consecutive
+// rows: rows of up to 8 entries are sorted by their own lane with a sorting
+// network in registers; rows of up to 64 entries (one per lane) and up to 256
+// entries (four per lane, element i = 4 lane + j) are sorted one after another
+// by the whole wave with a bitonic network; longer rows are listed for one
+// radix sort of (row, t) keys.
+constexpr int kTinyRow = 8;
+constexpr int kShortRow = 64;
+constexpr int kMidRow = 256;
+
+__device__ __forceinline__ void cswap(int32_t &a, int32_t &b) {
+    const int32_t lo = min(a, b), hi = max(a, b);
+    a = lo;
+    b = hi;
+}
+
+__device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col, int64_t r0, int32_t a, int lane) {
+    if (a <= kShortRow) {
+        int32_t x = lane < a ? col[r0 + lane] : INT32_MAX;
+#pragma unroll
+        for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+            for (int d = k >> 1; d > 0; d >>= 1) {
+                const int32_t y = __shfl_xor(x, d, 64);
+                const bool up = (lane & k) == 0, lower = (lane & d) == 0;
+                x = (lower == up) ? min(x, y) : max(x, y);
+            }
+        }
+        if (lane < a) col[r0 + lane] = x;
+        return;
+    }
+    int32_t v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int i = lane * 4 + j;
+        v[j] = i < a ? col[r0 + i] : INT32_MAX;
+    }
+#pragma unroll
+    for (int k = 2; k <= kMidRow; k <<= 1) {
+#pragma unroll
+        for (int d = k >> 1; d > 0; d >>= 1) {
+            if (d >= 4) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int i = lane * 4 + j;
+                    const int32_t y = __shfl_xor(v[j], d >> 2, 64);
+                    const bool up = (i & k) == 0, lower = (i & d) == 0;
+                    v[j] = (lower == up) ? min(v[j], y) : max(v[j], y);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (j & d) continue;
+                    const int p = j | d;
+                    const bool up = ((lane * 4 + j) & k) == 0;
+                    const int32_t lo = min(v[j], v[p]), hi = max(v[j], v[p]);
+                    v[j] = up ? lo : hi;
+                    v[p] = up ? hi : lo;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int i = lane * 4 + j;
+        if (i < a) col[r0 + i] = v[j];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sort_rows(const int64_t *__restrict__ off, int64_t N,
+                                                        int32_t *__restrict__ col, int32_t *__restrict__ long_rows,
+                                                        unsigned int *__restrict__ nlong) {
+    const int lane = __lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t g0 = wave * 64; g0 < N; g0 += nwaves * 64) {
+        const int64_t r = g0 + lane;
+        int64_t r0 = 0;
+        int32_t a = 0;
+        if (r < N) {
+            r0 = off[r];
+            a = (int32_t)(off[r + 1] - r0);
+        }
+        if (a >= 2 && a <= kTinyRow) {
+            // optimal 19-comparator network for 8 inputs; padding sorts last
+            int32_t x[kTinyRow];
+#pragma unroll
+            for (int j = 0; j < kTinyRow; ++j) x[j] = j < a ? col[r0 + j] : INT32_MAX;
+            cswap(x[0], x[2]); cswap(x[1], x[3]); cswap(x[4], x[6]); cswap(x[5], x[7]);
+            cswap(x[0], x[4]); cswap(x[1], x[5]); cswap(x[2], x[6]); cswap(x[3], x[7]);
+            cswap(x[0], x[1]); cswap(x[2], x[3]); cswap(x[4], x[5]); cswap(x[6], x[7]);
+            cswap(x[2], x[4]); cswap(x[3], x[5]);
+            cswap(x[1], x[4]); cswap(x[3], x[6]);
+            cswap(x[1], x[2]); cswap(x[3], x[4]); cswap(x[5], x[6]);
+#pragma unroll
+            for (int j = 0; j < kTinyRow; ++j)
+                if (j < a) col[r0 + j] = x[j];
+        }
+        uint64_t rest = __ballot(a > kTinyRow && a <= kMidRow);
+        while (rest) {
+            const int l = __ffsll((unsigned long long)rest) - 1;
+            rest &= rest - 1;
+            wave_sort_row(col, readlane64(r0, l), readlane32(a, l), lane);
+        }
+        if (a > kMidRow) long_rows[atomicAdd(nlong, 1u)] = (int32_t)r;
+    }
+}
+
+__global__ void k_long_lengths(const int64_t *__restrict__ off, const int32_t *__restrict__ long_rows, int64_t L,
+                               int64_t *__restrict__ len) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = long_rows[i];
+        len[i] = off[r + 1] - off[r];
+    }
+}
+
+// keys (i << gb) | t of the entries of long row i, from epos[i] on (one wave per row)
+__global__ void k_long_keys(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                            const int32_t *__restrict__ long_rows, const int64_t *__restrict__ epos, int64_t L, int gb,
+                            uint64_t *__restrict__ keys) {
+    const int lane = __lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = wave; i < L; i += nwaves) {
+        const int32_t r = long_rows[i];
+        const int64_t r0 = off[r], a = off[r + 1] - r0, e = epos[i];
+        for (int64_t p = lane; p < a; p += 64) keys[e + p] = ((uint64_t)i << gb) | (uint64_t)(uint32_t)col[r0 + p];
+    }
+}
+
+__global__ void k_long_write(const uint64_t *__restrict__ keys, int64_t E, int gb, const int64_t *__restrict__ off,
+                             const int32_t *__restrict__ long_rows, const int64_t *__restrict__ epos,
+                             int32_t *__restrict__ col) {
+    const uint64_t mask = (1ull << gb) - 1;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < E; q += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[q];
+        const int64_t i = (int64_t)(k >> gb);
+        col[off[long_rows[i]] + (q - epos[i])] = (int32_t)(k & mask);
     }
 }
 
@@ -477,6 +620,37 @@ struct PinnedStage {
 thread_local PinnedStage t_stage;
 }  // namespace
 
+// Sorts every row of (off, col) ascending.  ka / kb: scratch of cap keys each.
+void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka, uint64_t *kb, int64_t cap,
+               Allocator &tmp, hipStream_t s) {
+    if (N <= 0) return;
+    DevBuf<int32_t> long_rows(tmp, (size_t)N);
+    DevBuf<unsigned int> nlong(tmp, 1);
+    fill_zero(nlong.p, 4, s);
+    const int64_t waves = std::min<int64_t>(ceil_div(N, 64), (int64_t)device_cu_count() * 64);
+    k_sort_rows<<<(unsigned)ceil_div(waves * 64, kThreads), kThreads, 0, s>>>(off, N, col, long_rows.p, nlong.p);
+    TC_LAUNCH_CHECK();
+    unsigned int L = 0;
+    d2h(&L, nlong.p, 1, s);
+    TC_HIP(hipStreamSynchronize(s));
+    if (L == 0) return;
+    DevBuf<int64_t> len(tmp, L), epos(tmp, (size_t)L + 1);
+    k_long_lengths<<<grid_for(L), kThreads, 0, s>>>(off, long_rows.p, L, len.p);
+    TC_LAUNCH_CHECK();
+    exclusive_scan(len.p, epos.p, L, true, tmp, s);
+    int64_t E = 0;
+    d2h(&E, epos.p + L, 1, s);
+    TC_HIP(hipStreamSynchronize(s));
+    if (E > cap) throw Error(TC_ERR_DEVICE, "long-row scratch smaller than the long rows");
+    const int64_t lw = std::min<int64_t>(L, (int64_t)device_cu_count() * 64);
+    k_long_keys<<<(unsigned)ceil_div(lw * 64, kThreads), kThreads, 0, s>>>(off, col, long_rows.p, epos.p, L, gb, ka);
+    TC_LAUNCH_CHECK();
+    const int lb = std::max(1, bits_for((uint64_t)(L - 1)));
+    uint64_t *sorted = radix_sort_u64(ka, kb, E, 0, gb + lb, tmp, s);
+    k_long_write<<<grid_for(E, 4), kThreads, 0, s>>>(sorted, E, gb, off, long_rows.p, epos.p, col);
+    TC_LAUNCH_CHECK();
+}
+
 void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp, Allocator &al,
                 Allocator &tmp, hipStream_t s, Oriented &out);
 void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
@@ -556,7 +730,8 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     if (M > 0) {
         k_orient_keys<<<grid_for(M, 4), kThreads, 0, s>>>(ukeys, M, gb, rank.p, spare);
         TC_LAUNCH_CHECK();
-        okeys = radix_sort_u64(spare, ukeys, M, 0, 2 * gb, tmp, s);
+        // rows by s only (stable): each row keeps input order and is sorted below
+        okeys = radix_sort_u64(spare, ukeys, M, gb, 2 * gb, tmp, s);
         k_csr_rows<<<grid_for(M, 4), kThreads, 0, s>>>(okeys, M, gb, out.col.p, rowlen.p);
         TC_LAUNCH_CHECK();
     }
@@ -569,6 +744,7 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
         TC_LAUNCH_CHECK();
     }
     schedule_into(pk, bp, al, tmp, s, out, okeys, gb);
+    if (M > 0) sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, tmp, s);
 }
 
 // Step 6 proper.  okeys (sorted pair keys) speed up the edge costs when the
