@@ -1,7 +1,10 @@
-"""Autotuner for the task schedule: picks the wave/workgroup list threshold,
-the task floor of Eq. (2) and the cost function for a built handle by timing
-the counting kernels on the data itself, and caches the choice per device and
-graph shape in a JSON file.
+"""Autotuner for the task schedule: picks the rounds of Eq. (1) (how many tasks
+the first half of the cost is cut into per worker), the wave/workgroup list
+threshold, the task floor of Eq. (2) and the cost function for a built handle
+by timing the counting kernels on the data itself, and caches the choice per
+device and graph shape in a JSON file.  The search has two stages: rounds with
+the other parameters at their defaults, then the other parameters with the
+best rounds.
 
 Counts do not depend on any of these choices (Section V-D: any task split
 counts every triangle once); only the time does.  The search reschedules the
@@ -26,17 +29,22 @@ class Params:
     small_max: int = 128      # lists up to this length: one wave; longer: one workgroup
     floor_div: int = 128      # min_chunk = total_cost / (workers * floor_div)
     cost_fn: int = tc.COST_PRIOR
+    rounds: int = 0           # Eq. (1) with W = workers * rounds; 0 = the library's choice
 
     def min_chunk(self, total_cost: int, workers: int) -> int:
         return max(256, total_cost // (workers * self.floor_div + 1))
 
 
-def candidates() -> list:
+ROUNDS = (0, 1, 4, 16, 64)
+
+
+def candidates(rounds: int = 0) -> list:
+    """Second-stage grid (threshold, floor, cost function) at the given rounds."""
     out = []
     for cost_fn in (tc.COST_PRIOR, tc.COST_DEGREE):
         for small_max in (32, 64, 128):
             for floor_div in (16, 64, 128, 512):
-                out.append(Params(small_max, floor_div, cost_fn))
+                out.append(Params(small_max, floor_div, cost_fn, rounds))
     return out
 
 
@@ -86,7 +94,8 @@ class Autotuner:
                  space: Optional[Iterable[Params]] = None):
         self.cache_path = cache_path
         self.measure = measure or kernel_time
-        self.space = list(space) if space is not None else candidates()
+        # a fixed space replaces the two-stage search
+        self.space = list(space) if space is not None else None
         self.cache = {}
         if cache_path and os.path.exists(cache_path):
             try:
@@ -101,7 +110,8 @@ class Autotuner:
     def _apply(self, graph, p: Params):
         info = graph.info()
         graph.reschedule(workers=info["workers"], cost_fn=p.cost_fn,
-                         min_chunk=p.min_chunk(info["total_cost"], info["workers"]), small_max=p.small_max)
+                         min_chunk=p.min_chunk(info["total_cost"], info["workers"]), small_max=p.small_max,
+                         rounds=p.rounds)
 
     def tune(self, graph, per_node: bool = False, force: bool = False) -> Params:
         """Returns the chosen parameters and leaves the handle scheduled with them."""
@@ -112,12 +122,21 @@ class Autotuner:
             self._apply(graph, p)
             return p
         best, best_t, trials = None, float("inf"), []
-        for p in self.space:
-            self._apply(graph, p)
-            t = self.measure(graph, per_node)
-            trials.append((asdict(p), t))
-            if t < best_t:
-                best, best_t = p, t
+
+        def run(space):
+            nonlocal best, best_t
+            for p in space:
+                self._apply(graph, p)
+                t = self.measure(graph, per_node)
+                trials.append((asdict(p), t))
+                if t < best_t:
+                    best, best_t = p, t
+
+        if self.space is not None:
+            run(self.space)
+        else:
+            run([Params(rounds=r) for r in ROUNDS])
+            run([p for p in candidates(best.rounds) if p != best])
         self._apply(graph, best)
         self.cache[key] = {"params": asdict(best), "ms": best_t, "trials": len(trials)}
         self._save()

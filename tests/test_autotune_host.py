@@ -8,21 +8,23 @@ from paper_1406_5687_amd import autotune, tc
 class FakeGraph:
     def __init__(self):
         self.calls = []
-        self.sched = dict(workers=1024, cost_fn=tc.COST_PRIOR, min_chunk=0, small_max=128)
+        self.sched = dict(workers=1024, cost_fn=tc.COST_PRIOR, min_chunk=0, small_max=128, rounds=0)
 
     def info(self):
         return {"k": 1, "n": 1 << 20, "m": 50 << 20, "max_out_degree": 77, "total_cost": 5_000_000_000,
                 "workers": 1024, "wide_nodes": 0, "tasks": 9000}
 
-    def reschedule(self, workers, cost_fn, min_chunk, small_max):
-        self.sched = dict(workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max)
+    def reschedule(self, workers, cost_fn, min_chunk, small_max, rounds=0):
+        self.sched = dict(workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max,
+                          rounds=rounds)
         self.calls.append(dict(self.sched))
 
 
 def fake_measure(graph, per_node):
     s = graph.sched
-    # best: small_max 64, prior cost, floor 64
+    # best: 16 rounds, small_max 64, prior cost, floor 64
     t = 3.0 + abs(s["small_max"] - 64) / 64 + (0.5 if s["cost_fn"] != tc.COST_PRIOR else 0)
+    t += 0.0 if s["rounds"] == 16 else 0.3
     t += abs(s["min_chunk"] - autotune.Params(64, 64).min_chunk(5_000_000_000, 1024)) / 1e6
     return t
 
@@ -32,9 +34,10 @@ def test_search_picks_fastest_and_caches(tmp_path):
     g = FakeGraph()
     at = autotune.Autotuner(cache_path=path, measure=fake_measure)
     best = at.tune(g, per_node=False)
-    assert best == autotune.Params(64, 64, tc.COST_PRIOR)
-    assert g.sched["small_max"] == 64 and g.sched["cost_fn"] == tc.COST_PRIOR
-    assert len(g.calls) == len(autotune.candidates()) + 1
+    assert best == autotune.Params(64, 64, tc.COST_PRIOR, 16)
+    assert g.sched["small_max"] == 64 and g.sched["cost_fn"] == tc.COST_PRIOR and g.sched["rounds"] == 16
+    # stage 1 over rounds, stage 2 over the grid (minus the point already timed), then the final apply
+    assert len(g.calls) == len(autotune.ROUNDS) + (len(autotune.candidates(16)) - 1) + 1
     data = json.load(open(path))
     assert len(data) == 1 and list(data.values())[0]["params"]["small_max"] == 64
     # a second tuner reads the cache and applies without measuring
