@@ -157,6 +157,12 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
     const int lane = __lane_id();
     uint32_t *flag_word = reinterpret_cast<uint32_t *>(flag);
     uint32_t hits = 0;
+    // wave-uniform by construction; first-lane copies keep them in scalar registers
+    cur = uniform32(cur);
+    nt = uniform32(nt);
+    total = uniform32(total);
+    e_begin = uniform32(e_begin);
+    e_end = uniform32(e_end);
     for (int32_t e0 = e_begin; e0 < e_end; e0 += kStep) {
         int seg[kWin];
         int32_t w[kWin];
@@ -503,8 +509,8 @@ __device__ __forceinline__ void wide_rows(L &S, gptr_t<const int32_t> col, gptr_
     }
     if (threadIdx.x == 0) S.P[carry_n] = carry_sum;
     __syncthreads();
-    *nt_out = carry_n;
-    *total_out = carry_sum;
+    *nt_out = uniform32(carry_n);
+    *total_out = uniform32(carry_sum);
 }
 
 // This wave's contiguous share of the virtual sequence, in whole steps.
@@ -512,7 +518,7 @@ template <int WAVES, int HBITS, bool PER_NODE, bool IDX32, class L>
 __device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &rd, gptr_t<const int32_t> gcol,
                                                  int64_t *__restrict__ tv, int64_t rs, int32_t a, int32_t i0,
                                                  int32_t nt, int32_t total, bool in_lds) {
-    const int wave = threadIdx.x >> 6;
+    const int wave = uniform32(threadIdx.x >> 6);  // the same in every lane of the wave
     const int32_t nsteps = (total + kStep - 1) / kStep;
     const int32_t per = (nsteps + WAVES - 1) / WAVES;
     const int32_t s0 = wave * per;
@@ -522,7 +528,7 @@ __device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &r
     int lo = 0, hi = nt - 1;  // row holding e_begin: last row whose start is <= it
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (S.P[mid] <= e_begin)
+        if (uniform32(S.P[mid]) <= e_begin)
             lo = mid;
         else
             hi = mid - 1;
