@@ -52,23 +52,61 @@ __device__ __forceinline__ int upper_bound_i64(const int64_t *a, int n, int64_t 
 }
 
 // Step 1a: canonical keys.  err bit 0: id out of range.
+// Each thread takes kEdgeUnroll edges at a time: all endpoint loads are issued
+// before the first key is stored.
+constexpr int kEdgeUnroll = 4;
+
 __global__ void k_edge_keys(const int32_t *__restrict__ src, const int32_t *__restrict__ dst, int64_t m_in,
                             const int64_t *__restrict__ edge_base, const int64_t *__restrict__ node_base, int k,
                             int gb, uint64_t *__restrict__ keys, uint32_t *__restrict__ err) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m_in; e += (int64_t)gridDim.x * blockDim.x) {
-        int g = 0;
-        if (k > 1) g = upper_bound_i64(edge_base, k + 1, e) - 1;
-        const int64_t nb = node_base[g];
-        const int64_t ng = node_base[g + 1] - nb;
-        const int32_t u = src[e], v = dst[e];
-        uint64_t key = kInvalid;
-        if (u < 0 || v < 0 || u >= ng || v >= ng) {
-            atomicOr(err, 1u);
-        } else if (u != v) {
-            const uint64_t a = (uint64_t)(nb + (u < v ? u : v)), b = (uint64_t)(nb + (u < v ? v : u));
-            key = (a << gb) | b;
+    const int64_t b1 = k == 1 ? node_base[0] : 0, n1 = k == 1 ? node_base[1] - b1 : 0;  // the one graph
+    const int64_t step = (int64_t)blockDim.x * kEdgeUnroll;
+    for (int64_t e0 = (int64_t)blockIdx.x * step + threadIdx.x; e0 < m_in; e0 += (int64_t)gridDim.x * step) {
+        int32_t u[kEdgeUnroll], v[kEdgeUnroll];
+#pragma unroll
+        for (int j = 0; j < kEdgeUnroll; ++j) {
+            const int64_t e = e0 + (int64_t)j * blockDim.x;
+            u[j] = e < m_in ? __builtin_nontemporal_load(&src[e]) : 0;
+            v[j] = e < m_in ? __builtin_nontemporal_load(&dst[e]) : 0;
         }
-        keys[e] = key;
+        // each edge's graph (first node label and node count), all looked up
+        // before any key is stored
+        int64_t nb[kEdgeUnroll], ng[kEdgeUnroll];
+        if (k == 1) {
+#pragma unroll
+            for (int j = 0; j < kEdgeUnroll; ++j) {
+                nb[j] = b1;
+                ng[j] = n1;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kEdgeUnroll; ++j) {
+                const int64_t e = e0 + (int64_t)j * blockDim.x;
+                const int g = e < m_in ? upper_bound_i64(edge_base, k + 1, e) - 1 : 0;
+                nb[j] = node_base[g];
+                ng[j] = node_base[g + 1] - nb[j];
+            }
+        }
+        uint64_t key[kEdgeUnroll];
+        uint32_t bad = 0;
+#pragma unroll
+        for (int j = 0; j < kEdgeUnroll; ++j) {
+            const int64_t e = e0 + (int64_t)j * blockDim.x;
+            key[j] = kInvalid;
+            if (e >= m_in) continue;
+            if (u[j] < 0 || v[j] < 0 || u[j] >= ng[j] || v[j] >= ng[j]) {
+                bad = 1u;
+            } else if (u[j] != v[j]) {
+                const int32_t lo = u[j] < v[j] ? u[j] : v[j], hi = u[j] < v[j] ? v[j] : u[j];
+                key[j] = ((uint64_t)(nb[j] + lo) << gb) | (uint64_t)(nb[j] + hi);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kEdgeUnroll; ++j) {
+            const int64_t e = e0 + (int64_t)j * blockDim.x;
+            if (e < m_in) keys[e] = key[j];
+        }
+        if (bad) atomicOr(err, 1u);
     }
 }
 
@@ -77,26 +115,37 @@ __global__ void k_edge_keys(const int32_t *__restrict__ src, const int32_t *__re
 constexpr int kSelItems = 16;
 constexpr int kSelTile = kThreads * kSelItems;
 
-__device__ __forceinline__ bool first_of_run(const uint64_t *keys, int64_t i, uint64_t k) {
-    return k != kInvalid && (i == 0 || keys[i - 1] != k);
-}
-
+// Same layout as k_unique_write below: each wave walks its contiguous quarter
+// of the tile 64 keys at a time and compares each key with its predecessor
+// (a shuffle; lane 0 takes the last key of the previous step).
 __global__ __launch_bounds__(kThreads) void k_unique_count(const uint64_t *__restrict__ keys, int64_t n,
                                                            int64_t *__restrict__ partial) {
-    __shared__ int64_t wsum[kThreads / 64];
-    const int64_t base = (int64_t)blockIdx.x * kSelTile;
-    int64_t c = 0;
+    constexpr int kWaves = kThreads / 64;
+    __shared__ int32_t wsum[kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t wbase = (int64_t)blockIdx.x * kSelTile + (int64_t)wave * 64 * kSelItems;
+    uint64_t k[kSelItems];
 #pragma unroll
-    for (int j = 0; j < kSelItems; ++j) {
-        const int64_t i = base + (int64_t)j * kThreads + threadIdx.x;
-        if (i < n) c += first_of_run(keys, i, keys[i]) ? 1 : 0;
+    for (int r = 0; r < kSelItems; ++r) {
+        const int64_t i = wbase + r * 64 + lane;
+        k[r] = i < n ? keys[i] : kInvalid;
     }
-    c = wave_sum(c);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    const int64_t i0 = wbase - 1;
+    uint64_t carry = (i0 >= 0 && i0 < n) ? keys[i0] : kInvalid;  // key before this wave's range
+    int32_t cnt = 0;
+#pragma unroll
+    for (int r = 0; r < kSelItems; ++r) {
+        uint64_t prev = __shfl_up(k[r], 1, 64);
+        if (lane == 0) prev = carry;
+        const int64_t i = wbase + r * 64 + lane;
+        cnt += popc64(__ballot(k[r] != kInvalid && (i == 0 || prev != k[r])));
+        carry = __shfl(k[r], 63, 64);
+    }
+    if (lane == 0) wsum[wave] = cnt;
     __syncthreads();
     if (threadIdx.x == 0) {
         int64_t t = 0;
-        for (int w = 0; w < kThreads / 64; ++w) t += wsum[w];
+        for (int w = 0; w < kWaves; ++w) t += wsum[w];
         partial[blockIdx.x] = t;
     }
 }
@@ -159,35 +208,115 @@ __device__ __forceinline__ T run_sum_at_end(int64_t key, T val, bool *is_end) {
     return val;
 }
 
-// Step 2: degrees.  Keys are sorted, so the lower endpoints arrive in runs and
-// are counted per run; the upper endpoints are written out, sorted, and then
-// counted the same way (no per-edge atomics).
+// Runs of a sorted key array, one wave at a time.  The wave holds positions
+// w0 .. w0+63 (i = w0 + lane) with label x (>= 0; -1 past the end m) and the
+// labels xp, xn of positions i - 1 and i + 1 (-2 / -3 outside 0..m-1), all
+// three loaded by the caller at once.  A run cut by the wave's edges is split
+// into pieces.  Each lane that ends a piece gets the piece's length (the
+// others 0) and *whole = whether the piece is the entire run: then the lane
+// is the run's only writer and may store plainly; pieces of a longer run add
+// atomically.  Starts and ends come from two ballots.
+__device__ __forceinline__ int64_t run_piece_at_end(int64_t x, int64_t xp, int64_t xn, bool valid, int lane,
+                                                    bool *whole) {
+    const uint64_t starts = __ballot(valid && x != xp);
+    const uint64_t ends = __ballot(valid && x != xn);
+    *whole = false;
+    if (!valid || !(((ends >> lane) & 1ull) || lane == 63)) return 0;
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const uint64_t b = (starts | 1ull) & upto;  // lane 0 opens a piece
+    const int first = 63 - __clzll((long long)b);
+    *whole = ((starts >> first) & 1ull) && ((ends >> lane) & 1ull);
+    return lane - first + 1;
+}
+
+// Labels key >> shift at positions i - 1, i, i + 1 of keys[0..m).
+__device__ __forceinline__ void labels3(const uint64_t *__restrict__ keys, int64_t i, int64_t m, int shift,
+                                        uint64_t *k, int64_t *xp, int64_t *x, int64_t *xn) {
+    const bool valid = i < m;
+    *k = valid ? keys[i] : 0;
+    const uint64_t kp = (valid && i > 0) ? keys[i - 1] : 0;
+    const uint64_t kn = (i + 1 < m) ? keys[i + 1] : 0;
+    *x = valid ? (int64_t)(*k >> shift) : -1;
+    *xp = (valid && i > 0) ? (int64_t)(kp >> shift) : -2;
+    *xn = (i + 1 < m) ? (int64_t)(kn >> shift) : -3;
+}
+
+// Step 2: degrees.  Keys are sorted, so each lower endpoint forms one run,
+// counted per piece; the upper endpoints are written out for the histogram
+// below.
 __global__ void k_degrees_lo(const uint64_t *__restrict__ keys, int64_t m, int gb, int32_t *__restrict__ deg,
                              uint32_t *__restrict__ hi_out) {
     const uint64_t mask = (1ull << gb) - 1;
+    const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
         const int64_t i = base + threadIdx.x;
-        int64_t lo = -1 - (int64_t)threadIdx.x;  // distinct for inactive lanes
-        if (i < m) {
-            const uint64_t k = keys[i];
-            lo = (int64_t)(k >> gb);
-            hi_out[i] = (uint32_t)(k & mask);
-        }
-        bool end;
-        const int32_t cnt = run_sum_at_end<int32_t>(lo, i < m ? 1 : 0, &end);
-        if (i < m && end) atomicAdd(&deg[lo], cnt);
+        uint64_t k;
+        int64_t lp, lo, ln;
+        labels3(keys, i, m, gb, &k, &lp, &lo, &ln);
+        bool whole;
+        const int64_t cnt = run_piece_at_end(lo, lp, ln, i < m, lane, &whole);
+        if (cnt) atomicAdd(&deg[lo], (int32_t)cnt);  // adds without a read: nothing to wait for
+        // stores last: a wait for the loads of the next step would also wait
+        // for every store issued before them
+        if (i < m) hi_out[i] = (uint32_t)(k & mask);
     }
 }
 
-__global__ void k_run_counts(const uint32_t *__restrict__ v, int64_t m, int32_t *__restrict__ deg) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
-        const int64_t i = base + threadIdx.x;
-        const int64_t x = i < m ? (int64_t)v[i] : -1 - (int64_t)threadIdx.x;
-        bool end;
-        const int32_t cnt = run_sum_at_end<int32_t>(x, i < m ? 1 : 0, &end);
-        if (i < m && end) atomicAdd(&deg[x], cnt);
+// Upper endpoints: histogram in LDS by buckets of kBins consecutive labels.
+// vals is grouped by bucket (x >> kBinBits ascending).  Workgroup (b, j)
+// counts the j-th of `splits` equal parts of bucket b, then adds its
+// counters to deg: plainly when it is the bucket's only workgroup, else
+// atomically.
+constexpr int kBinBits = 12;
+constexpr int kBins = 1 << kBinBits;
+constexpr int kHistThreads = 1024;
+
+__global__ __launch_bounds__(kHistThreads) void k_bucket_hist(const uint32_t *__restrict__ vals, int64_t m,
+                                                              int splits, int64_t N, int32_t *__restrict__ deg) {
+    __shared__ uint32_t cnt[kBins];
+    __shared__ int64_t range[2];
+    const int64_t b = blockIdx.x / splits;
+    const int j = (int)(blockIdx.x % splits);
+    for (int i = threadIdx.x; i < kBins; i += kHistThreads) cnt[i] = 0;
+    if (threadIdx.x < 2) {
+        // first position whose bucket is >= b (thread 0) or >= b + 1 (thread 1)
+        const uint64_t want = (uint64_t)b + threadIdx.x;
+        int64_t lo = 0, hi = m;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((uint64_t)(vals[mid] >> kBinBits) < want)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        range[threadIdx.x] = lo;
+    }
+    __syncthreads();
+    const int64_t r0 = range[0], len = range[1] - range[0];
+    const int64_t p0 = r0 + len * j / splits, p1 = r0 + len * (j + 1) / splits;
+    constexpr int kUnroll = 4;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += (int64_t)kHistThreads * kUnroll) {
+        uint32_t v[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t q = p + (int64_t)u * kHistThreads;
+            v[u] = q < p1 ? vals[q] : ~0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+            if (v[u] != ~0u) atomicAdd(&cnt[v[u] & (kBins - 1)], 1u);
+    }
+    __syncthreads();
+    const int64_t x0 = b << kBinBits;
+    for (int i = threadIdx.x; i < kBins; i += kHistThreads) {
+        const int64_t x = x0 + i;
+        const uint32_t c = cnt[i];
+        if (c == 0 || x >= N) continue;
+        if (splits == 1)
+            deg[x] += (int32_t)c;
+        else
+            atomicAdd(&deg[x], (int32_t)c);
     }
 }
 
@@ -216,14 +345,37 @@ __global__ void k_rank_from_sorted(const uint64_t *__restrict__ keys, int64_t N,
 }
 
 // Step 4: oriented keys (s << gb) | t with s the lower new label.
+// Each thread takes kOrientUnroll keys at a time, so that all of their label
+// lookups are in flight together; the key streams are marked non-temporal to
+// leave the cache to the label array.
+constexpr int kOrientUnroll = 4;
+
 __global__ void k_orient_keys(const uint64_t *__restrict__ ukeys, int64_t m, int gb, const int32_t *__restrict__ rank,
                               uint64_t *__restrict__ okeys) {
     const uint64_t mask = (1ull << gb) - 1;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t k = ukeys[i];
-        const uint32_t ra = (uint32_t)rank[k >> gb], rb = (uint32_t)rank[k & mask];
-        const uint64_t s = ra < rb ? ra : rb, t = ra < rb ? rb : ra;
-        okeys[i] = (s << gb) | t;
+    const int64_t step = (int64_t)blockDim.x * kOrientUnroll;
+    for (int64_t i0 = (int64_t)blockIdx.x * step + threadIdx.x; i0 < m; i0 += (int64_t)gridDim.x * step) {
+        uint64_t k[kOrientUnroll];
+        uint32_t ra[kOrientUnroll], rb[kOrientUnroll];
+#pragma unroll
+        for (int u = 0; u < kOrientUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * blockDim.x;
+            k[u] = i < m ? __builtin_nontemporal_load(&ukeys[i]) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kOrientUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * blockDim.x;
+            ra[u] = i < m ? (uint32_t)rank[k[u] >> gb] : 0u;
+            rb[u] = i < m ? (uint32_t)rank[k[u] & mask] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kOrientUnroll; ++u) {
+            const int64_t i = i0 + (int64_t)u * blockDim.x;
+            if (i < m) {
+                const uint64_t s = ra[u] < rb[u] ? ra[u] : rb[u], t = ra[u] < rb[u] ? rb[u] : ra[u];
+                __builtin_nontemporal_store((s << gb) | t, &okeys[i]);
+            }
+        }
     }
 }
 
@@ -231,18 +383,17 @@ __global__ void k_orient_keys(const uint64_t *__restrict__ ukeys, int64_t m, int
 __global__ void k_csr_rows(const uint64_t *__restrict__ okeys, int64_t m, int gb, int32_t *__restrict__ col,
                            int32_t *__restrict__ rowlen) {
     const uint64_t mask = (1ull << gb) - 1;
+    const int lane = threadIdx.x & 63;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
         const int64_t i = base + threadIdx.x;
-        int64_t s = -1 - (int64_t)threadIdx.x;
-        if (i < m) {
-            const uint64_t k = okeys[i];
-            s = (int64_t)(k >> gb);
-            col[i] = (int32_t)(k & mask);
-        }
-        bool end;
-        const int32_t cnt = run_sum_at_end<int32_t>(s, i < m ? 1 : 0, &end);
-        if (i < m && end) atomicAdd(&rowlen[s], cnt);
+        uint64_t k;
+        int64_t sp, s, sn;
+        labels3(okeys, i, m, gb, &k, &sp, &s, &sn);
+        bool whole;
+        const int64_t cnt = run_piece_at_end(s, sp, sn, i < m, lane, &whole);
+        if (cnt) atomicAdd(&rowlen[s], (int32_t)cnt);
+        if (i < m) col[i] = (int32_t)(k & mask);  // stores last, as above
     }
 }
 
@@ -263,9 +414,17 @@ __device__ __forceinline__ void cswap(int32_t &a, int32_t &b) {
     b = hi;
 }
 
-__device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col, int64_t r0, int32_t a, int lane) {
+// Cost kind PRIOR of a row of length a: a * a + the row lengths of its
+// targets (Section IV-B).  Rows sorted here add it up from the entries they
+// already hold (f non-null), so no separate pass over the pairs is needed.
+__device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col, int64_t r0, int32_t a, int lane,
+                                              const int32_t *__restrict__ dh, int64_t *__restrict__ f, int64_t row) {
     if (a <= kShortRow) {
         int32_t x = lane < a ? col[r0 + lane] : INT32_MAX;
+        if (f) {
+            const int64_t c = wave_sum((int64_t)(lane < a ? dh[x] : 0));
+            if (lane == 0) f[row] = (int64_t)a * a + c;
+        }
 #pragma unroll
         for (int k = 2; k <= 64; k <<= 1) {
 #pragma unroll
@@ -283,6 +442,14 @@ __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col, int64_t
     for (int j = 0; j < 4; ++j) {
         const int i = lane * 4 + j;
         v[j] = i < a ? col[r0 + i] : INT32_MAX;
+    }
+    if (f) {
+        int64_t c = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (lane * 4 + j < a) c += dh[v[j]];
+        c = wave_sum(c);
+        if (lane == 0) f[row] = (int64_t)a * a + c;
     }
 #pragma unroll
     for (int k = 2; k <= kMidRow; k <<= 1) {
@@ -318,7 +485,8 @@ __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col, int64_t
 
 __global__ __launch_bounds__(kThreads) void k_sort_rows(const int64_t *__restrict__ off, int64_t N,
                                                         int32_t *__restrict__ col, int32_t *__restrict__ long_rows,
-                                                        unsigned int *__restrict__ nlong) {
+                                                        unsigned int *__restrict__ nlong,
+                                                        const int32_t *__restrict__ dh, int64_t *__restrict__ f) {
     const int lane = __lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -330,28 +498,97 @@ __global__ __launch_bounds__(kThreads) void k_sort_rows(const int64_t *__restric
             r0 = off[r];
             a = (int32_t)(off[r + 1] - r0);
         }
-        if (a >= 2 && a <= kTinyRow) {
-            // optimal 19-comparator network for 8 inputs; padding sorts last
+        if (f && r < N && a == 0) f[r] = 0;
+        if (a >= 1 && a <= kTinyRow) {
             int32_t x[kTinyRow];
 #pragma unroll
             for (int j = 0; j < kTinyRow; ++j) x[j] = j < a ? col[r0 + j] : INT32_MAX;
-            cswap(x[0], x[2]); cswap(x[1], x[3]); cswap(x[4], x[6]); cswap(x[5], x[7]);
-            cswap(x[0], x[4]); cswap(x[1], x[5]); cswap(x[2], x[6]); cswap(x[3], x[7]);
-            cswap(x[0], x[1]); cswap(x[2], x[3]); cswap(x[4], x[5]); cswap(x[6], x[7]);
-            cswap(x[2], x[4]); cswap(x[3], x[5]);
-            cswap(x[1], x[4]); cswap(x[3], x[6]);
-            cswap(x[1], x[2]); cswap(x[3], x[4]); cswap(x[5], x[6]);
+            if (f) {
+                int64_t c = (int64_t)a * a;
 #pragma unroll
-            for (int j = 0; j < kTinyRow; ++j)
-                if (j < a) col[r0 + j] = x[j];
+                for (int j = 0; j < kTinyRow; ++j)
+                    if (j < a) c += dh[x[j]];
+                f[r] = c;
+            }
+            if (a >= 2) {
+                // optimal 19-comparator network for 8 inputs; padding sorts last
+                cswap(x[0], x[2]); cswap(x[1], x[3]); cswap(x[4], x[6]); cswap(x[5], x[7]);
+                cswap(x[0], x[4]); cswap(x[1], x[5]); cswap(x[2], x[6]); cswap(x[3], x[7]);
+                cswap(x[0], x[1]); cswap(x[2], x[3]); cswap(x[4], x[5]); cswap(x[6], x[7]);
+                cswap(x[2], x[4]); cswap(x[3], x[5]);
+                cswap(x[1], x[4]); cswap(x[3], x[6]);
+                cswap(x[1], x[2]); cswap(x[3], x[4]); cswap(x[5], x[6]);
+#pragma unroll
+                for (int j = 0; j < kTinyRow; ++j)
+                    if (j < a) col[r0 + j] = x[j];
+            }
         }
-        uint64_t rest = __ballot(a > kTinyRow && a <= kMidRow);
+        // rows of up to 64 entries, one after another by the whole wave; the
+        // next row's entries are loaded while this one is sorted
+        uint64_t rest = __ballot(a > kTinyRow && a <= kShortRow);
+        if (rest) {
+            int l = __ffsll((unsigned long long)rest) - 1;
+            rest &= rest - 1;
+            int64_t rc = readlane64(r0, l);
+            int32_t ac = readlane32(a, l);
+            int32_t xc = lane < ac ? col[rc + lane] : INT32_MAX;
+            while (true) {
+                int ln = -1;
+                int64_t rn = 0;
+                int32_t an = 0, xn = INT32_MAX;
+                if (rest) {
+                    ln = __ffsll((unsigned long long)rest) - 1;
+                    rest &= rest - 1;
+                    rn = readlane64(r0, ln);
+                    an = readlane32(a, ln);
+                    xn = lane < an ? col[rn + lane] : INT32_MAX;
+                }
+                const int64_t dv = (f && lane < ac) ? (int64_t)dh[xc] : 0;
+#pragma unroll
+                for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+                    for (int d = k >> 1; d > 0; d >>= 1) {
+                        const int32_t y = __shfl_xor(xc, d, 64);
+                        const bool up = (lane & k) == 0, lower = (lane & d) == 0;
+                        xc = (lower == up) ? min(xc, y) : max(xc, y);
+                    }
+                }
+                if (lane < ac) col[rc + lane] = xc;
+                if (f) {
+                    const int64_t c = wave_sum(dv);
+                    if (lane == 0) f[g0 + l] = (int64_t)ac * ac + c;
+                }
+                if (ln < 0) break;
+                l = ln;
+                rc = rn;
+                ac = an;
+                xc = xn;
+            }
+        }
+        rest = __ballot(a > kShortRow && a <= kMidRow);
         while (rest) {
             const int l = __ffsll((unsigned long long)rest) - 1;
             rest &= rest - 1;
-            wave_sort_row(col, readlane64(r0, l), readlane32(a, l), lane);
+            wave_sort_row(col, readlane64(r0, l), readlane32(a, l), lane, dh, f, g0 + l);
         }
         if (a > kMidRow) long_rows[atomicAdd(nlong, 1u)] = (int32_t)r;
+    }
+}
+
+// PRIOR costs of the long rows (one wave per row).
+__global__ void k_long_costs(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                             const int32_t *__restrict__ long_rows, int64_t L, const int32_t *__restrict__ dh,
+                             int64_t *__restrict__ f) {
+    const int lane = __lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = wave; i < L; i += nwaves) {
+        const int32_t r = long_rows[i];
+        const int64_t r0 = off[r], a = off[r + 1] - r0;
+        int64_t c = 0;
+        for (int64_t p = lane; p < a; p += 64) c += dh[col[r0 + p]];
+        c = wave_sum(c);
+        if (lane == 0) f[r] = a * a + c;
     }
 }
 
@@ -465,6 +702,15 @@ __global__ void k_node_costs(const int64_t *__restrict__ off, const int32_t *__r
     }
     local_max = wave_reduce_max(local_max);
     if (__lane_id() == 0) atomicMax(max_dhat, local_max);
+}
+
+__global__ void k_totals(const int64_t *a, const int64_t *b, const int64_t *c, const int32_t *d, int64_t *out) {
+    if (threadIdx.x == 0) {
+        out[0] = *a;
+        out[1] = *b;
+        out[2] = *c;
+        out[3] = d ? (int64_t)*d : 0;
+    }
 }
 
 __global__ void k_compact_index(const uint32_t *__restrict__ flag, const int64_t *__restrict__ pos, int64_t n,
@@ -621,19 +867,27 @@ thread_local PinnedStage t_stage;
 }  // namespace
 
 // Sorts every row of (off, col) ascending.  ka / kb: scratch of cap keys each.
+// With f non-null, also writes the PRIOR cost of every row into f (dh: row
+// lengths).
 void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka, uint64_t *kb, int64_t cap,
-               Allocator &tmp, hipStream_t s) {
+               const int32_t *dh, int64_t *f, Allocator &tmp, hipStream_t s) {
     if (N <= 0) return;
     DevBuf<int32_t> long_rows(tmp, (size_t)N);
     DevBuf<unsigned int> nlong(tmp, 1);
     fill_zero(nlong.p, 4, s);
     const int64_t waves = std::min<int64_t>(ceil_div(N, 64), (int64_t)device_cu_count() * 64);
-    k_sort_rows<<<(unsigned)ceil_div(waves * 64, kThreads), kThreads, 0, s>>>(off, N, col, long_rows.p, nlong.p);
+    k_sort_rows<<<(unsigned)ceil_div(waves * 64, kThreads), kThreads, 0, s>>>(off, N, col, long_rows.p, nlong.p,
+                                                                               dh, f);
     TC_LAUNCH_CHECK();
     unsigned int L = 0;
     d2h(&L, nlong.p, 1, s);
     TC_HIP(hipStreamSynchronize(s));
     if (L == 0) return;
+    if (f) {
+        const int64_t cw = std::min<int64_t>(L, (int64_t)device_cu_count() * 64);
+        k_long_costs<<<(unsigned)ceil_div(cw * 64, kThreads), kThreads, 0, s>>>(off, col, long_rows.p, L, dh, f);
+        TC_LAUNCH_CHECK();
+    }
     DevBuf<int64_t> len(tmp, L), epos(tmp, (size_t)L + 1);
     k_long_lengths<<<grid_for(L), kThreads, 0, s>>>(off, long_rows.p, L, len.p);
     TC_LAUNCH_CHECK();
@@ -654,7 +908,7 @@ void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka
 void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp, Allocator &al,
                 Allocator &tmp, hipStream_t s, Oriented &out);
 void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
-                   Oriented &out, const uint64_t *okeys, int gb);
+                   Oriented &out, const uint64_t *okeys, int gb, int64_t *f_prior = nullptr);
 
 void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
                            Allocator &al, hipStream_t s, Oriented &out) {
@@ -696,13 +950,12 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     DevBuf<uint64_t> kb(tmp, (size_t)std::max<int64_t>(M_in, 1));
     uint64_t *ukeys = kb.p;
     if (M_in > 0) {
-        k_edge_keys<<<grid_for(M_in, 4), kThreads, 0, s>>>(src, dst, M_in, edge_base.p, out.node_base.p, k, gb, ka.p,
+        k_edge_keys<<<grid_for(M_in, 4 * kEdgeUnroll), kThreads, 0, s>>>(src, dst, M_in, edge_base.p, out.node_base.p, k, gb, ka.p,
                                                             err.p);
         TC_LAUNCH_CHECK();
         uint64_t *sorted = radix_sort_u64(ka.p, kb.p, M_in, 0, 2 * gb, tmp, s);
         uint64_t *other = sorted == ka.p ? kb.p : ka.p;
-        M = unique_sorted_keys(sorted, M_in, other, tmp, s);  // synchronises
-        ukeys = other;
+        M = unique_sorted_keys(sorted, M_in, other, &ukeys, tmp, s);  // synchronises
         uint32_t herr = 0;
         d2h(&herr, err.p, 1, s);
         TC_HIP(hipStreamSynchronize(s));
@@ -714,7 +967,7 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     // ---- 2. degrees
     DevBuf<int32_t> deg(tmp, (size_t)std::max<int64_t>(N, 1));
     fill_zero(deg.p, deg.bytes(), s);
-    add_degrees(ukeys, M, gb, deg.p, reinterpret_cast<uint32_t *>(spare), tmp, s);  // spare: >= 2 M words
+    add_degrees(ukeys, M, gb, deg.p, N, reinterpret_cast<uint32_t *>(spare), tmp, s);  // spare: >= 2 M words
 
     // ---- 3. degree order
     out.perm = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(N, 1));
@@ -728,7 +981,7 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     fill_zero(rowlen.p, rowlen.bytes(), s);
     uint64_t *okeys = nullptr;
     if (M > 0) {
-        k_orient_keys<<<grid_for(M, 4), kThreads, 0, s>>>(ukeys, M, gb, rank.p, spare);
+        k_orient_keys<<<grid_for(M, 4 * kOrientUnroll), kThreads, 0, s>>>(ukeys, M, gb, rank.p, spare);
         TC_LAUNCH_CHECK();
         // rows by s only (stable): each row keeps input order and is sorted below
         okeys = radix_sort_u64(spare, ukeys, M, gb, 2 * gb, tmp, s);
@@ -743,25 +996,37 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
         k_gather_deg<<<grid_for(N, 4), kThreads, 0, s>>>(deg.p, out.perm.p, N, out.deg.p);
         TC_LAUNCH_CHECK();
     }
-    schedule_into(pk, bp, al, tmp, s, out, okeys, gb);
-    if (M > 0) sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, tmp, s);
+    if (bp.cost_fn == TC_COST_PRIOR && M > 0) {
+        // the row sort adds up the PRIOR costs on the way
+        DevBuf<int64_t> f(tmp, (size_t)N);
+        sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, rowlen.p, f.p, tmp, s);
+        schedule_into(pk, bp, al, tmp, s, out, nullptr, gb, f.p);
+    } else {
+        schedule_into(pk, bp, al, tmp, s, out, okeys, gb);
+        if (M > 0) sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, nullptr, nullptr, tmp, s);
+    }
 }
 
 // Step 6 proper.  okeys (sorted pair keys) speed up the edge costs when the
 // build still holds them; otherwise costs are computed row by row.
 void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
-                   Oriented &out, const uint64_t *okeys, int gb) {
+                   Oriented &out, const uint64_t *okeys, int gb, int64_t *f_prior) {
     const int64_t N = pk.N, M = out.M;
-    DevBuf<int64_t> f(tmp, (size_t)std::max<int64_t>(N, 1));
-    fill_zero(f.p, f.bytes(), s);
-    if (M > 0 && (bp.cost_fn == TC_COST_PRIOR || bp.cost_fn == TC_COST_NEW)) {
+    DevBuf<int64_t> f_own;
+    int64_t *f = f_prior;  // PRIOR costs computed by the caller, else computed here
+    if (!f_prior) {
+        f_own = DevBuf<int64_t>(tmp, (size_t)std::max<int64_t>(N, 1));
+        f = f_own.p;
+        fill_zero(f, f_own.bytes(), s);
+    }
+    if (!f_prior && M > 0 && (bp.cost_fn == TC_COST_PRIOR || bp.cost_fn == TC_COST_NEW)) {
         DevBuf<int32_t> dh(tmp, (size_t)N);
         k_row_lengths<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, N, dh.p);
         TC_LAUNCH_CHECK();
         if (okeys) {
-            k_edge_costs<<<grid_for(M, 4), kThreads, 0, s>>>(dh.p, okeys, M, gb, bp.cost_fn, f.p);
+            k_edge_costs<<<grid_for(M, 4), kThreads, 0, s>>>(dh.p, okeys, M, gb, bp.cost_fn, f);
         } else {
-            k_row_costs<<<grid_for(N, 1), kThreads, 0, s>>>(out.off.p, out.col.p, dh.p, N, bp.cost_fn, f.p);
+            k_row_costs<<<grid_for(N, 1), kThreads, 0, s>>>(out.off.p, out.col.p, dh.p, N, bp.cost_fn, f);
         }
         TC_LAUNCH_CHECK();
     }
@@ -770,14 +1035,14 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
     fill_zero(maxd.p, 4, s);
     if (N > 0) {
         k_node_costs<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, out.deg.p, N, bp.cost_fn, bp.small_max,
-                                                          max_medium_list(), f.p, wmed.p, wlarge.p, maxd.p);
+                                                          max_medium_list(), f, wmed.p, wlarge.p, maxd.p);
         TC_LAUNCH_CHECK();
     }
     Schedule sc;
     BuildParams bpr = bp;
     bpr.rounds = bp.rounds > 0 ? bp.rounds : auto_rounds(pk.k, M);
     out.rounds = bpr.rounds;
-    schedule_sources(f.p, wmed.p, wlarge.p, N, pk.k, out.node_base.p, bpr, al, tmp, s, sc, maxd.p, &out.max_dhat);
+    schedule_sources(f, wmed.p, wlarge.p, N, pk.k, out.node_base.p, bpr, al, tmp, s, sc, maxd.p, &out.max_dhat);
     out.bnd = std::move(sc.bnd);
     out.gid = std::move(sc.gid);
     out.big = std::move(sc.big);
@@ -795,17 +1060,17 @@ void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wl
     exclusive_scan(f, F.p, N, true, tmp, s);
     exclusive_scan(wmed, pmed.p, N, true, tmp, s);
     exclusive_scan(wlarge, plarge.p, N, true, tmp, s);
-    int64_t hv[3] = {0, 0, 0};
-    int32_t hmax = 0;
-    d2h(&hv[0], F.p + N, 1, s);
-    d2h(&hv[1], pmed.p + N, 1, s);
-    d2h(&hv[2], plarge.p + N, 1, s);
-    if (maxd_dev) d2h(&hmax, maxd_dev, 1, s);
+    // the three totals and the longest list in one copy
+    int64_t hv[4] = {0, 0, 0, 0};
+    DevBuf<int64_t> tot4(tmp, 4);
+    k_totals<<<1, 64, 0, s>>>(F.p + N, pmed.p + N, plarge.p + N, maxd_dev, tot4.p);
+    TC_LAUNCH_CHECK();
+    d2h(hv, tot4.p, 4, s);
     TC_HIP(hipStreamSynchronize(s));
     out.total_cost = hv[0];
     out.nmed = hv[1];
     out.nbig = hv[1] + hv[2];
-    if (maxd_host) *maxd_host = hmax;
+    if (maxd_host) *maxd_host = (int32_t)hv[3];
 
     out.big = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(out.nbig, 1));
     if (out.nmed > 0) {
@@ -857,10 +1122,10 @@ void task_bounds(const int64_t *F, int64_t N, const std::vector<int64_t> &target
     DevBuf<int64_t> dtg(tmp, (size_t)std::max<int64_t>(ntg, 1));
     void *pin = t_stage.get((size_t)ntg * sizeof(int64_t));
     if (pin) {
+        // the staging buffer is reused by the next call; every caller
+        // synchronises the stream before that
         std::memcpy(pin, targets.data(), ntg * sizeof(int64_t));
         TC_HIP(hipMemcpyAsync(dtg.p, pin, ntg * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        // the staging buffer is reused by the next call: wait for this copy
-        TC_HIP(hipStreamSynchronize(s));
     } else {
         TC_HIP(hipMemcpyAsync(dtg.p, targets.data(), ntg * sizeof(int64_t), hipMemcpyHostToDevice, s));
     }
@@ -868,30 +1133,41 @@ void task_bounds(const int64_t *F, int64_t N, const std::vector<int64_t> &target
     TC_LAUNCH_CHECK();
 }
 
-int64_t unique_sorted_keys(const uint64_t *sorted, int64_t n, uint64_t *out, Allocator &tmp, hipStream_t s) {
+int64_t unique_sorted_keys(uint64_t *sorted, int64_t n, uint64_t *out, uint64_t **res, Allocator &tmp,
+                           hipStream_t s) {
+    *res = out;
     if (n <= 0) return 0;
     const int64_t nt = ceil_div(n, kSelTile);
     DevBuf<int64_t> part(tmp, (size_t)nt + 1);
     k_unique_count<<<(unsigned)nt, kThreads, 0, s>>>(sorted, n, part.p);
     TC_LAUNCH_CHECK();
     exclusive_scan(part.p, part.p, nt, true, tmp, s);
-    k_unique_write<<<(unsigned)nt, kThreads, 0, s>>>(sorted, n, part.p, out);
-    TC_LAUNCH_CHECK();
     int64_t M = 0;
     d2h(&M, part.p + nt, 1, s);
     TC_HIP(hipStreamSynchronize(s));
+    if (M == n) {
+        *res = sorted;  // no duplicates and no self-loops: already the set
+        return M;
+    }
+    k_unique_write<<<(unsigned)nt, kThreads, 0, s>>>(sorted, n, part.p, out);
+    TC_LAUNCH_CHECK();
     return M;
 }
 
-void add_degrees(const uint64_t *ukeys, int64_t M, int gb, int32_t *deg, uint32_t *spare, Allocator &tmp,
+void add_degrees(const uint64_t *ukeys, int64_t M, int gb, int32_t *deg, int64_t N, uint32_t *spare, Allocator &tmp,
                  hipStream_t s) {
     if (M <= 0) return;
     uint32_t *hi = spare;  // 2 M words
     uint32_t *hi_tmp = hi + M;
     k_degrees_lo<<<grid_for(M, 4), kThreads, 0, s>>>(ukeys, M, gb, deg, hi);
     TC_LAUNCH_CHECK();
-    uint32_t *hs = radix_sort_u32(hi, hi_tmp, M, 0, gb, tmp, s);
-    k_run_counts<<<grid_for(M, 4), kThreads, 0, s>>>(hs, M, deg);
+    // group the upper endpoints by bucket (label bits above kBinBits), then
+    // count each bucket in LDS
+    uint32_t *hs = gb > kBinBits ? radix_sort_u32(hi, hi_tmp, M, kBinBits, gb, tmp, s) : hi;
+    const int64_t nbuckets = gb > kBinBits ? (int64_t)1 << (gb - kBinBits) : 1;
+    const int64_t per_group = (int64_t)1 << 17;  // values per workgroup, about
+    const int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, ceil_div(M, nbuckets * per_group)));
+    k_bucket_hist<<<(unsigned)(nbuckets * splits), kHistThreads, 0, s>>>(hs, M, splits, N, deg);
     TC_LAUNCH_CHECK();
 }
 

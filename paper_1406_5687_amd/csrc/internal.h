@@ -94,9 +94,14 @@ std::vector<int64_t> task_targets(int64_t total, int32_t W, int64_t min_chunk, b
 void task_bounds(const int64_t *F, int64_t N, const std::vector<int64_t> &targets, int32_t *bnd, Allocator &tmp,
                  hipStream_t s);
 // Build steps shared by the resident and the partitioned builds.
-int64_t unique_sorted_keys(const uint64_t *sorted, int64_t n, uint64_t *out, Allocator &tmp,
-                           hipStream_t s);  // synchronises; returns the count
-void add_degrees(const uint64_t *ukeys, int64_t M, int gb, int32_t *deg, uint32_t *spare /* 2 M words */,
+// Distinct valid keys of sorted[0..n), in order.  *res is set to where they
+// are: sorted itself when all n keys are distinct and valid (nothing is
+// copied), else out.  Synchronises; returns their number.
+int64_t unique_sorted_keys(uint64_t *sorted, int64_t n, uint64_t *out, uint64_t **res, Allocator &tmp,
+                           hipStream_t s);
+// deg[x] += number of distinct neighbours of x in the sorted, distinct pair
+// keys (x_lo << gb) | x_hi; deg has N entries, every label is below N.
+void add_degrees(const uint64_t *ukeys, int64_t M, int gb, int32_t *deg, int64_t N, uint32_t *spare /* 2 M words */,
                  Allocator &tmp, hipStream_t s);
 void degree_rank(const int32_t *deg, int64_t N, const int64_t *node_base, int k, int32_t max_n, int32_t *perm,
                  int32_t *rank, Allocator &tmp, hipStream_t s);

@@ -393,9 +393,11 @@ void build_partitioned(const int32_t *src, const int32_t *dst, bool on_device, c
             if ((int64_t)got != nraw) throw Error(TC_ERR_DEVICE, "bucket edge count disagrees with the histogram");
             uint64_t *sorted = radix_sort_u64(ka.p, kb.p, (int64_t)nraw, 0, 2 * gb, al, s);
             uint64_t *other = sorted == ka.p ? kb.p : ka.p;
-            const int64_t mb = unique_sorted_keys(sorted, (int64_t)nraw, other, al, s);
-            add_degrees(other, mb, gb, deg.p, reinterpret_cast<uint32_t *>(sorted), al, s);
-            d2h(U.p + M, other, (size_t)mb, s);
+            uint64_t *uk = nullptr;
+            const int64_t mb = unique_sorted_keys(sorted, (int64_t)nraw, other, &uk, al, s);
+            uint64_t *spare = uk == sorted ? other : sorted;
+            add_degrees(uk, mb, gb, deg.p, N, reinterpret_cast<uint32_t *>(spare), al, s);
+            d2h(U.p + M, uk, (size_t)mb, s);
             TC_HIP(hipStreamSynchronize(s));
             M += mb;
         }

@@ -32,11 +32,19 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const Tin *__restr
                                                              Tout *__restrict__ partial) {
     __shared__ Tout wave_tot[kScanThreads / 64];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    // every load is issued before the first is used (positions past the end
+    // read the last element, then count 0: no branch around the loads)
+    Tin v[kScanItems];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t i = base + (int64_t)j * kScanThreads + threadIdx.x;
+        v[j] = in[i < n ? i : n - 1];
+    }
     Tout s = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         const int64_t i = base + (int64_t)j * kScanThreads + threadIdx.x;
-        if (i < n) s += (Tout)in[i];
+        s += i < n ? (Tout)v[j] : (Tout)0;
     }
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) wave_tot[threadIdx.x >> 6] = s;
@@ -57,12 +65,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const Tin *__restri
     __shared__ Tout wave_tot[kScanThreads / 64];
     __shared__ Tout stage[kScanTile];
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    // coalesced load into LDS, then each thread scans a contiguous run
+    // coalesced loads (all issued before the first is used; positions past
+    // the end read the last element and stage 0) into LDS, then each thread
+    // scans a contiguous run
+    {
+        Tin ld[kScanItems];
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const int idx = j * kScanThreads + threadIdx.x;
-        const int64_t i = base + idx;
-        stage[idx] = i < n ? (Tout)in[i] : (Tout)0;
+        for (int j = 0; j < kScanItems; ++j) {
+            const int64_t i = base + j * kScanThreads + threadIdx.x;
+            ld[j] = in[i < n ? i : n - 1];
+        }
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            const int64_t i = base + j * kScanThreads + threadIdx.x;
+            stage[j * kScanThreads + threadIdx.x] = i < n ? (Tout)ld[j] : (Tout)0;
+        }
     }
     __syncthreads();
     Tout v[kScanItems];

@@ -1,9 +1,10 @@
-// LSD radix sort of 64-bit keys over a bit range, 8 bits per pass.
+// LSD radix sort of 32- or 64-bit keys over a bit range, 8 bits per pass (the
+// last pass takes what is left of the range).
 //
-// Each pass: (1) per-tile digit histograms, (2) one exclusive scan over the
+// Each pass: (1) per-tile digit histograms (LDS adds), (2) one exclusive scan over the
 // digit-major histogram table giving every (digit, tile) its output base,
 // (3) a stable scatter: each wave ranks its keys among equal digits with
-// ballots, the tile is reordered by digit in LDS, and runs of equal digits
+// ballots over the digit bits, the tile is reordered by digit in LDS, and runs of equal digits
 // are written out contiguously.
 #include "internal.h"
 
@@ -23,14 +24,31 @@ __device__ __forceinline__ int64_t key_index(int64_t tile_base, int wave, int r,
     return tile_base + (int64_t)wave * 64 * kSortRounds + r * 64 + lane;
 }
 
+// Workgroups go to the 8 XCDs round-robin by index.  Tile of workgroup b: each
+// XCD takes one contiguous range of tiles, so the digit-table entries and the
+// output runs that neighbouring tiles share sit in the same L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+    const int64_t x = b & 7, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// Digit of a key in the pass at `shift`: `bits` (<= 8) bits, so that a
+// range whose width is not a multiple of 8 ignores the bits above it.
+template <class K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t dmask) {
+    return (uint32_t)(key >> shift) & dmask;
+}
+
 template <class K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K *__restrict__ keys, int64_t n, int shift,
-                                                             int64_t nblocks, uint32_t *__restrict__ hist) {
-    __shared__ uint32_t h[kRadix];
-    for (int i = threadIdx.x; i < kRadix; i += kSortThreads) h[i] = 0;
+                                                             int bits, int64_t nblocks, uint32_t *__restrict__ hist) {
+    const uint32_t dmask = (1u << bits) - 1u;
+    __shared__ uint32_t hw[kSortWaves][kRadix];  // one histogram per wave
+    for (int i = threadIdx.x; i < kSortWaves * kRadix; i += kSortThreads) (&hw[0][0])[i] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    const int64_t t = xcd_tile(blockIdx.x, nblocks);
+    const int64_t tile = t * kSortTile;
     // all of the lane's keys are loaded before any is ranked
     K kk[kSortRounds];
 #pragma unroll
@@ -41,20 +59,31 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K *__restrict
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         const int64_t i = key_index(tile, wave, r, lane);
-        uint32_t d = 256u;  // inactive
-        if (i < n) d = (uint32_t)(kk[r] >> shift) & 0xffu;
-        const uint64_t peers = match_peers9(d);
-        const int leader = __ffsll((unsigned long long)peers) - 1;
-        if (d < 256u && leader == lane) atomicAdd(&h[d], (uint32_t)popc64(peers));
+        const uint32_t d = digit_of(kk[r], shift, dmask);
+        // one add when all 64 keys share a digit (sorted or narrow input),
+        // else one LDS add per key
+        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+        if (__ballot(i < n && d == d0) == ~0ull) {
+            if (lane == 0) atomicAdd(&hw[wave][d0], 64u);
+        } else if (i < n) {
+            atomicAdd(&hw[wave][d], 1u);
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kRadix; i += kSortThreads) hist[(int64_t)i * nblocks + blockIdx.x] = h[i];
+    for (int i = threadIdx.x; i < kRadix; i += kSortThreads) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kSortWaves; ++w) c += hw[w][i];
+        hist[(int64_t)i * nblocks + t] = c;
+    }
 }
 
 template <class K>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K *__restrict__ keys, K *__restrict__ out,
-                                                                int64_t n, int shift, int64_t nblocks,
+                                                                int64_t n, int shift, int bits, int64_t nblocks,
                                                                 const int64_t *__restrict__ base) {
+    static_assert(kSortThreads >= kRadix, "one thread per digit in the tile scan");
+    const uint32_t dmask = (1u << bits) - 1u;
     __shared__ uint32_t wcnt[kSortWaves][kRadix];
     __shared__ uint32_t bstart[kRadix];
     __shared__ int64_t gbase[kRadix];
@@ -65,7 +94,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K *__restr
     for (int i = threadIdx.x; i < kSortWaves * kRadix; i += kSortThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
 
-    const int64_t tile = (int64_t)blockIdx.x * kSortTile;
+    const int64_t t = xcd_tile(blockIdx.x, nblocks);
+    const int64_t tile = t * kSortTile;
+    const bool full = n - tile >= kSortTile;  // block-uniform: every lane holds a key
     K k[kSortRounds];
     uint32_t rank[kSortRounds];
 #pragma unroll
@@ -76,8 +107,27 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K *__restr
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         const int64_t i = key_index(tile, wave, r, lane);
-        const uint32_t d = i < n ? (uint32_t)(k[r] >> shift) & 0xffu : 256u;
-        const uint64_t peers = match_peers9(d);
+        const uint32_t d = i < n ? digit_of(k[r], shift, dmask) : 256u;  // 256: past the end
+        // lanes of this wave holding the same digit: all of them when the
+        // first lane's digit is everyone's, else one ballot per digit bit
+        // (plus one for the past-the-end flag in the last tile)
+        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+        uint64_t peers = ~0ull;
+        if (__ballot(d == d0) != ~0ull) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                if (b < bits) {
+                    const bool bit = (d >> b) & 1u;
+                    const uint64_t bal = __ballot(bit);
+                    peers &= bit ? bal : ~bal;
+                }
+            }
+            if (!full) {
+                const bool past = d >> 8;
+                const uint64_t bal = __ballot(past);
+                peers &= past ? bal : ~bal;
+            }
+        }
         const int leader = __ffsll((unsigned long long)peers) - 1;
         uint32_t before = 0;
         if (d < 256u) before = wcnt[wave][d];
@@ -89,13 +139,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K *__restr
     __syncthreads();
     // per digit: offsets of each wave, tile total, start of the digit in the tile
     {
-        const int d = threadIdx.x;  // kSortThreads == kRadix
+        const int d = threadIdx.x;  // threads past the last digit add nothing
         uint32_t tot = 0;
+        if (d < kRadix) {
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) {
-            const uint32_t c = wcnt[w][d];
-            wcnt[w][d] = tot;
-            tot += c;
+            for (int w = 0; w < kSortWaves; ++w) {
+                const uint32_t c = wcnt[w][d];
+                wcnt[w][d] = tot;
+                tot += c;
+            }
         }
         // block exclusive scan of tot over digits
         uint32_t inc = wave_inclusive_sum(tot);
@@ -105,15 +157,17 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K *__restr
 #pragma unroll
         for (int w = 0; w < kSortWaves; ++w)
             if (w < wave) add += scan_tmp[w];
-        bstart[d] = add + inc - tot;
-        gbase[d] = base[(int64_t)d * nblocks + blockIdx.x];
+        if (d < kRadix) {
+            bstart[d] = add + inc - tot;
+            gbase[d] = base[(int64_t)d * nblocks + t];
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         const int64_t i = key_index(tile, wave, r, lane);
         if (i < n) {
-            const uint32_t d = (uint32_t)(k[r] >> shift) & 0xffu;
+            const uint32_t d = digit_of(k[r], shift, dmask);
             stage[bstart[d] + wcnt[wave][d] + rank[r]] = k[r];
         }
     }
@@ -121,7 +175,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K *__restr
     const int64_t valid = n - tile < kSortTile ? n - tile : kSortTile;
     for (int i = threadIdx.x; i < valid; i += kSortThreads) {
         const K key = stage[i];
-        const uint32_t d = (uint32_t)(key >> shift) & 0xffu;
+        const uint32_t d = digit_of(key, shift, dmask);
         const int64_t at = gbase[d] + (i - (int64_t)bstart[d]);
         if ((uint64_t)at < (uint64_t)n) out[at] = key;
     }
@@ -135,10 +189,11 @@ K *radix_sort_impl(K *keys, K *tmp, int64_t n, int begin_bit, int end_bit, Alloc
     DevBuf<int64_t> base(al, (size_t)(nb * kRadix) + 1);
     K *a = keys, *b = tmp;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        k_radix_hist<K><<<(unsigned)nb, kSortThreads, 0, s>>>(a, n, shift, nb, hist.p);
+        const int bits = std::min(8, end_bit - shift);
+        k_radix_hist<K><<<(unsigned)nb, kSortThreads, 0, s>>>(a, n, shift, bits, nb, hist.p);
         TC_LAUNCH_CHECK();
         exclusive_scan(hist.p, base.p, nb * kRadix, false, al, s);
-        k_radix_scatter<K><<<(unsigned)nb, kSortThreads, 0, s>>>(a, b, n, shift, nb, base.p);
+        k_radix_scatter<K><<<(unsigned)nb, kSortThreads, 0, s>>>(a, b, n, shift, bits, nb, base.p);
         TC_LAUNCH_CHECK();
         K *t = a;
         a = b;
