@@ -122,7 +122,8 @@ typedef struct tc_graph tc_graph;
  * layout.  With a budget, or partitions > 0, a single graph may be built in the
  * partitioned form, its oriented adjacency kept in pinned host memory.
  * Errors: TC_ERR_INVALID_ARG (NULL graphs/out, k < 1, negative n or m, NULL
- * src/dst with m > 0), TC_ERR_ID_RANGE, TC_ERR_TOO_LARGE (sum of n >= 2^31),
+ * src/dst with m > 0), TC_ERR_ID_RANGE, TC_ERR_TOO_LARGE (sum of n >= 2^31,
+ * or 2^32 - 1 or more distinct edges in one resident handle),
  * TC_ERR_OUT_OF_MEMORY, TC_ERR_DEVICE.  *out is written only on TC_OK. */
 tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options *opt, tc_graph **out);
 

@@ -10,7 +10,8 @@
 //   3. degree order        -- sort (g, d_x, v): position r in the sorted list is the
 //                             new label of x (Section III-A order, ties by id)
 //   4. orientation         -- edge {a, b} stored at the lower label s as (s, t);
-//                             a stable radix sort of (s << GB) | t by s groups the rows
+//                             stable radix passes order the keys by s >> 4, one
+//                             wave per 16 rows places them into the rows
 //   5. CSR                 -- col = t, off = exclusive scan of row lengths; each row
 //                             then sorted ascending on its own
 //   6. costs and tasks     -- f per node (Sections IV-B, IV-F, V-A), prefix sums,
@@ -320,6 +321,94 @@ __global__ __launch_bounds__(kHistThreads) void k_bucket_hist(const uint32_t *__
     }
 }
 
+// Step 4b: rows by group.  The oriented keys (s << gb) | t are sorted by
+// s >> kGroupBits (stable radix passes over the label bits above
+// kGroupBits); one wave per group of kGroupRows rows then counts the rows,
+// writes their lengths and offsets, and puts every key at its row's next
+// slot inside the group's part of col (rows are sorted on their own
+// afterwards, so the order of the slots does not matter).  Counts and slots
+// are the wave's LDS counters, one add per key.
+constexpr int kGroupBits = 4;
+constexpr int kGroupRows = 1 << kGroupBits;
+constexpr int kGroupUnroll = 4;  // rounds of 64 keys loaded together
+
+__global__ void k_group_bounds(const uint64_t *__restrict__ keys, int64_t m, int shift, int64_t ngroups,
+                               int64_t *__restrict__ gstart) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g <= ngroups;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = 0, hi = m;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)(keys[mid] >> (shift + kGroupBits)) < g)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        gstart[g] = lo;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_group_place(const uint64_t *__restrict__ keys, int shift,
+                                                          const int64_t *__restrict__ gstart, int64_t ngroups,
+                                                          int64_t N, int32_t *__restrict__ rowlen,
+                                                          int64_t *__restrict__ off, int32_t *__restrict__ col) {
+    __shared__ uint32_t ctr[kThreads / 64][kGroupRows];
+    const int lane = __lane_id();
+    uint32_t *c = ctr[threadIdx.x >> 6];
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t mask = (1ull << shift) - 1;
+    constexpr int64_t kStep = 64 * kGroupUnroll;
+    for (int64_t g = wave; g < ngroups; g += nwaves) {
+        const int64_t gs = gstart[g], ge = gstart[g + 1];
+        const int64_t x0 = g << kGroupBits;
+        const int nrows = (int)min((int64_t)kGroupRows, N - x0);
+        if (lane < kGroupRows) c[lane] = 0;
+        wave_lds_sync();
+        // 1. row counts
+        for (int64_t p0 = gs + lane; p0 < ge; p0 += kStep) {
+            uint64_t k[kGroupUnroll];
+#pragma unroll
+            for (int u = 0; u < kGroupUnroll; ++u) {
+                const int64_t p = p0 + u * 64;
+                k[u] = p < ge ? keys[p] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kGroupUnroll; ++u)
+                if (p0 + u * 64 < ge) atomicAdd(&c[(k[u] >> shift) & (kGroupRows - 1)], 1u);
+        }
+        wave_lds_sync();
+        // 2. row starts; lengths and offsets
+        const uint32_t v = lane < kGroupRows ? c[lane] : 0u;
+        const uint32_t start = wave_inclusive_sum(v) - v;
+        if (lane < nrows) {
+            rowlen[x0 + lane] = (int32_t)v;
+            off[x0 + lane] = gs + start;
+        }
+        if (g == ngroups - 1 && lane == 0) off[N] = ge;
+        wave_lds_sync();
+        if (lane < kGroupRows) c[lane] = start;
+        wave_lds_sync();
+        // 3. every key to its row's next slot
+        for (int64_t p0 = gs + lane; p0 < ge; p0 += kStep) {
+            uint64_t k[kGroupUnroll];
+#pragma unroll
+            for (int u = 0; u < kGroupUnroll; ++u) {
+                const int64_t p = p0 + u * 64;
+                k[u] = p < ge ? keys[p] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kGroupUnroll; ++u) {
+                if (p0 + u * 64 < ge) {
+                    const uint32_t slot = atomicAdd(&c[(k[u] >> shift) & (kGroupRows - 1)], 1u);
+                    col[gs + slot] = (int32_t)(k[u] & mask);
+                }
+            }
+        }
+        wave_lds_sync();
+    }
+}
+
 // Step 3a: degree-order keys (g, d, v).
 __global__ void k_rank_keys(const int32_t *__restrict__ deg, int64_t N, const int64_t *__restrict__ node_base, int k,
                             int db, int vb, uint64_t *__restrict__ keys) {
@@ -376,24 +465,6 @@ __global__ void k_orient_keys(const uint64_t *__restrict__ ukeys, int64_t m, int
                 __builtin_nontemporal_store((s << gb) | t, &okeys[i]);
             }
         }
-    }
-}
-
-// Step 5: column entries and row lengths (rows arrive in runs).
-__global__ void k_csr_rows(const uint64_t *__restrict__ okeys, int64_t m, int gb, int32_t *__restrict__ col,
-                           int32_t *__restrict__ rowlen) {
-    const uint64_t mask = (1ull << gb) - 1;
-    const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
-        const int64_t i = base + threadIdx.x;
-        uint64_t k;
-        int64_t sp, s, sn;
-        labels3(okeys, i, m, gb, &k, &sp, &s, &sn);
-        bool whole;
-        const int64_t cnt = run_piece_at_end(s, sp, sn, i < m, lane, &whole);
-        if (cnt) atomicAdd(&rowlen[s], (int32_t)cnt);
-        if (i < m) col[i] = (int32_t)(k & mask);  // stores last, as above
     }
 }
 
@@ -914,9 +985,9 @@ void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing
                            Allocator &al, hipStream_t s, Oriented &out) {
     const int64_t N = pk.N, M_in = pk.M_in;
     // One scratch region for every temporary of the build (bump allocation),
-    // sized from the input: keys 16 B/edge, sort tables < 3 B/edge, node
-    // arrays < 72 B/node, task targets.
-    const size_t arena_bytes = (size_t)M_in * 19 + (size_t)N * 72 + (size_t)bp.workers * 128 + (8u << 20);
+    // sized from the input: keys 16 B/edge, sort tables < 4 B/edge,
+    // node arrays < 80 B/node, task targets.
+    const size_t arena_bytes = (size_t)M_in * 20 + (size_t)N * 80 + (size_t)bp.workers * 128 + (8u << 20);
     void *arena = al.get(arena_bytes);
     Allocator tmp = al;
     tmp.arena = (uint8_t *)arena;
@@ -983,12 +1054,20 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     if (M > 0) {
         k_orient_keys<<<grid_for(M, 4 * kOrientUnroll), kThreads, 0, s>>>(ukeys, M, gb, rank.p, spare);
         TC_LAUNCH_CHECK();
-        // rows by s only (stable): each row keeps input order and is sorted below
-        okeys = radix_sort_u64(spare, ukeys, M, gb, 2 * gb, tmp, s);
-        k_csr_rows<<<grid_for(M, 4), kThreads, 0, s>>>(okeys, M, gb, out.col.p, rowlen.p);
+        // order by s >> kGroupBits, then place each group of rows (in key
+        // order inside a row: rows are sorted below)
+        okeys = gb > kGroupBits ? radix_sort_u64(spare, ukeys, M, gb + kGroupBits, 2 * gb, tmp, s) : spare;
+        const int64_t ngroups = ceil_div(N, (int64_t)kGroupRows);
+        DevBuf<int64_t> gstart(tmp, (size_t)ngroups + 1);
+        k_group_bounds<<<grid_for(ngroups + 1), kThreads, 0, s>>>(okeys, M, gb, ngroups, gstart.p);
         TC_LAUNCH_CHECK();
+        const int64_t gw = std::min<int64_t>(ngroups, (int64_t)device_cu_count() * 64);  // waves
+        k_group_place<<<(unsigned)ceil_div(gw * 64, kThreads), kThreads, 0, s>>>(okeys, gb, gstart.p, ngroups, N,
+                                                                                  rowlen.p, out.off.p, out.col.p);
+        TC_LAUNCH_CHECK();
+    } else {
+        exclusive_scan(rowlen.p, out.off.p, N, true, tmp, s);
     }
-    exclusive_scan(rowlen.p, out.off.p, N, true, tmp, s);
 
     // ---- 6. costs, wide lists, task table
     out.deg = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(N, 1));

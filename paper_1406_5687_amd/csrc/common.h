@@ -253,6 +253,14 @@ __device__ __forceinline__ int64_t uniform64(int64_t x) { return readlane64(x, _
 
 // Lanes of the wave holding the same 9-bit value v (bit 8 flags an inactive
 // lane), found with one ballot per bit.
+// Workgroups go to the 8 XCDs round-robin by index.  Item of workgroup b
+// (b < nb): each XCD takes one contiguous range of the nb items, so data that
+// neighbouring items share stays in one XCD's L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+    const int64_t x = b & 7, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 __device__ __forceinline__ uint64_t match_peers9(uint32_t v) {
     uint64_t peers = ~0ull;
 #pragma unroll

@@ -24,14 +24,6 @@ __device__ __forceinline__ int64_t key_index(int64_t tile_base, int wave, int r,
     return tile_base + (int64_t)wave * 64 * kSortRounds + r * 64 + lane;
 }
 
-// Workgroups go to the 8 XCDs round-robin by index.  Tile of workgroup b: each
-// XCD takes one contiguous range of tiles, so the digit-table entries and the
-// output runs that neighbouring tiles share sit in the same L2.
-__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
-    const int64_t x = b & 7, q = nb >> 3, r = nb & 7;
-    return x * q + (x < r ? x : r) + (b >> 3);
-}
-
 // Digit of a key in the pass at `shift`: `bits` (<= 8) bits, so that a
 // range whose width is not a multiple of 8 ignores the bits above it.
 template <class K>
@@ -47,8 +39,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K *__restrict
     for (int i = threadIdx.x; i < kSortWaves * kRadix; i += kSortThreads) (&hw[0][0])[i] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t t = xcd_tile(blockIdx.x, nblocks);
-    const int64_t tile = t * kSortTile;
+    const int64_t t = xcd_tile(blockIdx.x, nblocks);  // digit-table entries and output runs of
+    const int64_t tile = t * kSortTile;               // neighbouring tiles share one L2
     // all of the lane's keys are loaded before any is ranked
     K kk[kSortRounds];
 #pragma unroll
