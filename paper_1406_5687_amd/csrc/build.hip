@@ -18,6 +18,7 @@
 //                             Eq. (1)/(2) targets, one binary search per task boundary
 #include <algorithm>
 #include <cstring>
+#include <functional>
 
 #include "internal.h"
 
@@ -646,6 +647,44 @@ __global__ __launch_bounds__(kThreads) void k_sort_rows(const int64_t *__restric
     }
 }
 
+// Total PRIOR cost of the rows scheduled for single waves (length <= small),
+// before any cost is computed per row.  Over all rows the PRIOR costs add up
+// to sum_v dhat_v * d_v (pair (v, t) contributes dhat_v to f(v) and dhat_t
+// to f(v); dhat_t is counted once for each of t's d_t - dhat_t in-pairs);
+// each longer row's own cost is subtracted, one wave per row.
+__global__ void k_prior_total(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
+                              const int32_t *__restrict__ deg, int64_t N, int small,
+                              unsigned long long *__restrict__ acc) {
+    const int lane = __lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    int64_t part = 0;
+    for (int64_t g0 = wave * 64; g0 < N; g0 += nwaves * 64) {
+        const int64_t r = g0 + lane;
+        int64_t r0 = 0, a = 0;
+        if (r < N) {
+            r0 = off[r];
+            a = off[r + 1] - r0;
+            part += a * (int64_t)deg[r];
+        }
+        uint64_t wide = __ballot(a > small);
+        while (wide) {
+            const int l = __ffsll((unsigned long long)wide) - 1;
+            wide &= wide - 1;
+            const int64_t w0 = readlane64(r0, l), wa = readlane64(a, l);
+            int64_t c = 0;
+            for (int64_t p = lane; p < wa; p += 64) {
+                const int32_t t = col[w0 + p];
+                c += off[t + 1] - off[t];
+            }
+            c = wave_sum(c);
+            if (lane == 0) part -= wa * wa + c;
+        }
+    }
+    part = wave_sum(part);
+    if (lane == 0) atomicAdd(acc, (unsigned long long)part);
+}
+
 // PRIOR costs of the long rows (one wave per row).
 __global__ void k_long_costs(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
                              const int32_t *__restrict__ long_rows, int64_t L, const int32_t *__restrict__ dh,
@@ -935,13 +974,22 @@ struct PinnedStage {
     }
 };
 thread_local PinnedStage t_stage;
+thread_local PinnedStage t_total;  // the early cost total
+
+struct EventGuard {
+    hipEvent_t e = nullptr;
+    ~EventGuard() {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
 }  // namespace
 
 // Sorts every row of (off, col) ascending.  ka / kb: scratch of cap keys each.
 // With f non-null, also writes the PRIOR cost of every row into f (dh: row
 // lengths).
 void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka, uint64_t *kb, int64_t cap,
-               const int32_t *dh, int64_t *f, Allocator &tmp, hipStream_t s) {
+               const int32_t *dh, int64_t *f, Allocator &tmp, hipStream_t s,
+               const std::function<void()> &while_sorting) {
     if (N <= 0) return;
     DevBuf<int32_t> long_rows(tmp, (size_t)N);
     DevBuf<unsigned int> nlong(tmp, 1);
@@ -950,6 +998,7 @@ void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka
     k_sort_rows<<<(unsigned)ceil_div(waves * 64, kThreads), kThreads, 0, s>>>(off, N, col, long_rows.p, nlong.p,
                                                                                dh, f);
     TC_LAUNCH_CHECK();
+    if (while_sorting) while_sorting();  // host work that overlaps the row sort
     unsigned int L = 0;
     d2h(&L, nlong.p, 1, s);
     TC_HIP(hipStreamSynchronize(s));
@@ -979,7 +1028,8 @@ void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka
 void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp, Allocator &al,
                 Allocator &tmp, hipStream_t s, Oriented &out);
 void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
-                   Oriented &out, const uint64_t *okeys, int gb, int64_t *f_prior = nullptr);
+                   Oriented &out, const uint64_t *okeys, int gb, int64_t *f_prior = nullptr,
+                   PresetTargets *pre = nullptr);
 
 void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
                            Allocator &al, hipStream_t s, Oriented &out) {
@@ -1076,20 +1126,43 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
         TC_LAUNCH_CHECK();
     }
     if (bp.cost_fn == TC_COST_PRIOR && M > 0) {
-        // the row sort adds up the PRIOR costs on the way
+        // The row sort adds up the PRIOR costs on the way.  Their total is
+        // known before it (k_prior_total), so the host computes the task
+        // targets while the device sorts.
         DevBuf<int64_t> f(tmp, (size_t)N);
-        sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, rowlen.p, f.p, tmp, s);
-        schedule_into(pk, bp, al, tmp, s, out, nullptr, gb, f.p);
+        DevBuf<unsigned long long> acc(tmp, 1);
+        fill_zero(acc.p, 8, s);
+        const int64_t tw = std::min<int64_t>(ceil_div(N, 64), (int64_t)device_cu_count() * 64);
+        k_prior_total<<<(unsigned)ceil_div(tw * 64, kThreads), kThreads, 0, s>>>(out.off.p, out.col.p, out.deg.p,
+                                                                                  N, bp.small_max, acc.p);
+        TC_LAUNCH_CHECK();
+        PresetTargets pre;
+        auto *htot = static_cast<unsigned long long *>(t_total.get(sizeof(unsigned long long)));
+        EventGuard ev;
+        if (htot) {
+            TC_HIP(hipMemcpyAsync(htot, acc.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+            TC_HIP(hipEventCreateWithFlags(&ev.e, hipEventDisableTiming));
+            TC_HIP(hipEventRecord(ev.e, s));
+        }
+        BuildParams bpr = bp;
+        bpr.rounds = bp.rounds > 0 ? bp.rounds : auto_rounds(pk.k, M);
+        sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, rowlen.p, f.p, tmp, s, [&] {
+            if (!htot) return;
+            TC_HIP(hipEventSynchronize(ev.e));
+            pre.total = (int64_t)*htot;
+            pre.targets = schedule_targets(pre.total, bpr);
+        });
+        schedule_into(pk, bp, al, tmp, s, out, nullptr, gb, f.p, &pre);
     } else {
         schedule_into(pk, bp, al, tmp, s, out, okeys, gb);
-        if (M > 0) sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, nullptr, nullptr, tmp, s);
+        if (M > 0) sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, nullptr, nullptr, tmp, s, nullptr);
     }
 }
 
 // Step 6 proper.  okeys (sorted pair keys) speed up the edge costs when the
 // build still holds them; otherwise costs are computed row by row.
 void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
-                   Oriented &out, const uint64_t *okeys, int gb, int64_t *f_prior) {
+                   Oriented &out, const uint64_t *okeys, int gb, int64_t *f_prior, PresetTargets *pre) {
     const int64_t N = pk.N, M = out.M;
     DevBuf<int64_t> f_own;
     int64_t *f = f_prior;  // PRIOR costs computed by the caller, else computed here
@@ -1121,7 +1194,7 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
     BuildParams bpr = bp;
     bpr.rounds = bp.rounds > 0 ? bp.rounds : auto_rounds(pk.k, M);
     out.rounds = bpr.rounds;
-    schedule_sources(f, wmed.p, wlarge.p, N, pk.k, out.node_base.p, bpr, al, tmp, s, sc, maxd.p, &out.max_dhat);
+    schedule_sources(f, wmed.p, wlarge.p, N, pk.k, out.node_base.p, bpr, al, tmp, s, sc, maxd.p, &out.max_dhat, pre);
     out.bnd = std::move(sc.bnd);
     out.gid = std::move(sc.gid);
     out.big = std::move(sc.big);
@@ -1131,9 +1204,20 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
     out.nbig = sc.nbig;
 }
 
+std::vector<int64_t> schedule_targets(int64_t total, const BuildParams &bp) {
+    int64_t min_chunk = bp.min_chunk;
+    if (min_chunk <= 0) {
+        // automatic floor: about 1/64 of an initial task's cost, at least 256
+        min_chunk = std::max<int64_t>(256, total / ((int64_t)bp.workers * 128 + 1));
+    }
+    const int64_t W = (int64_t)bp.workers * std::max(1, bp.rounds);
+    if (W > INT32_MAX) throw Error(TC_ERR_INVALID_ARG, "workers * rounds too large");
+    return task_targets(total, (int32_t)W, min_chunk, bp.static_chunks != 0);
+}
+
 void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wlarge, int64_t N, int k,
                       const int64_t *node_base, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
-                      Schedule &out, const int32_t *maxd_dev, int32_t *maxd_host) {
+                      Schedule &out, const int32_t *maxd_dev, int32_t *maxd_host, PresetTargets *pre) {
     DevBuf<int64_t> F(tmp, (size_t)N + 1);
     DevBuf<int64_t> pmed(tmp, (size_t)N + 1), plarge(tmp, (size_t)N + 1);
     exclusive_scan(f, F.p, N, true, tmp, s);
@@ -1161,14 +1245,8 @@ void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wl
         TC_LAUNCH_CHECK();
     }
 
-    int64_t min_chunk = bp.min_chunk;
-    if (min_chunk <= 0) {
-        // automatic floor: about 1/64 of an initial task's cost, at least 256
-        min_chunk = std::max<int64_t>(256, out.total_cost / ((int64_t)bp.workers * 128 + 1));
-    }
-    const int64_t W = (int64_t)bp.workers * std::max(1, bp.rounds);
-    if (W > INT32_MAX) throw Error(TC_ERR_INVALID_ARG, "workers * rounds too large");
-    std::vector<int64_t> tg = task_targets(out.total_cost, (int32_t)W, min_chunk, bp.static_chunks != 0);
+    std::vector<int64_t> tg = (pre && pre->total == out.total_cost) ? std::move(pre->targets)
+                                                                      : schedule_targets(out.total_cost, bp);
     const int64_t ntg = (int64_t)tg.size();
     DevBuf<int32_t> bnd(al, (size_t)ntg + 1);
     task_bounds(F.p, N, tg, bnd.p, tmp, s);
@@ -1260,7 +1338,9 @@ void degree_rank(const int32_t *deg, int64_t N, const int64_t *node_base, int k,
     DevBuf<uint64_t> ra(tmp, (size_t)N), rb(tmp, (size_t)N);
     k_rank_keys<<<grid_for(N, 4), kThreads, 0, s>>>(deg, N, node_base, k, db, vb, ra.p);
     TC_LAUNCH_CHECK();
-    uint64_t *sorted = radix_sort_u64(ra.p, rb.p, N, 0, kb_bits + db + vb, tmp, s);
+    // keys are made in label order, so v already ascends within every
+    // (g, d): a stable sort by (g, d) alone gives the (g, d, v) order
+    uint64_t *sorted = radix_sort_u64(ra.p, rb.p, N, vb, kb_bits + db + vb, tmp, s);
     k_rank_from_sorted<<<grid_for(N, 4), kThreads, 0, s>>>(sorted, N, node_base, db, vb, perm, rank);
     TC_LAUNCH_CHECK();
 }

@@ -86,9 +86,18 @@ struct Schedule {
     int64_t nmed = 0;
     int64_t nbig = 0;
 };
+// Eq. (1)/(2) cost targets of a schedule (bp.rounds resolved) for a total cost.
+std::vector<int64_t> schedule_targets(int64_t total, const BuildParams &bp);
+// Targets computed ahead (on the host, while the device works) for a total
+// cost; schedule_sources takes them when its total is the same.
+struct PresetTargets {
+    int64_t total = -1;
+    std::vector<int64_t> targets;
+};
 void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wlarge, int64_t N, int k,
                       const int64_t *node_base, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
-                      Schedule &out, const int32_t *maxd_dev = nullptr, int32_t *maxd_host = nullptr);
+                      Schedule &out, const int32_t *maxd_dev = nullptr, int32_t *maxd_host = nullptr,
+                      PresetTargets *pre = nullptr);
 std::vector<int64_t> task_targets(int64_t total, int32_t W, int64_t min_chunk, bool static_chunks = false);
 // bnd[0] = 0, bnd[j+1] = first x in [0, N] with F[x] >= targets[j] (targets < 0: N)
 void task_bounds(const int64_t *F, int64_t N, const std::vector<int64_t> &targets, int32_t *bnd, Allocator &tmp,
