@@ -681,8 +681,16 @@ __global__ void k_prior_total(const int64_t *__restrict__ off, const int32_t *__
             if (lane == 0) part -= wa * wa + c;
         }
     }
+    // one add per workgroup: adds to one address are serialised
+    __shared__ int64_t wpart[kThreads / 64];
     part = wave_sum(part);
-    if (lane == 0) atomicAdd(acc, (unsigned long long)part);
+    if (lane == 0) wpart[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < kThreads / 64; ++w) t += wpart[w];
+        atomicAdd(acc, (unsigned long long)t);
+    }
 }
 
 // PRIOR costs of the long rows (one wave per row).
@@ -810,8 +818,16 @@ __global__ void k_node_costs(const int64_t *__restrict__ off, const int32_t *__r
         wide_med[r] = (w && dh <= med_max) ? 1u : 0u;
         wide_large[r] = (w && dh > med_max) ? 1u : 0u;
     }
+    // one atomic per workgroup: atomics to one address are serialised
+    __shared__ int32_t wmax[kThreads / 64];
     local_max = wave_reduce_max(local_max);
-    if (__lane_id() == 0) atomicMax(max_dhat, local_max);
+    if (__lane_id() == 0) wmax[threadIdx.x >> 6] = local_max;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t m = 0;
+        for (int w = 0; w < kThreads / 64; ++w) m = max(m, wmax[w]);
+        atomicMax(max_dhat, m);
+    }
 }
 
 __global__ void k_totals(const int64_t *a, const int64_t *b, const int64_t *c, const int32_t *d, int64_t *out) {
@@ -1132,7 +1148,7 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
         DevBuf<int64_t> f(tmp, (size_t)N);
         DevBuf<unsigned long long> acc(tmp, 1);
         fill_zero(acc.p, 8, s);
-        const int64_t tw = std::min<int64_t>(ceil_div(N, 64), (int64_t)device_cu_count() * 64);
+        const int64_t tw = std::min<int64_t>(ceil_div(N, 64), (int64_t)device_cu_count() * 8);  // waves
         k_prior_total<<<(unsigned)ceil_div(tw * 64, kThreads), kThreads, 0, s>>>(out.off.p, out.col.p, out.deg.p,
                                                                                   N, bp.small_max, acc.p);
         TC_LAUNCH_CHECK();
@@ -1186,7 +1202,7 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
     DevBuf<int32_t> maxd(tmp, 1);
     fill_zero(maxd.p, 4, s);
     if (N > 0) {
-        k_node_costs<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, out.deg.p, N, bp.cost_fn, bp.small_max,
+        k_node_costs<<<grid_for(N, 16), kThreads, 0, s>>>(out.off.p, out.deg.p, N, bp.cost_fn, bp.small_max,
                                                           max_medium_list(), f, wmed.p, wlarge.p, maxd.p);
         TC_LAUNCH_CHECK();
     }
