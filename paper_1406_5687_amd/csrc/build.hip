@@ -53,7 +53,7 @@ __device__ __forceinline__ int upper_bound_i64(const int64_t *a, int n, int64_t 
     return lo;
 }
 
-// Step 1a: canonical keys.  err bit 0: id out of range.
+// Step 1a: canonical keys.  err bit 0: id out of range; bit 1: a loop.
 // Each thread takes kEdgeUnroll edges at a time: all endpoint loads are issued
 // before the first key is stored.
 constexpr int kEdgeUnroll = 4;
@@ -97,8 +97,10 @@ __global__ void k_edge_keys(const int32_t *__restrict__ src, const int32_t *__re
             key[j] = kInvalid;
             if (e >= m_in) continue;
             if (u[j] < 0 || v[j] < 0 || u[j] >= ng[j] || v[j] >= ng[j]) {
-                bad = 1u;
-            } else if (u[j] != v[j]) {
+                bad |= 1u;
+            } else if (u[j] == v[j]) {
+                bad |= 2u;  // a loop: dropped
+            } else {
                 const int32_t lo = u[j] < v[j] ? u[j] : v[j], hi = u[j] < v[j] ? v[j] : u[j];
                 key[j] = ((uint64_t)(nb[j] + lo) << gb) | (uint64_t)(nb[j] + hi);
             }
@@ -108,7 +110,7 @@ __global__ void k_edge_keys(const int32_t *__restrict__ src, const int32_t *__re
             const int64_t e = e0 + (int64_t)j * blockDim.x;
             if (e < m_in) keys[e] = key[j];
         }
-        if (bad) atomicOr(err, 1u);
+        if (bad) atomicOr(err, bad);
     }
 }
 
@@ -489,8 +491,16 @@ __device__ __forceinline__ void cswap(int32_t &a, int32_t &b) {
 // Cost kind PRIOR of a row of length a: a * a + the row lengths of its
 // targets (Section IV-B).  Rows sorted here add it up from the entries they
 // already hold (f non-null), so no separate pass over the pairs is needed.
+// Repeated entries in a sorted row mean a repeated edge in the input (only
+// possible when the canonical sort was skipped): one flag for the build.
+// Called by the whole wave.
+__device__ __forceinline__ void note_repeat(bool repeat, unsigned int *__restrict__ dup) {
+    if (__ballot(repeat) && __lane_id() == 0) atomicOr(dup, 1u);
+}
+
 __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col, int64_t r0, int32_t a, int lane,
-                                              const int32_t *__restrict__ dh, int64_t *__restrict__ f, int64_t row) {
+                                              const int32_t *__restrict__ dh, int64_t *__restrict__ f, int64_t row,
+                                              unsigned int *__restrict__ dup) {
     if (a <= kShortRow) {
         int32_t x = lane < a ? col[r0 + lane] : INT32_MAX;
         if (f) {
@@ -507,6 +517,7 @@ __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col, int64_t
             }
         }
         if (lane < a) col[r0 + lane] = x;
+        note_repeat(lane + 1 < a && x == __shfl_down(x, 1, 64), dup);
         return;
     }
     int32_t v[4];
@@ -553,16 +564,24 @@ __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col, int64_t
         const int i = lane * 4 + j;
         if (i < a) col[r0 + i] = v[j];
     }
+    bool rep = false;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) rep |= lane * 4 + j + 1 < a && v[j] == v[j + 1];
+    const int32_t nx = __shfl_down(v[0], 1, 64);
+    rep |= lane < 63 && lane * 4 + 4 < a && v[3] == nx;
+    note_repeat(rep, dup);
 }
 
 __global__ __launch_bounds__(kThreads) void k_sort_rows(const int64_t *__restrict__ off, int64_t N,
                                                         int32_t *__restrict__ col, int32_t *__restrict__ long_rows,
                                                         unsigned int *__restrict__ nlong,
-                                                        const int32_t *__restrict__ dh, int64_t *__restrict__ f) {
+                                                        const int32_t *__restrict__ dh, int64_t *__restrict__ f,
+                                                        unsigned int *__restrict__ dup) {
     const int lane = __lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t g0 = wave * 64; g0 < N; g0 += nwaves * 64) {
+        bool rep = false;
         const int64_t r = g0 + lane;
         int64_t r0 = 0;
         int32_t a = 0;
@@ -593,8 +612,11 @@ __global__ __launch_bounds__(kThreads) void k_sort_rows(const int64_t *__restric
 #pragma unroll
                 for (int j = 0; j < kTinyRow; ++j)
                     if (j < a) col[r0 + j] = x[j];
+#pragma unroll
+                for (int j = 0; j + 1 < kTinyRow; ++j) rep |= j + 1 < a && x[j] == x[j + 1];
             }
         }
+        note_repeat(rep, dup);
         // rows of up to 64 entries, one after another by the whole wave; the
         // next row's entries are loaded while this one is sorted
         uint64_t rest = __ballot(a > kTinyRow && a <= kShortRow);
@@ -626,6 +648,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_rows(const int64_t *__restric
                     }
                 }
                 if (lane < ac) col[rc + lane] = xc;
+                note_repeat(lane + 1 < ac && xc == __shfl_down(xc, 1, 64), dup);
                 if (f) {
                     const int64_t c = wave_sum(dv);
                     if (lane == 0) f[g0 + l] = (int64_t)ac * ac + c;
@@ -641,7 +664,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_rows(const int64_t *__restric
         while (rest) {
             const int l = __ffsll((unsigned long long)rest) - 1;
             rest &= rest - 1;
-            wave_sort_row(col, readlane64(r0, l), readlane32(a, l), lane, dh, f, g0 + l);
+            wave_sort_row(col, readlane64(r0, l), readlane32(a, l), lane, dh, f, g0 + l, dup);
         }
         if (a > kMidRow) long_rows[atomicAdd(nlong, 1u)] = (int32_t)r;
     }
@@ -734,13 +757,16 @@ __global__ void k_long_keys(const int64_t *__restrict__ off, const int32_t *__re
 
 __global__ void k_long_write(const uint64_t *__restrict__ keys, int64_t E, int gb, const int64_t *__restrict__ off,
                              const int32_t *__restrict__ long_rows, const int64_t *__restrict__ epos,
-                             int32_t *__restrict__ col) {
+                             int32_t *__restrict__ col, unsigned int *__restrict__ dup) {
     const uint64_t mask = (1ull << gb) - 1;
+    bool rep = false;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < E; q += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t k = keys[q];
         const int64_t i = (int64_t)(k >> gb);
         col[off[long_rows[i]] + (q - epos[i])] = (int32_t)(k & mask);
+        rep |= q > 0 && keys[q - 1] == k;  // (row, entry) keys: equal neighbours repeat an entry
     }
+    note_repeat(rep, dup);
 }
 
 // Step 6a: per-node cost f (degree-order labels) over stored pairs (s, t).
@@ -1004,7 +1030,7 @@ struct EventGuard {
 // With f non-null, also writes the PRIOR cost of every row into f (dh: row
 // lengths).
 void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka, uint64_t *kb, int64_t cap,
-               const int32_t *dh, int64_t *f, Allocator &tmp, hipStream_t s,
+               const int32_t *dh, int64_t *f, unsigned int *dup, Allocator &tmp, hipStream_t s,
                const std::function<void()> &while_sorting) {
     if (N <= 0) return;
     DevBuf<int32_t> long_rows(tmp, (size_t)N);
@@ -1012,7 +1038,7 @@ void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka
     fill_zero(nlong.p, 4, s);
     const int64_t waves = std::min<int64_t>(ceil_div(N, 64), (int64_t)device_cu_count() * 64);
     k_sort_rows<<<(unsigned)ceil_div(waves * 64, kThreads), kThreads, 0, s>>>(off, N, col, long_rows.p, nlong.p,
-                                                                               dh, f);
+                                                                               dh, f, dup);
     TC_LAUNCH_CHECK();
     if (while_sorting) while_sorting();  // host work that overlaps the row sort
     unsigned int L = 0;
@@ -1037,7 +1063,7 @@ void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka
     TC_LAUNCH_CHECK();
     const int lb = std::max(1, bits_for((uint64_t)(L - 1)));
     uint64_t *sorted = radix_sort_u64(ka, kb, E, 0, gb + lb, tmp, s);
-    k_long_write<<<grid_for(E, 4), kThreads, 0, s>>>(sorted, E, gb, off, long_rows.p, epos.p, col);
+    k_long_write<<<grid_for(E, 4), kThreads, 0, s>>>(sorted, E, gb, off, long_rows.p, epos.p, col, dup);
     TC_LAUNCH_CHECK();
 }
 
@@ -1068,8 +1094,18 @@ void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing
     al.put(arena, arena_bytes);
 }
 
-void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp, Allocator &al,
-                Allocator &tmp, hipStream_t s, Oriented &out) {
+namespace {
+void add_endpoint_counts(const uint64_t *keys, int64_t M, int gb, int32_t *deg, int64_t N, uint32_t *spare,
+                         Allocator &tmp, hipStream_t s);
+}  // namespace
+
+// One build.  simple: the input is taken to be a simple graph (no edge
+// twice, no loop): degrees are counted from the endpoints as given and the
+// canonical sort is skipped.  Returns false when that assumption fails (a
+// loop in the input, or a repeated entry in a sorted row); out is then
+// incomplete and the caller builds again without it.
+static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
+                       Allocator &al, Allocator &tmp, hipStream_t s, Oriented &out, bool simple) {
     const int64_t N = pk.N, M_in = pk.M_in;
     const int k = pk.k;
     const int gb = std::max(1, bits_for((uint64_t)std::max<int64_t>(N - 1, 1)));  // bits of a packed label
@@ -1078,7 +1114,7 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     TC_HIP(hipMemcpyAsync(out.node_base.p, pk.node_base.data(), (k + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
     DevBuf<int64_t> edge_base(tmp, (size_t)k + 1);
     TC_HIP(hipMemcpyAsync(edge_base.p, pk.edge_base.data(), (k + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    DevBuf<uint32_t> err(tmp, 4);
+    DevBuf<uint32_t> err(tmp, 4);  // [0]: input errors, [1]: repeated entry
     fill_zero(err.p, 16, s);
 
     // ---- 1. canonical edge set
@@ -1087,16 +1123,25 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     DevBuf<uint64_t> kb(tmp, (size_t)std::max<int64_t>(M_in, 1));
     uint64_t *ukeys = kb.p;
     if (M_in > 0) {
-        k_edge_keys<<<grid_for(M_in, 4 * kEdgeUnroll), kThreads, 0, s>>>(src, dst, M_in, edge_base.p, out.node_base.p, k, gb, ka.p,
-                                                            err.p);
+        k_edge_keys<<<grid_for(M_in, 4 * kEdgeUnroll), kThreads, 0, s>>>(src, dst, M_in, edge_base.p,
+                                                                          out.node_base.p, k, gb, ka.p, err.p);
         TC_LAUNCH_CHECK();
-        uint64_t *sorted = radix_sort_u64(ka.p, kb.p, M_in, 0, 2 * gb, tmp, s);
-        uint64_t *other = sorted == ka.p ? kb.p : ka.p;
-        M = unique_sorted_keys(sorted, M_in, other, &ukeys, tmp, s);  // synchronises
         uint32_t herr = 0;
-        d2h(&herr, err.p, 1, s);
-        TC_HIP(hipStreamSynchronize(s));
-        if (herr & 1u) throw Error(TC_ERR_ID_RANGE, "an edge endpoint is outside 0..n-1 of its graph");
+        if (simple) {
+            d2h(&herr, err.p, 1, s);
+            TC_HIP(hipStreamSynchronize(s));
+            if (herr & 1u) throw Error(TC_ERR_ID_RANGE, "an edge endpoint is outside 0..n-1 of its graph");
+            if (herr & 2u) return false;  // a loop: take the canonical path
+            M = M_in;
+            ukeys = ka.p;
+        } else {
+            uint64_t *sorted = radix_sort_u64(ka.p, kb.p, M_in, 0, 2 * gb, tmp, s);
+            uint64_t *other = sorted == ka.p ? kb.p : ka.p;
+            M = unique_sorted_keys(sorted, M_in, other, &ukeys, tmp, s);  // synchronises
+            d2h(&herr, err.p, 1, s);
+            TC_HIP(hipStreamSynchronize(s));
+            if (herr & 1u) throw Error(TC_ERR_ID_RANGE, "an edge endpoint is outside 0..n-1 of its graph");
+        }
     }
     out.M = M;
     uint64_t *spare = ukeys == ka.p ? kb.p : ka.p;
@@ -1104,7 +1149,10 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
     // ---- 2. degrees
     DevBuf<int32_t> deg(tmp, (size_t)std::max<int64_t>(N, 1));
     fill_zero(deg.p, deg.bytes(), s);
-    add_degrees(ukeys, M, gb, deg.p, N, reinterpret_cast<uint32_t *>(spare), tmp, s);  // spare: >= 2 M words
+    if (simple)
+        add_endpoint_counts(ukeys, M, gb, deg.p, N, reinterpret_cast<uint32_t *>(spare), tmp, s);
+    else
+        add_degrees(ukeys, M, gb, deg.p, N, reinterpret_cast<uint32_t *>(spare), tmp, s);  // spare: >= 2 M words
 
     // ---- 3. degree order
     out.perm = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(N, 1));
@@ -1141,6 +1189,7 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
         k_gather_deg<<<grid_for(N, 4), kThreads, 0, s>>>(deg.p, out.perm.p, N, out.deg.p);
         TC_LAUNCH_CHECK();
     }
+    uint32_t *dup = err.p + 1;
     if (bp.cost_fn == TC_COST_PRIOR && M > 0) {
         // The row sort adds up the PRIOR costs on the way.  Their total is
         // known before it (k_prior_total), so the host computes the task
@@ -1162,7 +1211,7 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
         }
         BuildParams bpr = bp;
         bpr.rounds = bp.rounds > 0 ? bp.rounds : auto_rounds(pk.k, M);
-        sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, rowlen.p, f.p, tmp, s, [&] {
+        sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, rowlen.p, f.p, dup, tmp, s, [&] {
             if (!htot) return;
             TC_HIP(hipEventSynchronize(ev.e));
             pre.total = (int64_t)*htot;
@@ -1171,8 +1220,26 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
         schedule_into(pk, bp, al, tmp, s, out, nullptr, gb, f.p, &pre);
     } else {
         schedule_into(pk, bp, al, tmp, s, out, okeys, gb);
-        if (M > 0) sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, nullptr, nullptr, tmp, s, nullptr);
+        if (M > 0) sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, nullptr, nullptr, dup, tmp, s, nullptr);
     }
+    if (simple && M > 0) {
+        uint32_t hdup = 0;
+        d2h(&hdup, dup, 1, s);
+        TC_HIP(hipStreamSynchronize(s));
+        if (hdup) return false;  // an edge given twice: take the canonical path
+    }
+    return true;
+}
+
+// Most inputs are simple graphs; for them the first pass is the build.  A
+// loop or a repeated edge sends the build down the canonical path (sort and
+// unique selection of the pairs) from the start.
+void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp, Allocator &al,
+                Allocator &tmp, hipStream_t s, Oriented &out) {
+    const size_t mark = tmp.arena_used;
+    if (build_pass(src, dst, pk, bp, al, tmp, s, out, true)) return;
+    tmp.arena_used = mark;  // every scratch buffer of the first pass is released
+    build_pass(src, dst, pk, bp, al, tmp, s, out, false);
 }
 
 // Step 6 proper.  okeys (sorted pair keys) speed up the edge costs when the
@@ -1327,6 +1394,43 @@ int64_t unique_sorted_keys(uint64_t *sorted, int64_t n, uint64_t *out, uint64_t 
     return M;
 }
 
+namespace {
+// deg[x] += occurrences of x in vals[0..M) (labels below N < 2^gb): the
+// values are grouped by bucket (label bits above kBinBits; vals_tmp holds M
+// more), then each bucket is counted in LDS.
+void histogram_add(uint32_t *vals, uint32_t *vals_tmp, int64_t M, int gb, int32_t *deg, int64_t N, Allocator &tmp,
+                   hipStream_t s) {
+    uint32_t *hs = gb > kBinBits ? radix_sort_u32(vals, vals_tmp, M, kBinBits, gb, tmp, s) : vals;
+    const int64_t nbuckets = gb > kBinBits ? (int64_t)1 << (gb - kBinBits) : 1;
+    const int64_t per_group = (int64_t)1 << 17;  // values per workgroup, about
+    const int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, ceil_div(M, nbuckets * per_group)));
+    k_bucket_hist<<<(unsigned)(nbuckets * splits), kHistThreads, 0, s>>>(hs, M, splits, N, deg);
+    TC_LAUNCH_CHECK();
+}
+
+// One endpoint of every pair key: the lower (hi == 0) or the upper label.
+__global__ void k_endpoint(const uint64_t *__restrict__ keys, int64_t m, int gb, int hi,
+                           uint32_t *__restrict__ out) {
+    const uint64_t mask = (1ull << gb) - 1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = __builtin_nontemporal_load(&keys[i]);
+        out[i] = (uint32_t)(hi ? (k & mask) : (k >> gb));
+    }
+}
+
+// Degrees of a simple graph given as pair keys in any order: the number of
+// keys each label is an endpoint of.
+void add_endpoint_counts(const uint64_t *keys, int64_t M, int gb, int32_t *deg, int64_t N, uint32_t *spare,
+                         Allocator &tmp, hipStream_t s) {
+    if (M <= 0) return;
+    for (int hi = 0; hi < 2; ++hi) {
+        k_endpoint<<<grid_for(M, 4), kThreads, 0, s>>>(keys, M, gb, hi, spare);  // spare: 2 M words
+        TC_LAUNCH_CHECK();
+        histogram_add(spare, spare + M, M, gb, deg, N, tmp, s);
+    }
+}
+}  // namespace
+
 void add_degrees(const uint64_t *ukeys, int64_t M, int gb, int32_t *deg, int64_t N, uint32_t *spare, Allocator &tmp,
                  hipStream_t s) {
     if (M <= 0) return;
@@ -1334,14 +1438,7 @@ void add_degrees(const uint64_t *ukeys, int64_t M, int gb, int32_t *deg, int64_t
     uint32_t *hi_tmp = hi + M;
     k_degrees_lo<<<grid_for(M, 4), kThreads, 0, s>>>(ukeys, M, gb, deg, hi);
     TC_LAUNCH_CHECK();
-    // group the upper endpoints by bucket (label bits above kBinBits), then
-    // count each bucket in LDS
-    uint32_t *hs = gb > kBinBits ? radix_sort_u32(hi, hi_tmp, M, kBinBits, gb, tmp, s) : hi;
-    const int64_t nbuckets = gb > kBinBits ? (int64_t)1 << (gb - kBinBits) : 1;
-    const int64_t per_group = (int64_t)1 << 17;  // values per workgroup, about
-    const int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, ceil_div(M, nbuckets * per_group)));
-    k_bucket_hist<<<(unsigned)(nbuckets * splits), kHistThreads, 0, s>>>(hs, M, splits, N, deg);
-    TC_LAUNCH_CHECK();
+    histogram_add(hi, hi_tmp, M, gb, deg, N, tmp, s);
 }
 
 void degree_rank(const int32_t *deg, int64_t N, const int64_t *node_base, int k, int32_t max_n, int32_t *perm,

@@ -270,6 +270,43 @@ def test_relabel_and_input_noise(tc):
     np.testing.assert_array_equal(tv3, tv)
 
 
+def _complete(n):
+    iu = np.triu_indices(n, 1)
+    return graphgen.EdgeList(n, iu[0].astype(np.int32), iu[1].astype(np.int32), f"K{n}")
+
+
+@pytest.mark.parametrize("maker,repeats", [
+    (lambda: graphgen.preferential_attachment(5000, 10, 3), 1),
+    (lambda: graphgen.preferential_attachment(5000, 10, 3), 37),
+    (lambda: graphgen.preferential_attachment(5000, 10, 3), 4000),
+    (lambda: _complete(400), 1),       # rows longer than 256: the long-row sort sees the repeat
+    (lambda: _complete(400), 500),
+], ids=["pa-1", "pa-37", "pa-4000", "k400-1", "k400-500"])
+def test_repeated_edges_without_loops(tc, maker, repeats):
+    # A simple input is built without sorting the pairs; an edge given twice
+    # (here without any loop, so only the sorted rows reveal it) must send the
+    # build back to the canonical path: adjacency, schedule and counts as for
+    # the edges given once.
+    g = maker()
+    rng = np.random.default_rng(repeats)
+    pick = rng.integers(0, g.m, repeats)
+    flip = rng.random(repeats) < 0.5
+    s = np.concatenate([g.src, np.where(flip, g.dst[pick], g.src[pick])]).astype(np.int32)
+    d = np.concatenate([g.dst, np.where(flip, g.src[pick], g.dst[pick])]).astype(np.int32)
+    with tc.build_oriented([(g.n, g.src, g.dst)]) as h1, tc.build_oriented([(g.n, s, d)]) as h2:
+        a1, a2 = h1.export_csr(), h2.export_csr()
+        for x, y in zip(a1, a2):
+            np.testing.assert_array_equal(x, y)
+        i1, i2 = h1.info(), h2.info()
+        assert i1["m"] == i2["m"] == g.m
+        assert i1["tasks"] == i2["tasks"] and i1["total_cost"] == i2["total_cost"]
+        tv1, t1 = h1.count_per_node()
+        tv2, t2 = h2.count_per_node()
+    np.testing.assert_array_equal(tv1, tv2)
+    assert t1[0] == t2[0]
+    check(tc, g.n, s, d)
+
+
 # ------------------------------------------------------------ packed graphs and batches
 
 def test_packed_handle_equals_separate(tc):
