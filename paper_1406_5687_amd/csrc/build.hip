@@ -267,38 +267,59 @@ __global__ void k_degrees_lo(const uint64_t *__restrict__ keys, int64_t m, int g
     }
 }
 
-// Upper endpoints: histogram in LDS by buckets of kBins consecutive labels.
-// vals is grouped by bucket (x >> kBinBits ascending).  Workgroup (b, j)
-// counts the j-th of `splits` equal parts of bucket b, then adds its
-// counters to deg: plainly when it is the bucket's only workgroup, else
-// atomically.
+// Label histogram in LDS by buckets of kBins consecutive labels.  vals is
+// grouped by bucket (x >> kBinBits ascending); bucket b is cut into
+// S_b = ceil(len_b / kHistChunk) equal parts (cstart: exclusive prefix of
+// S_b, so heavy buckets get more workgroups).  The workgroup of part j counts
+// its values, then adds its counters to deg: plainly when it is its bucket's
+// only workgroup, else atomically.
 constexpr int kBinBits = 12;
 constexpr int kBins = 1 << kBinBits;
 constexpr int kHistThreads = 1024;
+constexpr int64_t kHistChunk = (int64_t)1 << 17;
 
-__global__ __launch_bounds__(kHistThreads) void k_bucket_hist(const uint32_t *__restrict__ vals, int64_t m,
-                                                              int splits, int64_t N, int32_t *__restrict__ deg) {
-    __shared__ uint32_t cnt[kBins];
-    __shared__ int64_t range[2];
-    const int64_t b = blockIdx.x / splits;
-    const int j = (int)(blockIdx.x % splits);
-    for (int i = threadIdx.x; i < kBins; i += kHistThreads) cnt[i] = 0;
-    if (threadIdx.x < 2) {
-        // first position whose bucket is >= b (thread 0) or >= b + 1 (thread 1)
-        const uint64_t want = (uint64_t)b + threadIdx.x;
+__global__ void k_val_bucket_bounds(const uint32_t *__restrict__ vals, int64_t m, int64_t nbuckets,
+                                    int64_t *__restrict__ bstart) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= nbuckets;
+         b += (int64_t)gridDim.x * blockDim.x) {
         int64_t lo = 0, hi = m;
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
-            if ((uint64_t)(vals[mid] >> kBinBits) < want)
+            if ((int64_t)(vals[mid] >> kBinBits) < b)
                 lo = mid + 1;
             else
                 hi = mid;
         }
-        range[threadIdx.x] = lo;
+        bstart[b] = lo;
     }
+}
+
+__global__ void k_bucket_parts(const int64_t *__restrict__ bstart, int64_t nbuckets, int32_t *__restrict__ parts) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nbuckets;
+         b += (int64_t)gridDim.x * blockDim.x)
+        parts[b] = (int32_t)max((int64_t)1, (bstart[b + 1] - bstart[b] + kHistChunk - 1) / kHistChunk);
+}
+
+__global__ __launch_bounds__(kHistThreads) void k_bucket_hist(const uint32_t *__restrict__ vals,
+                                                              const int64_t *__restrict__ bstart,
+                                                              const int64_t *__restrict__ cstart, int64_t nbuckets,
+                                                              int64_t N, int32_t *__restrict__ deg) {
+    __shared__ uint32_t cnt[kBins];
+    const int64_t c = blockIdx.x;
+    if (c >= cstart[nbuckets]) return;  // the grid is an upper bound on the parts
+    int64_t b = 0, h = nbuckets;       // last bucket whose first part is <= c
+    while (h - b > 1) {
+        const int64_t mid = (b + h) >> 1;
+        if (cstart[mid] <= c)
+            b = mid;
+        else
+            h = mid;
+    }
+    const int64_t j = c - cstart[b], S = cstart[b + 1] - cstart[b];
+    for (int i = threadIdx.x; i < kBins; i += kHistThreads) cnt[i] = 0;
     __syncthreads();
-    const int64_t r0 = range[0], len = range[1] - range[0];
-    const int64_t p0 = r0 + len * j / splits, p1 = r0 + len * (j + 1) / splits;
+    const int64_t r0 = bstart[b], len = bstart[b + 1] - r0;
+    const int64_t p0 = r0 + len * j / S, p1 = r0 + len * (j + 1) / S;
     constexpr int kUnroll = 4;
     for (int64_t p = p0 + threadIdx.x; p < p1; p += (int64_t)kHistThreads * kUnroll) {
         uint32_t v[kUnroll];
@@ -315,12 +336,12 @@ __global__ __launch_bounds__(kHistThreads) void k_bucket_hist(const uint32_t *__
     const int64_t x0 = b << kBinBits;
     for (int i = threadIdx.x; i < kBins; i += kHistThreads) {
         const int64_t x = x0 + i;
-        const uint32_t c = cnt[i];
-        if (c == 0 || x >= N) continue;
-        if (splits == 1)
-            deg[x] += (int32_t)c;
+        const uint32_t cc = cnt[i];
+        if (cc == 0 || x >= N) continue;
+        if (S == 1)
+            deg[x] += (int32_t)cc;
         else
-            atomicAdd(&deg[x], (int32_t)c);
+            atomicAdd(&deg[x], (int32_t)cc);
     }
 }
 
@@ -329,8 +350,9 @@ __global__ __launch_bounds__(kHistThreads) void k_bucket_hist(const uint32_t *__
 // kGroupBits); one wave per group of kGroupRows rows then counts the rows,
 // writes their lengths and offsets, and puts every key at its row's next
 // slot inside the group's part of col (rows are sorted on their own
-// afterwards, so the order of the slots does not matter).  Counts and slots
-// are the wave's LDS counters, one add per key.
+// afterwards).  Counts and slots live in the wave's LDS counters; lanes
+// holding the same row are found with one ballot per label bit, so every
+// counter is read and written by one lane per round (no LDS atomics).
 constexpr int kGroupBits = 4;
 constexpr int kGroupRows = 1 << kGroupBits;
 constexpr int kGroupUnroll = 4;  // rounds of 64 keys loaded together
@@ -351,6 +373,18 @@ __global__ void k_group_bounds(const uint64_t *__restrict__ keys, int64_t m, int
     }
 }
 
+// Lanes holding the same row (0 .. kGroupRows; kGroupRows = no key).
+__device__ __forceinline__ uint64_t same_row(uint32_t row) {
+    uint64_t peers = ~0ull;
+#pragma unroll
+    for (int b = 0; b <= kGroupBits; ++b) {
+        const bool bit = (row >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
 __global__ __launch_bounds__(kThreads) void k_group_place(const uint64_t *__restrict__ keys, int shift,
                                                           const int64_t *__restrict__ gstart, int64_t ngroups,
                                                           int64_t N, int32_t *__restrict__ rowlen,
@@ -368,19 +402,25 @@ __global__ __launch_bounds__(kThreads) void k_group_place(const uint64_t *__rest
         const int nrows = (int)min((int64_t)kGroupRows, N - x0);
         if (lane < kGroupRows) c[lane] = 0;
         wave_lds_sync();
-        // 1. row counts
-        for (int64_t p0 = gs + lane; p0 < ge; p0 += kStep) {
+        // 1. row counts: per round, the first lane of each row adds the
+        // number of lanes holding that row (no two lanes write one counter)
+        for (int64_t b0 = gs; b0 < ge; b0 += kStep) {
             uint64_t k[kGroupUnroll];
 #pragma unroll
             for (int u = 0; u < kGroupUnroll; ++u) {
-                const int64_t p = p0 + u * 64;
+                const int64_t p = b0 + u * 64 + lane;
                 k[u] = p < ge ? keys[p] : 0;
             }
 #pragma unroll
-            for (int u = 0; u < kGroupUnroll; ++u)
-                if (p0 + u * 64 < ge) atomicAdd(&c[(k[u] >> shift) & (kGroupRows - 1)], 1u);
+            for (int u = 0; u < kGroupUnroll; ++u) {
+                if (b0 + u * 64 >= ge) break;
+                const bool valid = b0 + u * 64 + lane < ge;
+                const uint32_t row = valid ? (uint32_t)(k[u] >> shift) & (kGroupRows - 1) : (uint32_t)kGroupRows;
+                const uint64_t peers = same_row(row);
+                if (valid && lane == __ffsll((unsigned long long)peers) - 1) c[row] += (uint32_t)popc64(peers);
+                wave_lds_sync();
+            }
         }
-        wave_lds_sync();
         // 2. row starts; lengths and offsets
         const uint32_t v = lane < kGroupRows ? c[lane] : 0u;
         const uint32_t start = wave_inclusive_sum(v) - v;
@@ -392,20 +432,26 @@ __global__ __launch_bounds__(kThreads) void k_group_place(const uint64_t *__rest
         wave_lds_sync();
         if (lane < kGroupRows) c[lane] = start;
         wave_lds_sync();
-        // 3. every key to its row's next slot
-        for (int64_t p0 = gs + lane; p0 < ge; p0 += kStep) {
+        // 3. every key to its row's next slot: the row's cursor plus the
+        // number of lower lanes holding the same row
+        for (int64_t b0 = gs; b0 < ge; b0 += kStep) {
             uint64_t k[kGroupUnroll];
 #pragma unroll
             for (int u = 0; u < kGroupUnroll; ++u) {
-                const int64_t p = p0 + u * 64;
+                const int64_t p = b0 + u * 64 + lane;
                 k[u] = p < ge ? keys[p] : 0;
             }
 #pragma unroll
             for (int u = 0; u < kGroupUnroll; ++u) {
-                if (p0 + u * 64 < ge) {
-                    const uint32_t slot = atomicAdd(&c[(k[u] >> shift) & (kGroupRows - 1)], 1u);
-                    col[gs + slot] = (int32_t)(k[u] & mask);
-                }
+                if (b0 + u * 64 >= ge) break;
+                const bool valid = b0 + u * 64 + lane < ge;
+                const uint32_t row = valid ? (uint32_t)(k[u] >> shift) & (kGroupRows - 1) : (uint32_t)kGroupRows;
+                const uint64_t peers = same_row(row);
+                const uint32_t base = valid ? c[row] : 0u;
+                wave_lds_sync();
+                if (valid && lane == __ffsll((unsigned long long)peers) - 1) c[row] = base + (uint32_t)popc64(peers);
+                wave_lds_sync();
+                if (valid) col[gs + base + (uint32_t)popc64(peers & lanemask_lt())] = (int32_t)(k[u] & mask);
             }
         }
         wave_lds_sync();
@@ -1402,9 +1448,15 @@ void histogram_add(uint32_t *vals, uint32_t *vals_tmp, int64_t M, int gb, int32_
                    hipStream_t s) {
     uint32_t *hs = gb > kBinBits ? radix_sort_u32(vals, vals_tmp, M, kBinBits, gb, tmp, s) : vals;
     const int64_t nbuckets = gb > kBinBits ? (int64_t)1 << (gb - kBinBits) : 1;
-    const int64_t per_group = (int64_t)1 << 17;  // values per workgroup, about
-    const int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, ceil_div(M, nbuckets * per_group)));
-    k_bucket_hist<<<(unsigned)(nbuckets * splits), kHistThreads, 0, s>>>(hs, M, splits, N, deg);
+    DevBuf<int64_t> bstart(tmp, (size_t)nbuckets + 1), cstart(tmp, (size_t)nbuckets + 1);
+    DevBuf<int32_t> parts(tmp, (size_t)nbuckets);
+    k_val_bucket_bounds<<<grid_for(nbuckets + 1), kThreads, 0, s>>>(hs, M, nbuckets, bstart.p);
+    TC_LAUNCH_CHECK();
+    k_bucket_parts<<<grid_for(nbuckets), kThreads, 0, s>>>(bstart.p, nbuckets, parts.p);
+    TC_LAUNCH_CHECK();
+    exclusive_scan(parts.p, cstart.p, nbuckets, true, tmp, s);
+    const int64_t pmax = nbuckets + ceil_div(M, kHistChunk);  // parts, at most
+    k_bucket_hist<<<(unsigned)pmax, kHistThreads, 0, s>>>(hs, bstart.p, cstart.p, nbuckets, N, deg);
     TC_LAUNCH_CHECK();
 }
 

@@ -1,11 +1,12 @@
 // LSD radix sort of 32- or 64-bit keys over a bit range, 8 bits per pass (the
 // last pass takes what is left of the range).
 //
-// Each pass: (1) per-tile digit histograms (LDS adds), (2) one exclusive scan over the
-// digit-major histogram table giving every (digit, tile) its output base,
-// (3) a stable scatter: each wave ranks its keys among equal digits with
-// ballots over the digit bits, the tile is reordered by digit in LDS, and runs of equal digits
-// are written out contiguously.
+// Each pass: (1) per-tile digit histograms (per-wave counters, one writer per
+// digit and round), (2) one exclusive scan over the digit-major histogram
+// table giving every (digit, tile) its output base, (3) a stable scatter:
+// each wave ranks its keys among equal digits with ballots over the digit
+// bits, the tile is reordered by digit in LDS, and runs of equal digits are
+// written out contiguously.
 #include "internal.h"
 
 namespace tc {
@@ -48,18 +49,44 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K *__restrict
         const int64_t i = key_index(tile, wave, r, lane);
         kk[r] = i < n ? keys[i] : (K)0;
     }
+    const bool full = n - tile >= kSortTile;  // block-uniform: every lane holds a key
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         const int64_t i = key_index(tile, wave, r, lane);
-        const uint32_t d = digit_of(kk[r], shift, dmask);
-        // one add when all 64 keys share a digit (sorted or narrow input),
-        // else one LDS add per key
+        const uint32_t d = i < n ? digit_of(kk[r], shift, dmask) : 256u;  // 256: past the end
+        // lanes holding the same digit (all of them when the first lane's
+        // digit is everyone's, else one ballot per digit bit); the first of
+        // them adds their number to the wave's counter, so no counter gets
+        // two writes in one round and no LDS atomics are needed
         const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
-        if (__ballot(i < n && d == d0) == ~0ull) {
-            if (lane == 0) atomicAdd(&hw[wave][d0], 64u);
-        } else if (i < n) {
-            atomicAdd(&hw[wave][d], 1u);
+        if (sizeof(K) == 4) {
+            // 32-bit keys: one LDS add per key measured faster here (the
+            // tile's loads are shorter, the ballots not hidden behind them)
+            if (__ballot(d == d0) == ~0ull) {
+                if (lane == 0 && d0 < 256u) atomicAdd(&hw[wave][d0], 64u);
+            } else if (d < 256u) {
+                atomicAdd(&hw[wave][d], 1u);
+            }
+            continue;
         }
+        uint64_t peers = ~0ull;
+        if (__ballot(d == d0) != ~0ull) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                if (b < bits) {
+                    const bool bit = (d >> b) & 1u;
+                    const uint64_t bal = __ballot(bit);
+                    peers &= bit ? bal : ~bal;
+                }
+            }
+            if (!full) {
+                const bool past = d >> 8;
+                const uint64_t bal = __ballot(past);
+                peers &= past ? bal : ~bal;
+            }
+        }
+        if (d < 256u && lane == __ffsll((unsigned long long)peers) - 1) hw[wave][d] += (uint32_t)popc64(peers);
+        wave_lds_sync();
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kRadix; i += kSortThreads) {
