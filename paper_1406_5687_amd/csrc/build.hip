@@ -517,6 +517,62 @@ __global__ void k_orient_keys(const uint64_t *__restrict__ ukeys, int64_t m, int
     }
 }
 
+// One graph given as an edge list: err bit 0 if an id is outside 0..n-1,
+// bit 1 if an edge is a loop (the pairs are checked before anything else
+// reads them as labels).
+__global__ void k_check_pairs(const int32_t *__restrict__ src, const int32_t *__restrict__ dst, int64_t m,
+                              int64_t n, uint32_t *__restrict__ err) {
+    const int64_t step = (int64_t)blockDim.x * kEdgeUnroll;
+    uint32_t bad = 0;
+    for (int64_t e0 = (int64_t)blockIdx.x * step + threadIdx.x; e0 < m; e0 += (int64_t)gridDim.x * step) {
+        int32_t u[kEdgeUnroll], v[kEdgeUnroll];
+#pragma unroll
+        for (int j = 0; j < kEdgeUnroll; ++j) {
+            const int64_t e = e0 + (int64_t)j * blockDim.x;
+            u[j] = e < m ? src[e] : 0;
+            v[j] = e < m ? dst[e] : 1;
+        }
+#pragma unroll
+        for (int j = 0; j < kEdgeUnroll; ++j) {
+            if (u[j] < 0 || v[j] < 0 || u[j] >= n || v[j] >= n) bad |= 1u;
+            else if (u[j] == v[j]) bad |= 2u;
+        }
+    }
+    const uint32_t w = (__ballot(bad & 1u) ? 1u : 0u) | (__ballot(bad & 2u) ? 2u : 0u);
+    if (w && __lane_id() == 0) atomicOr(err, w);
+}
+
+// Oriented keys straight from a checked edge list of one graph (labels are
+// the ids), as k_orient_keys does from pair keys.
+__global__ void k_orient_pairs(const int32_t *__restrict__ src, const int32_t *__restrict__ dst, int64_t m, int gb,
+                               const int32_t *__restrict__ rank, uint64_t *__restrict__ okeys) {
+    const int64_t step = (int64_t)blockDim.x * kOrientUnroll;
+    for (int64_t i0 = (int64_t)blockIdx.x * step + threadIdx.x; i0 < m; i0 += (int64_t)gridDim.x * step) {
+        int32_t u[kOrientUnroll], v[kOrientUnroll];
+        uint32_t ra[kOrientUnroll], rb[kOrientUnroll];
+#pragma unroll
+        for (int j = 0; j < kOrientUnroll; ++j) {
+            const int64_t i = i0 + (int64_t)j * blockDim.x;
+            u[j] = i < m ? __builtin_nontemporal_load(&src[i]) : 0;
+            v[j] = i < m ? __builtin_nontemporal_load(&dst[i]) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kOrientUnroll; ++j) {
+            const int64_t i = i0 + (int64_t)j * blockDim.x;
+            ra[j] = i < m ? (uint32_t)rank[u[j]] : 0u;
+            rb[j] = i < m ? (uint32_t)rank[v[j]] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kOrientUnroll; ++j) {
+            const int64_t i = i0 + (int64_t)j * blockDim.x;
+            if (i < m) {
+                const uint64_t lo = ra[j] < rb[j] ? ra[j] : rb[j], hi = ra[j] < rb[j] ? rb[j] : ra[j];
+                __builtin_nontemporal_store((lo << gb) | hi, &okeys[i]);
+            }
+        }
+    }
+}
+
 // Step 5b: rows sorted ascending.  The pair sort above orders by s only, so
 // each row holds its entries in input order.  A wave takes 64 consecutive
 // rows: rows of up to 8 entries are sorted by their own lane with a sorting
@@ -1143,6 +1199,8 @@ void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing
 namespace {
 void add_endpoint_counts(const uint64_t *keys, int64_t M, int gb, int32_t *deg, int64_t N, uint32_t *spare,
                          Allocator &tmp, hipStream_t s);
+void add_pair_counts(const int32_t *src, const int32_t *dst, int64_t M, int gb, int32_t *deg, int64_t N,
+                     uint32_t *spare, Allocator &tmp, hipStream_t s);
 }  // namespace
 
 // One build.  simple: the input is taken to be a simple graph (no edge
@@ -1168,7 +1226,19 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
     DevBuf<uint64_t> ka(tmp, (size_t)std::max<int64_t>(M_in, 1));
     DevBuf<uint64_t> kb(tmp, (size_t)std::max<int64_t>(M_in, 1));
     uint64_t *ukeys = kb.p;
-    if (M_in > 0) {
+    // one graph given as an edge list: the ids are the labels, so a simple
+    // input needs no pair keys at all (degrees and orientation read it)
+    const bool pairs = simple && k == 1;
+    if (M_in > 0 && pairs) {
+        k_check_pairs<<<grid_for(M_in, 4 * kEdgeUnroll), kThreads, 0, s>>>(src, dst, M_in, N, err.p);
+        TC_LAUNCH_CHECK();
+        uint32_t herr = 0;
+        d2h(&herr, err.p, 1, s);
+        TC_HIP(hipStreamSynchronize(s));
+        if (herr & 1u) throw Error(TC_ERR_ID_RANGE, "an edge endpoint is outside 0..n-1 of its graph");
+        if (herr & 2u) return false;  // a loop: take the canonical path
+        M = M_in;
+    } else if (M_in > 0) {
         k_edge_keys<<<grid_for(M_in, 4 * kEdgeUnroll), kThreads, 0, s>>>(src, dst, M_in, edge_base.p,
                                                                           out.node_base.p, k, gb, ka.p, err.p);
         TC_LAUNCH_CHECK();
@@ -1195,7 +1265,9 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
     // ---- 2. degrees
     DevBuf<int32_t> deg(tmp, (size_t)std::max<int64_t>(N, 1));
     fill_zero(deg.p, deg.bytes(), s);
-    if (simple)
+    if (pairs)
+        add_pair_counts(src, dst, M, gb, deg.p, N, reinterpret_cast<uint32_t *>(spare), tmp, s);
+    else if (simple)
         add_endpoint_counts(ukeys, M, gb, deg.p, N, reinterpret_cast<uint32_t *>(spare), tmp, s);
     else
         add_degrees(ukeys, M, gb, deg.p, N, reinterpret_cast<uint32_t *>(spare), tmp, s);  // spare: >= 2 M words
@@ -1212,7 +1284,10 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
     fill_zero(rowlen.p, rowlen.bytes(), s);
     uint64_t *okeys = nullptr;
     if (M > 0) {
-        k_orient_keys<<<grid_for(M, 4 * kOrientUnroll), kThreads, 0, s>>>(ukeys, M, gb, rank.p, spare);
+        if (pairs)
+            k_orient_pairs<<<grid_for(M, 4 * kOrientUnroll), kThreads, 0, s>>>(src, dst, M, gb, rank.p, spare);
+        else
+            k_orient_keys<<<grid_for(M, 4 * kOrientUnroll), kThreads, 0, s>>>(ukeys, M, gb, rank.p, spare);
         TC_LAUNCH_CHECK();
         // order by s >> kGroupBits, then place each group of rows (in key
         // order inside a row: rows are sorted below)
@@ -1445,8 +1520,13 @@ namespace {
 // values are grouped by bucket (label bits above kBinBits; vals_tmp holds M
 // more), then each bucket is counted in LDS.
 void histogram_add(uint32_t *vals, uint32_t *vals_tmp, int64_t M, int gb, int32_t *deg, int64_t N, Allocator &tmp,
-                   hipStream_t s) {
-    uint32_t *hs = gb > kBinBits ? radix_sort_u32(vals, vals_tmp, M, kBinBits, gb, tmp, s) : vals;
+                   hipStream_t s, const uint32_t *first = nullptr) {
+    // with first given, the values are read from it (vals: scratch)
+    const uint32_t *hs;
+    if (first)
+        hs = gb > kBinBits ? radix_sort_u32_from(first, vals, vals_tmp, M, kBinBits, gb, tmp, s) : first;
+    else
+        hs = gb > kBinBits ? radix_sort_u32(vals, vals_tmp, M, kBinBits, gb, tmp, s) : vals;
     const int64_t nbuckets = gb > kBinBits ? (int64_t)1 << (gb - kBinBits) : 1;
     DevBuf<int64_t> bstart(tmp, (size_t)nbuckets + 1), cstart(tmp, (size_t)nbuckets + 1);
     DevBuf<int32_t> parts(tmp, (size_t)nbuckets);
@@ -1468,6 +1548,15 @@ __global__ void k_endpoint(const uint64_t *__restrict__ keys, int64_t m, int gb,
         const uint64_t k = __builtin_nontemporal_load(&keys[i]);
         out[i] = (uint32_t)(hi ? (k & mask) : (k >> gb));
     }
+}
+
+// Degrees of a simple graph given as one edge list (labels are the ids):
+// the number of times each id occurs in src and in dst, read in place.
+void add_pair_counts(const int32_t *src, const int32_t *dst, int64_t M, int gb, int32_t *deg, int64_t N,
+                     uint32_t *spare, Allocator &tmp, hipStream_t s) {
+    if (M <= 0) return;
+    histogram_add(spare, spare + M, M, gb, deg, N, tmp, s, reinterpret_cast<const uint32_t *>(src));
+    histogram_add(spare, spare + M, M, gb, deg, N, tmp, s, reinterpret_cast<const uint32_t *>(dst));
 }
 
 // Degrees of a simple graph given as pair keys in any order: the number of

@@ -18,6 +18,8 @@ uint64_t *radix_sort_u64(uint64_t *keys, uint64_t *tmp, int64_t n, int begin_bit
                          hipStream_t s);
 uint32_t *radix_sort_u32(uint32_t *keys, uint32_t *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al,
                          hipStream_t s);
+uint32_t *radix_sort_u32_from(const uint32_t *first, uint32_t *keys, uint32_t *tmp, int64_t n, int begin_bit,
+                              int end_bit, Allocator &al, hipStream_t s);
 
 // build.hip -------------------------------------------------------------
 

@@ -200,23 +200,38 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K *__restr
     }
 }
 
+// With `first` given, the first pass reads it instead of keys (first is
+// never written; the result is in keys or tmp).
 template <class K>
-K *radix_sort_impl(K *keys, K *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al, hipStream_t s) {
-    if (n <= 1 || end_bit <= begin_bit) return keys;
+K *radix_sort_impl(K *keys, K *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al, hipStream_t s,
+                   const K *first = nullptr) {
+    if (n <= 1 || end_bit <= begin_bit) {
+        if (first && n > 0) TC_HIP(hipMemcpyAsync(keys, first, (size_t)n * sizeof(K), hipMemcpyDeviceToDevice, s));
+        return keys;
+    }
     const int64_t nb = ceil_div(n, kSortTile);
     DevBuf<uint32_t> hist(al, (size_t)(nb * kRadix));
     DevBuf<int64_t> base(al, (size_t)(nb * kRadix) + 1);
+    const K *in = first ? first : keys;
     K *a = keys, *b = tmp;
+    if (first) {
+        a = tmp;  // written by the first pass
+        b = keys;
+    }
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
         const int bits = std::min(8, end_bit - shift);
-        k_radix_hist<K><<<(unsigned)nb, kSortThreads, 0, s>>>(a, n, shift, bits, nb, hist.p);
+        K *outp = first && shift == begin_bit ? a : b;
+        k_radix_hist<K><<<(unsigned)nb, kSortThreads, 0, s>>>(in, n, shift, bits, nb, hist.p);
         TC_LAUNCH_CHECK();
         exclusive_scan(hist.p, base.p, nb * kRadix, false, al, s);
-        k_radix_scatter<K><<<(unsigned)nb, kSortThreads, 0, s>>>(a, b, n, shift, bits, nb, base.p);
+        k_radix_scatter<K><<<(unsigned)nb, kSortThreads, 0, s>>>(in, outp, n, shift, bits, nb, base.p);
         TC_LAUNCH_CHECK();
-        K *t = a;
-        a = b;
-        b = t;
+        if (!(first && shift == begin_bit)) {
+            K *t = a;
+            a = b;
+            b = t;
+        }
+        in = a;
     }
     return a;
 }
@@ -233,6 +248,13 @@ uint64_t *radix_sort_u64(uint64_t *keys, uint64_t *tmp, int64_t n, int begin_bit
 uint32_t *radix_sort_u32(uint32_t *keys, uint32_t *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al,
                          hipStream_t s) {
     return radix_sort_impl<uint32_t>(keys, tmp, n, begin_bit, end_bit, al, s);
+}
+
+// The same, reading the keys from first (left unchanged): keys and tmp are
+// both scratch of n keys.
+uint32_t *radix_sort_u32_from(const uint32_t *first, uint32_t *keys, uint32_t *tmp, int64_t n, int begin_bit,
+                              int end_bit, Allocator &al, hipStream_t s) {
+    return radix_sort_impl<uint32_t>(keys, tmp, n, begin_bit, end_bit, al, s, first);
 }
 
 }  // namespace tc
