@@ -517,29 +517,68 @@ __global__ void k_orient_keys(const uint64_t *__restrict__ ukeys, int64_t m, int
     }
 }
 
-// One graph given as an edge list: err bit 0 if an id is outside 0..n-1,
-// bit 1 if an edge is a loop (the pairs are checked before anything else
-// reads them as labels).
+// One graph given as an edge list: bit 0 of chk[0] if an id is outside
+// 0..n-1, bit 1 if an edge is a loop (the pairs are checked before anything
+// else reads them as labels).  Each workgroup also stores how often src and
+// dst change value from one edge to the next (chk[2 + 2b], chk[3 + 2b]):
+// long runs of one id (an edge list made from adjacency lists) let the
+// degrees be counted from the runs instead of a histogram.
+constexpr int kCheckBlocks = 1024;
+
 __global__ void k_check_pairs(const int32_t *__restrict__ src, const int32_t *__restrict__ dst, int64_t m,
-                              int64_t n, uint32_t *__restrict__ err) {
+                              int64_t n, unsigned long long *__restrict__ chk) {
+    __shared__ unsigned long long part[2][kThreads / 64];
     const int64_t step = (int64_t)blockDim.x * kEdgeUnroll;
     uint32_t bad = 0;
+    uint32_t bs = 0, bd = 0;  // value changes in src and dst
     for (int64_t e0 = (int64_t)blockIdx.x * step + threadIdx.x; e0 < m; e0 += (int64_t)gridDim.x * step) {
-        int32_t u[kEdgeUnroll], v[kEdgeUnroll];
+        int32_t u[kEdgeUnroll], v[kEdgeUnroll], up[kEdgeUnroll], vp[kEdgeUnroll];
 #pragma unroll
         for (int j = 0; j < kEdgeUnroll; ++j) {
             const int64_t e = e0 + (int64_t)j * blockDim.x;
             u[j] = e < m ? src[e] : 0;
             v[j] = e < m ? dst[e] : 1;
+            up[j] = (e < m && e > 0) ? src[e - 1] : u[j];
+            vp[j] = (e < m && e > 0) ? dst[e - 1] : v[j];
         }
 #pragma unroll
         for (int j = 0; j < kEdgeUnroll; ++j) {
             if (u[j] < 0 || v[j] < 0 || u[j] >= n || v[j] >= n) bad |= 1u;
             else if (u[j] == v[j]) bad |= 2u;
+            bs += u[j] != up[j] ? 1u : 0u;
+            bd += v[j] != vp[j] ? 1u : 0u;
         }
     }
     const uint32_t w = (__ballot(bad & 1u) ? 1u : 0u) | (__ballot(bad & 2u) ? 2u : 0u);
-    if (w && __lane_id() == 0) atomicOr(err, w);
+    if (w && __lane_id() == 0) atomicOr(&chk[0], (unsigned long long)w);
+    const unsigned long long ts = wave_sum((unsigned long long)bs), td = wave_sum((unsigned long long)bd);
+    if (__lane_id() == 0) {
+        part[0][threadIdx.x >> 6] = ts;
+        part[1][threadIdx.x >> 6] = td;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long t = 0;
+        for (int q = 0; q < kThreads / 64; ++q) t += part[threadIdx.x][q];
+        chk[2 + 2 * blockIdx.x + threadIdx.x] = t;
+    }
+}
+
+// Degrees from runs of equal ids: each run (cut at wave edges into pieces)
+// adds its length with one atomic.  For edge lists whose runs are long.
+__global__ void k_run_degrees(const int32_t *__restrict__ vals, int64_t m, int32_t *__restrict__ deg) {
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < m;
+        const int64_t x = valid ? (int64_t)vals[i] : -1;
+        const int64_t xp = (valid && i > 0) ? (int64_t)vals[i - 1] : -2;
+        const int64_t xn = i + 1 < m ? (int64_t)vals[i + 1] : -3;
+        bool whole;
+        const int64_t cnt = run_piece_at_end(x, xp, xn, valid, lane, &whole);
+        if (cnt) atomicAdd(&deg[x], (int32_t)cnt);
+    }
 }
 
 // Oriented keys straight from a checked edge list of one graph (labels are
@@ -1200,7 +1239,7 @@ namespace {
 void add_endpoint_counts(const uint64_t *keys, int64_t M, int gb, int32_t *deg, int64_t N, uint32_t *spare,
                          Allocator &tmp, hipStream_t s);
 void add_pair_counts(const int32_t *src, const int32_t *dst, int64_t M, int gb, int32_t *deg, int64_t N,
-                     uint32_t *spare, Allocator &tmp, hipStream_t s);
+                     uint32_t *spare, Allocator &tmp, hipStream_t s, bool runs_src, bool runs_dst);
 }  // namespace
 
 // One build.  simple: the input is taken to be a simple graph (no edge
@@ -1229,14 +1268,26 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
     // one graph given as an edge list: the ids are the labels, so a simple
     // input needs no pair keys at all (degrees and orientation read it)
     const bool pairs = simple && k == 1;
+    bool runs_src = false, runs_dst = false;
     if (M_in > 0 && pairs) {
-        k_check_pairs<<<grid_for(M_in, 4 * kEdgeUnroll), kThreads, 0, s>>>(src, dst, M_in, N, err.p);
+        const unsigned nblk = std::min<unsigned>(grid_for(M_in, 4 * kEdgeUnroll), kCheckBlocks);
+        DevBuf<unsigned long long> chk(tmp, 2 + 2 * (size_t)nblk);
+        fill_zero(chk.p, 16, s);
+        k_check_pairs<<<nblk, kThreads, 0, s>>>(src, dst, M_in, N, chk.p);
         TC_LAUNCH_CHECK();
-        uint32_t herr = 0;
-        d2h(&herr, err.p, 1, s);
+        std::vector<unsigned long long> hc(2 + 2 * (size_t)nblk);
+        d2h(hc.data(), chk.p, hc.size(), s);
         TC_HIP(hipStreamSynchronize(s));
-        if (herr & 1u) throw Error(TC_ERR_ID_RANGE, "an edge endpoint is outside 0..n-1 of its graph");
-        if (herr & 2u) return false;  // a loop: take the canonical path
+        if (hc[0] & 1u) throw Error(TC_ERR_ID_RANGE, "an edge endpoint is outside 0..n-1 of its graph");
+        if (hc[0] & 2u) return false;  // a loop: take the canonical path
+        unsigned long long bs = 0, bd = 0;
+        for (unsigned b = 0; b < nblk; ++b) {
+            bs += hc[2 + 2 * b];
+            bd += hc[3 + 2 * b];
+        }
+        // count runs when they average 4 or more edges
+        runs_src = (int64_t)bs * 4 <= M_in;
+        runs_dst = (int64_t)bd * 4 <= M_in;
         M = M_in;
     } else if (M_in > 0) {
         k_edge_keys<<<grid_for(M_in, 4 * kEdgeUnroll), kThreads, 0, s>>>(src, dst, M_in, edge_base.p,
@@ -1266,7 +1317,7 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
     DevBuf<int32_t> deg(tmp, (size_t)std::max<int64_t>(N, 1));
     fill_zero(deg.p, deg.bytes(), s);
     if (pairs)
-        add_pair_counts(src, dst, M, gb, deg.p, N, reinterpret_cast<uint32_t *>(spare), tmp, s);
+        add_pair_counts(src, dst, M, gb, deg.p, N, reinterpret_cast<uint32_t *>(spare), tmp, s, runs_src, runs_dst);
     else if (simple)
         add_endpoint_counts(ukeys, M, gb, deg.p, N, reinterpret_cast<uint32_t *>(spare), tmp, s);
     else
@@ -1553,10 +1604,18 @@ __global__ void k_endpoint(const uint64_t *__restrict__ keys, int64_t m, int gb,
 // Degrees of a simple graph given as one edge list (labels are the ids):
 // the number of times each id occurs in src and in dst, read in place.
 void add_pair_counts(const int32_t *src, const int32_t *dst, int64_t M, int gb, int32_t *deg, int64_t N,
-                     uint32_t *spare, Allocator &tmp, hipStream_t s) {
+                     uint32_t *spare, Allocator &tmp, hipStream_t s, bool runs_src, bool runs_dst) {
     if (M <= 0) return;
-    histogram_add(spare, spare + M, M, gb, deg, N, tmp, s, reinterpret_cast<const uint32_t *>(src));
-    histogram_add(spare, spare + M, M, gb, deg, N, tmp, s, reinterpret_cast<const uint32_t *>(dst));
+    const int32_t *arr[2] = {src, dst};
+    const bool runs[2] = {runs_src, runs_dst};
+    for (int q = 0; q < 2; ++q) {
+        if (runs[q]) {
+            k_run_degrees<<<grid_for(M, 4), kThreads, 0, s>>>(arr[q], M, deg);
+            TC_LAUNCH_CHECK();
+        } else {
+            histogram_add(spare, spare + M, M, gb, deg, N, tmp, s, reinterpret_cast<const uint32_t *>(arr[q]));
+        }
+    }
 }
 
 // Degrees of a simple graph given as pair keys in any order: the number of

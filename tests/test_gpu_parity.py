@@ -307,6 +307,37 @@ def test_repeated_edges_without_loops(tc, maker, repeats):
     check(tc, g.n, s, d)
 
 
+def test_edge_list_orders(tc):
+    # Degrees of a simple input are counted from runs of equal ids when the
+    # list has long runs (made from adjacency lists), else by a histogram:
+    # every order of the same edges gives the same handle.
+    g = graphgen.workload_er(1)
+    rng = np.random.default_rng(5)
+    lo, hi = np.minimum(g.src, g.dst), np.maximum(g.src, g.dst)
+    o = np.lexsort((hi, lo))
+    shuf = rng.permutation(g.m)
+    by_hi = np.argsort(hi, kind="stable")
+    orders = [
+        (g.src, g.dst),           # as drawn
+        (lo[o], hi[o]),           # sorted by the smaller id: long runs in src
+        (hi[o], lo[o]),           # the same with the columns swapped: long runs in dst
+        (lo[shuf], hi[shuf]),     # shuffled
+        (hi[by_hi], lo[by_hi]),   # sorted by the larger id
+    ]
+    ref = None
+    for s, d in orders:
+        s = np.ascontiguousarray(s, dtype=np.int32)
+        d = np.ascontiguousarray(d, dtype=np.int32)
+        with tc.build_oriented([(g.n, s, d)]) as h:
+            got = tuple(np.asarray(x) for x in h.export_csr()) + (h.count_per_node()[0],)
+        if ref is None:
+            ref = got
+        else:
+            for x, y in zip(ref, got):
+                np.testing.assert_array_equal(x, y)
+    check(tc, g.n, np.ascontiguousarray(lo[o], dtype=np.int32), np.ascontiguousarray(hi[o], dtype=np.int32))
+
+
 # ------------------------------------------------------------ packed graphs and batches
 
 def test_packed_handle_equals_separate(tc):
