@@ -523,7 +523,7 @@ __global__ void k_orient_keys(const uint64_t *__restrict__ ukeys, int64_t m, int
 // dst change value from one edge to the next (chk[2 + 2b], chk[3 + 2b]):
 // long runs of one id (an edge list made from adjacency lists) let the
 // degrees be counted from the runs instead of a histogram.
-constexpr int kCheckBlocks = 1024;
+constexpr int kCheckBlocks = 8192;  // partial counts go to the host: 16 B per workgroup
 
 __global__ void k_check_pairs(const int32_t *__restrict__ src, const int32_t *__restrict__ dst, int64_t m,
                               int64_t n, unsigned long long *__restrict__ chk) {
@@ -572,9 +572,15 @@ __global__ void k_run_degrees(const int32_t *__restrict__ vals, int64_t m, int32
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
         const int64_t i = base + threadIdx.x;
         const bool valid = i < m;
-        const int64_t x = valid ? (int64_t)vals[i] : -1;
-        const int64_t xp = (valid && i > 0) ? (int64_t)vals[i - 1] : -2;
-        const int64_t xn = i + 1 < m ? (int64_t)vals[i + 1] : -3;
+        // neighbours from the next lanes; the wave's two edge lanes load theirs
+        const int32_t v0 = valid ? vals[i] : -1;
+        const int32_t e0 = (lane == 0 && valid && i > 0) ? vals[i - 1] : -2;
+        const int32_t e1 = (lane == 63 && i + 1 < m) ? vals[i + 1] : -3;
+        const int64_t x = v0;
+        int64_t xp = __shfl_up(v0, 1, 64), xn = __shfl_down(v0, 1, 64);
+        if (lane == 0) xp = e0;
+        if (lane == 63) xn = e1;
+        if (!valid) xn = -3;
         bool whole;
         const int64_t cnt = run_piece_at_end(x, xp, xn, valid, lane, &whole);
         if (cnt) atomicAdd(&deg[x], (int32_t)cnt);
