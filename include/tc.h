@@ -204,7 +204,7 @@ tc_status tc_export_schedule(const tc_graph *g, const tc_options *opt, int32_t *
  * handles): for each persistent worker i, times[3i] and times[3i+1] receive when
  * it started and when it stopped, in nanoseconds from the earliest start, and
  * times[3i+2] its kind: 0 = a wave taking node-range tasks (Eq. (1)/(2)),
- * 1 = a workgroup taking lists of up to 1024 entries, 2 = a workgroup taking
+ * 1 = a workgroup taking lists of up to 768 entries, 2 = a workgroup taking
  * longer lists.  cap is the number of workers times can hold; *nworkers
  * receives the number of workers (0 if no such count).  Synchronises the
  * stream.  Errors: TC_ERR_INVALID_ARG (NULL g or nworkers, cap below

@@ -19,7 +19,7 @@
 //   - lists with 2 <= a <= small_max (at most 128): one wave per list, tasks
 //     of consecutive sources pulled by waves (k_count_small);
 //   - longer lists: one workgroup per list (k_count_wide): 4 waves for lists
-//     up to 1024 entries, 16 waves above; lists longer than the LDS table
+//     up to 768 entries, 16 waves above; lists longer than the LDS table
 //     (lds_max) are probed by binary search in device memory instead.
 //
 // Per-node counts (Section II): a triangle {s, t_i, w} found at probe w adds
@@ -45,7 +45,7 @@ constexpr int kSmallHash = 1 << kSmallHashBits;  // load factor <= 1/4
 constexpr int kSmallWaves = 4;
 
 constexpr int kMedWaves = 4;
-constexpr int kMedMax = 1024;
+constexpr int kMedMax = 768;  // 24 KB of LDS per workgroup: six resident per CU
 constexpr int kMedHashBits = 11;  // load factor <= 1/2
 
 constexpr int kLdsMax = 4096;
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
 // ---------------------------------------------------------- one workgroup
 
 // Long lists: one workgroup per list.  Two tiers share this code: lists up to
-// 1024 entries go to 4-wave workgroups with a ~31 KB LDS table (several per
+// 768 entries go to 4-wave workgroups with a ~24 KB LDS table (six per
 // compute unit), longer ones to 16-wave workgroups with a 127 KB table.
 // Lists are handed out longest-rank first (roughly longest first).
 template <int WAVES, int LMAX, int HBITS, bool IDX32>
