@@ -146,7 +146,10 @@ using idx_t = typename std::conditional<IDX32, int32_t, int64_t>::type;
 //   IN_LDS: membership in the source list by the LDS hash (key/pos);
 //   otherwise by binary search in the sorted list col[rs .. rs+a) (huge lists).
 // Per-node counts go to LDS counters by list position, or (huge lists) to tv.
-template <int HBITS, bool PER_NODE, bool IN_LDS, bool IDX32, class PosT>
+// GATHER: the list positions of a step's hits are read for all windows before
+// any counter is updated (one LDS wait per step); otherwise window by window,
+// which is faster where hits are sparse (the one-wave kernel's short lists).
+template <int HBITS, bool PER_NODE, bool IN_LDS, bool IDX32, bool GATHER, class PosT>
 __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *pos, const int32_t *P,
                                                const idx_t<IDX32> *base, const PosT *tpos, int32_t *cnt,
                                                uint8_t *flag, const ColReader<IDX32> &rd,
@@ -227,15 +230,32 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
                     }
                 }
             }
+            if (PER_NODE && GATHER) {
+                // slots and rows are valid in every lane
+                int kw[kWin], kt[kWin];
 #pragma unroll
-            for (int q = 0; q < kWin; ++q) {
-                const bool hit = ok[q] && k[q] == w[q];
-                hits += hit ? 1u : 0u;
-                if (PER_NODE && hit) {
-                    atomicAdd(&cnt[pos[sl[q]]], 1);
-                    atomicAdd(&cnt[tpos[seg[q]]], 1);
+                for (int q = 0; q < kWin; ++q) {
+                    kw[q] = pos[sl[q]];
+                    kt[q] = tpos[seg[q]];
+                }
+#pragma unroll
+                for (int q = 0; q < kWin; ++q) {
+                    if (ok[q] && k[q] == w[q]) {
+                        atomicAdd(&cnt[kw[q]], 1);
+                        atomicAdd(&cnt[kt[q]], 1);
+                    }
+                }
+            } else if (PER_NODE) {
+#pragma unroll
+                for (int q = 0; q < kWin; ++q) {
+                    if (ok[q] && k[q] == w[q]) {
+                        atomicAdd(&cnt[pos[sl[q]]], 1);
+                        atomicAdd(&cnt[tpos[seg[q]]], 1);
+                    }
                 }
             }
+#pragma unroll
+            for (int q = 0; q < kWin; ++q) hits += ok[q] && k[q] == w[q] ? 1u : 0u;
         } else {
 #pragma unroll
             for (int q = 0; q < kWin; ++q) {
@@ -329,7 +349,7 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     wave_lds_sync();
 
     const int32_t e_end = ((total + kStep - 1) / kStep) * kStep;
-    const uint32_t hits = walk_steps<kSmallHashBits, PER_NODE, true, IDX32, uint8_t>(
+    const uint32_t hits = walk_steps<kSmallHashBits, PER_NODE, true, IDX32, false, uint8_t>(
         S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag, rd, gcol, nt, total, 0, 0, e_end, 0, a, 0, tv);
     if (PER_NODE) {
         const uint64_t hs = wave_sum((uint64_t)hits);
@@ -534,10 +554,10 @@ __device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &r
             hi = mid - 1;
     }
     if (in_lds)
-        return walk_steps<HBITS, PER_NODE, true, IDX32, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
+        return walk_steps<HBITS, PER_NODE, true, IDX32, true, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
                                                                  S.flag[wave], rd, gcol, nt, total, lo, e_begin,
                                                                  s1 * kStep, rs, a, i0, tv);
-    return walk_steps<HBITS, PER_NODE, false, IDX32, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
+    return walk_steps<HBITS, PER_NODE, false, IDX32, true, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
                                                               S.flag[wave], rd, gcol, nt, total, lo, e_begin,
                                                               s1 * kStep, rs, a, i0, tv);
 }
