@@ -96,6 +96,7 @@ void ensure_scratch(tc_graph *g, bool per_node, hipStream_t s) {
         d.off = g->o.off.p;
         d.col = g->o.col.p;
         d.bnd = g->o.bnd.p;
+        d.start = g->o.start.p;
         d.gid = g->pk.k > 1 ? g->o.gid.p : nullptr;
         d.node_base = g->o.node_base.p;
         d.big = g->o.big.p;
@@ -425,6 +426,7 @@ tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt,
             d.off = g->o.off.p;
             d.col = g->o.col.p;
             d.bnd = g->o.bnd.p;
+            d.start = g->o.start.p;
             d.gid = g->pk.k > 1 ? g->o.gid.p : nullptr;
             d.node_base = g->o.node_base.p;
             d.big = g->o.big.p;

@@ -1080,6 +1080,41 @@ __global__ void k_merge_bounds(const int32_t *__restrict__ bnd, int64_t nb1, con
     }
 }
 
+// Step 6e: where each task's scan begins.  A node of degree 0 or 1 has no
+// pair of neighbours, hence no triangle to count; in the degree order such
+// nodes lead every graph, and a task reaching into that block (for a graph
+// with many isolated nodes, one task can hold millions of them, all of cost
+// 0) would scan it node by node.  Degrees never decrease inside a task, so
+// one wave per task finds its first node of degree >= 2 by a 64-way search.
+__global__ void k_task_starts(const int32_t *__restrict__ bnd, int64_t tasks, const int32_t *__restrict__ deg,
+                              int32_t *__restrict__ start) {
+    const int lane = __lane_id();
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; c < tasks; c += nw) {
+        // the answer lies in [lo, hi]; hi means "none below hi"
+        int64_t lo = bnd[c], hi = bnd[c + 1];
+        if (lo < hi && deg[lo] < 2) {
+            while (hi - lo > 64) {
+                const int64_t step = (hi - lo + 63) / 64;  // 64 probes cover [lo, hi)
+                const int64_t p = min(lo + lane * step, hi - 1);
+                const uint64_t b = __ballot(deg[p] >= 2);
+                if (!b) {
+                    lo = min(lo + 63 * step, hi - 1) + 1;
+                } else {
+                    const int j = __ffsll((unsigned long long)b) - 1;
+                    const int64_t pj = min(lo + j * step, hi - 1);
+                    lo = j > 0 ? min(lo + (j - 1) * step, hi - 1) + 1 : lo;
+                    hi = pj;
+                }
+            }
+            const int64_t p = lo + lane;
+            const uint64_t b = __ballot(p < hi && deg[p] >= 2);
+            lo = b ? lo + __ffsll((unsigned long long)b) - 1 : hi;
+        }
+        if (lane == 0) start[c] = (int32_t)lo;
+    }
+}
+
 __global__ void k_task_graph(const int32_t *__restrict__ bnd, int64_t ntasks, const int64_t *__restrict__ node_base,
                              int k, int32_t *__restrict__ gid) {
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ntasks; c += (int64_t)gridDim.x * blockDim.x) {
@@ -1455,9 +1490,13 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
     BuildParams bpr = bp;
     bpr.rounds = bp.rounds > 0 ? bp.rounds : auto_rounds(pk.k, M);
     out.rounds = bpr.rounds;
-    schedule_sources(f, wmed.p, wlarge.p, N, pk.k, out.node_base.p, bpr, al, tmp, s, sc, maxd.p, &out.max_dhat, pre);
+    // labels follow the degree order inside each graph, so degrees never
+    // decrease inside a task
+    schedule_sources(f, wmed.p, wlarge.p, N, pk.k, out.node_base.p, bpr, al, tmp, s, sc, maxd.p, &out.max_dhat, pre,
+                     out.deg.p);
     out.bnd = std::move(sc.bnd);
     out.gid = std::move(sc.gid);
+    out.start = std::move(sc.start);
     out.big = std::move(sc.big);
     out.tasks = sc.tasks;
     out.total_cost = sc.total_cost;
@@ -1478,7 +1517,8 @@ std::vector<int64_t> schedule_targets(int64_t total, const BuildParams &bp) {
 
 void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wlarge, int64_t N, int k,
                       const int64_t *node_base, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
-                      Schedule &out, const int32_t *maxd_dev, int32_t *maxd_host, PresetTargets *pre) {
+                      Schedule &out, const int32_t *maxd_dev, int32_t *maxd_host, PresetTargets *pre,
+                      const int32_t *deg_sorted) {
     DevBuf<int64_t> F(tmp, (size_t)N + 1);
     DevBuf<int64_t> pmed(tmp, (size_t)N + 1), plarge(tmp, (size_t)N + 1);
     exclusive_scan(f, F.p, N, true, tmp, s);
@@ -1523,6 +1563,11 @@ void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wl
     } else {
         out.bnd = std::move(bnd);
         out.tasks = ntg;
+    }
+    if (deg_sorted && out.tasks > 0) {
+        out.start = DevBuf<int32_t>(al, (size_t)out.tasks);
+        k_task_starts<<<grid_for(out.tasks * 64), kThreads, 0, s>>>(out.bnd.p, out.tasks, deg_sorted, out.start.p);
+        TC_LAUNCH_CHECK();
     }
     // Scratch buffers are released in stream order when this scope ends.
     TC_HIP(hipStreamSynchronize(s));

@@ -404,7 +404,9 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
         int64_t *__restrict__ tv = descs[h].tv;
         const int32_t row_lo = SLICE ? descs[h].row_lo : 0;
         const int64_t lt = c - descs[h].task_base;
-        const int32_t v0 = descs[h].bnd[lt], v1 = descs[h].bnd[lt + 1];
+        // the scan starts past the task's leading nodes of degree < 2 when the
+        // build recorded where they end
+        const int32_t v0 = descs[h].start ? descs[h].start[lt] : descs[h].bnd[lt], v1 = descs[h].bnd[lt + 1];
         const int g = descs[h].gid ? descs[h].gid[lt] : 0;
         // rows are addressed from the first entry of the task's graph
         int64_t ebase = 0, mg = descs[h].m;

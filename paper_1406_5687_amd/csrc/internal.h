@@ -56,6 +56,7 @@ struct Oriented {
     DevBuf<int64_t> node_base;  // k+1 (device copy)
     DevBuf<int32_t> bnd;        // tasks+1
     DevBuf<int32_t> gid;        // tasks (k > 1 only)
+    DevBuf<int32_t> start;      // tasks: where each task's scan begins (see Schedule::start)
     DevBuf<int32_t> big;        // long lists, handled by whole workgroups: medium ones first
     int64_t M = 0;
     int64_t tasks = 0;
@@ -82,6 +83,9 @@ void fill_zero(void *p, size_t bytes, hipStream_t s);
 struct Schedule {
     DevBuf<int32_t> bnd;  // tasks+1
     DevBuf<int32_t> gid;  // tasks (k > 1 only)
+    // tasks, only when schedule_sources is given the degrees: the first node of
+    // task c of degree 2 or more (bnd[c+1] if none), where its scan begins
+    DevBuf<int32_t> start;
     DevBuf<int32_t> big;  // medium lists first, then large ones
     int64_t tasks = 0;
     int64_t total_cost = 0;
@@ -99,7 +103,7 @@ struct PresetTargets {
 void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wlarge, int64_t N, int k,
                       const int64_t *node_base, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
                       Schedule &out, const int32_t *maxd_dev = nullptr, int32_t *maxd_host = nullptr,
-                      PresetTargets *pre = nullptr);
+                      PresetTargets *pre = nullptr, const int32_t *deg_sorted = nullptr);
 std::vector<int64_t> task_targets(int64_t total, int32_t W, int64_t min_chunk, bool static_chunks = false);
 // bnd[0] = 0, bnd[j+1] = first x in [0, N] with F[x] >= targets[j] (targets < 0: N)
 void task_bounds(const int64_t *F, int64_t N, const std::vector<int64_t> &targets, int32_t *bnd, Allocator &tmp,
@@ -164,6 +168,7 @@ struct CountDesc {
     const int64_t *off;  // target rows: row of label t is off[t - row_lo] .. off[t - row_lo + 1] in col
     const int32_t *col;
     const int32_t *bnd;
+    const int32_t *start;      // tasks, or NULL: task c scans nodes start[c] .. bnd[c+1]
     const int32_t *gid;        // NULL when k == 1
     const int64_t *node_base;  // k+1
     const int32_t *big;  // long lists: [0, nmed) up to 1024 entries, [nmed, nbig) longer

@@ -363,6 +363,60 @@ def test_packed_handle_equals_separate(tc):
             assert nb[gid[c]] <= bnd[c] and bnd[c + 1] <= nb[gid[c] + 1]
 
 
+def _sparse_core(n, core_n, pendants, seed):
+    # a dense core, pendant nodes hanging off it, and isolated nodes: most
+    # labels of the degree order have degree 0 or 1 and come first
+    core = graphgen.preferential_attachment(core_n, 6, seed)
+    rng = np.random.default_rng(seed)
+    pend = (core_n + rng.permutation(n - core_n)[:pendants]).astype(np.int32)
+    src = np.concatenate([core.src, pend])
+    dst = np.concatenate([core.dst, rng.integers(0, core_n, pendants).astype(np.int32)])
+    return src, dst
+
+
+@pytest.mark.parametrize("kw", [dict(workers=7), dict(workers=64), dict(workers=4096),
+                                dict(workers=64, cost_fn=0), dict(workers=64, cost_fn=1),
+                                dict(workers=50, static_chunks=True)])
+def test_leading_low_degree_block(tc, kw):
+    # tasks reaching into the leading labels of degree < 2 start their scan
+    # past them; counts and the exported Eq. (1)/(2) schedule are unchanged
+    n = 300_000
+    src, dst = _sparse_core(n, 3000, 40_000, 31)
+    T_ref, tv_ref, _ = oracle.count(n, src, dst)
+    with tc.build_oriented([(n, src, dst)], **kw) as h:
+        tv, tot = h.count_per_node()
+        tot2 = h.count_total()
+        bnd, _ = h.export_schedule()
+    assert tot[0] == T_ref and tot2[0] == T_ref
+    np.testing.assert_array_equal(tv, tv_ref)
+    if len(kw) == 1:
+        W = kw["workers"]
+        m, off_o, col_o, deg = oracle.orient(n, src, dst)
+        perm = oracle.degree_order(deg)
+        f = oracle.costs(off_o, col_o, deg, oracle.COST_PRIOR)[perm].copy()
+        f[np.diff(off_o)[perm] > 128] = 0
+        total = int(f.sum())
+        np.testing.assert_array_equal(bnd, oracle.schedule(f, W, max(256, total // (W * 128 + 1))))
+        assert bnd[0] == 0 and (np.diff(bnd) >= 0).all()
+
+
+def test_leading_low_degree_blocks_packed(tc):
+    # every packed graph leads with its own block of degree < 2
+    parts = [_sparse_core(n, c, p, s) for n, c, p, s in
+             ((120_000, 1500, 20_000, 41), (5_000, 4000, 100, 42), (80_000, 900, 30_000, 43))]
+    ns = (120_000, 5_000, 80_000)
+    with tc.build_oriented([(n, s_, d_) for n, (s_, d_) in zip(ns, parts)], workers=64) as h:
+        tv, tot = h.count_per_node()
+        tot2 = h.count_total()
+    np.testing.assert_array_equal(tot, tot2)
+    base = 0
+    for i, (n, (s_, d_)) in enumerate(zip(ns, parts)):
+        T_ref, tv_ref, _ = oracle.count(n, s_, d_)
+        assert tot[i] == T_ref
+        np.testing.assert_array_equal(tv[base:base + n], tv_ref)
+        base += n
+
+
 def test_batch_of_handles_equals_separate(tc):
     parts = [graphgen.rmat(11, 16, seed=s) for s in range(3)] + [graphgen.erdos_renyi(800, 5000, 9)]
     hs = [tc.build_oriented([(p.n, p.src, p.dst)]) for p in parts]
