@@ -86,7 +86,7 @@ typedef struct {
     int32_t small_max;  /* lists up to this length are handled by one wave, longer ones by a
                            whole workgroup; 0 = automatic (128, also the maximum) */
     int32_t lds_list_max; /* longest list a workgroup stages in LDS; longer lists are probed by
-                             binary search in device memory; 0 = automatic (4096, the maximum) */
+                             binary search in device memory; 0 = automatic (1920, the maximum) */
     int32_t time_kernels; /* 1: record device events around the counting kernels of each count
                              call; the elapsed time is reported by tc_graph_info.  2: also record
                              when each worker starts and stops (tc_worker_times) */

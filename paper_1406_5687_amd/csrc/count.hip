@@ -19,7 +19,7 @@
 //   - lists with 2 <= a <= small_max (at most 128): one wave per list, tasks
 //     of consecutive sources pulled by waves (k_count_small);
 //   - longer lists: one workgroup per list (k_count_wide): 4 waves for lists
-//     up to 768 entries, 16 waves above; lists longer than the LDS table
+//     up to 768 entries, 8 waves up to 1920; lists longer than the LDS table
 //     (lds_max) are probed by binary search in device memory instead.
 //
 // Per-node counts (Section II): a triangle {s, t_i, w} found at probe w adds
@@ -48,9 +48,9 @@ constexpr int kMedWaves = 4;
 constexpr int kMedMax = 768;  // 24 KB of LDS per workgroup: six resident per CU
 constexpr int kMedHashBits = 11;  // load factor <= 1/2
 
-constexpr int kLdsMax = 4096;
-constexpr int kBigHashBits = 13;  // load factor <= 1/2
-constexpr int kBigWaves = 16;
+constexpr int kLdsMax = 1920;    // 52 KB of LDS per workgroup: three resident per CU
+constexpr int kBigHashBits = 12;  // load factor <= 1/2
+constexpr int kBigWaves = 8;
 constexpr int kBigThreads = kBigWaves * 64;
 
 constexpr int kWin = 4;           // 64-id windows walked per step
@@ -468,7 +468,8 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
 
 // Long lists: one workgroup per list.  Two tiers share this code: lists up to
 // 768 entries go to 4-wave workgroups with a ~24 KB LDS table (six per
-// compute unit), longer ones to 16-wave workgroups with a 127 KB table.
+// compute unit), longer ones to 8-wave workgroups with a ~52 KB table (three
+// per compute unit; the kernel is held to 80 registers so that 24 waves fit).
 // Lists are handed out longest-rank first (roughly longest first).
 template <int WAVES, int LMAX, int HBITS, bool IDX32>
 struct WideLds {
@@ -566,7 +567,7 @@ __device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &r
 
 // tier 1: lists in big[0, nmed); tier 2: lists in big[nmed, nbig)
 template <bool PER_NODE, bool IDX32, int WAVES, int LMAX, int HBITS, int TIER, bool SLICE>
-__global__ __launch_bounds__(WAVES * 64) void k_count_wide(const CountDesc *__restrict__ descs, int ndesc,
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVES == 8 ? 6 : 1))) void k_count_wide(const CountDesc *__restrict__ descs, int ndesc,
                                                            int64_t total_items, uint32_t *__restrict__ head,
                                                            int lds_max, unsigned long long *__restrict__ times) {
     constexpr int kThreadsW = WAVES * 64;
@@ -741,7 +742,10 @@ void launch_all(CountLaunch &L, int lds_max, hipStream_t s) {
         TC_LAUNCH_CHECK();
     }
     if (L.total_large > 0) {
-        const int blocks = (int)std::min<int64_t>(cus, L.total_large);
+        int per_cu = 0;
+        TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, k_count_wide<PER_NODE, IDX32, kBigWaves, kLdsMax, kBigHashBits, 2, SLICE>, kBigThreads, 0));
+        const int blocks = (int)std::min<int64_t>((int64_t)std::max(1, per_cu) * cus, L.total_large);
         unsigned long long *tm = times_for(blocks);
         L.times_tier[2] = tm ? blocks : 0;
         k_count_wide<PER_NODE, IDX32, kBigWaves, kLdsMax, kBigHashBits, 2, SLICE>

@@ -241,7 +241,7 @@ def test_tuning_invariance(tc, kw):
 @pytest.mark.parametrize("n", [300, 1100, 4200])
 def test_long_lists_all_paths(tc, n):
     # K_n: lists up to n-1 entries.  300 -> 4-wave workgroups; 1100 -> also the
-    # 16-wave workgroups; 4200 -> also lists longer than the LDS table (binary
+    # 8-wave workgroups; 4200 -> also lists longer than the LDS table (binary
     # search in device memory).  Smaller lds_list_max forces the binary-search
     # path in both workgroup kernels.
     nn, s, d = gs.complete(n)

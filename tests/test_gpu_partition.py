@@ -78,7 +78,7 @@ def test_closed_forms_partitioned(tc, P):
 
 
 def test_partitioned_long_lists(tc):
-    # K_1100: lists past 768 entries (16-wave workgroups) and, with a small
+    # K_1100: lists past 768 entries (8-wave workgroups) and, with a small
     # LDS cap, the binary-search path, all fed from streamed ranges
     nn, s, d = gs.complete(1100)
     for kw in (dict(), dict(lds_list_max=64)):
