@@ -166,7 +166,10 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
     total = uniform32(total);
     e_begin = uniform32(e_begin);
     e_end = uniform32(e_end);
-    for (int32_t e0 = e_begin; e0 < e_end; e0 += kStep) {
+    // A step wholly inside the sequence (every step of a source but its last)
+    // needs no masking of lanes past the end: the body is instantiated twice.
+    auto step = [&](int32_t e0, auto full_c) {
+        constexpr bool FULL = decltype(full_c)::value;
         int seg[kWin];
         int32_t w[kWin];
         bool ok[kWin];
@@ -178,7 +181,7 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
             for (int q = 0; q < kWin; ++q) {
                 seg[q] = cur;
                 const int32_t e = e0 + 64 * q + lane;
-                ok[q] = e < total;
+                ok[q] = FULL || e < total;
                 w[q] = rd.load(b + e, ok[q]);
             }
         } else {
@@ -204,7 +207,7 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
             for (int q = 0; q < kWin; ++q) {
                 seg[q] = min(cur + pre[q] + mbcnt64(M[q]) + (int)((fw >> (8 * q)) & 1u), nt - 1);
                 const int32_t e = e0 + 64 * q + lane;
-                ok[q] = e < total;
+                ok[q] = FULL || e < total;
                 w[q] = rd.load(base[seg[q]] + e, ok[q]);
             }
         }
@@ -218,10 +221,10 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
                 sl[q] = hash_slot(w[q], HBITS);
                 k[q] = key[sl[q]];
             }
-            bool chain = false;
+            uint64_t chain = 0;
 #pragma unroll
-            for (int q = 0; q < kWin; ++q) chain = chain || (k[q] != w[q] && k[q] != -1);
-            if (__ballot(chain)) {
+            for (int q = 0; q < kWin; ++q) chain |= __ballot(k[q] != w[q] && k[q] != -1);
+            if (chain) {
 #pragma unroll
                 for (int q = 0; q < kWin; ++q) {
                     while (k[q] != w[q] && k[q] != -1) {  // collision chain (rare)
@@ -281,6 +284,12 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
         if (nc + 1 < nt && uniform32(P[nc + 1]) == e0 + kStep) ++nc;
         cur = nc;
         wave_lds_sync();
+    };
+    for (int32_t e0 = e_begin; e0 < e_end; e0 += kStep) {
+        if (e0 + kStep <= total)
+            step(e0, std::true_type{});
+        else
+            step(e0, std::false_type{});
     }
     return hits;
 }
