@@ -813,7 +813,23 @@ __global__ __launch_bounds__(kThreads) void k_sort_rows(const int64_t *__restric
             rest &= rest - 1;
             wave_sort_row(col, readlane64(r0, l), readlane32(a, l), lane, dh, f, g0 + l, dup);
         }
+        // longer rows are listed for one radix sort; their PRIOR costs do not
+        // depend on the order of their entries and are added up here, one
+        // wave per row, so the task table can be built before they are sorted
         if (a > kMidRow) long_rows[atomicAdd(nlong, 1u)] = (int32_t)r;
+        if (f) {
+            uint64_t lng = __ballot(a > kMidRow);
+            while (lng) {
+                const int l = __ffsll((unsigned long long)lng) - 1;
+                lng &= lng - 1;
+                const int64_t w0 = readlane64(r0, l);
+                const int32_t wa = readlane32(a, l);
+                int64_t c = 0;
+                for (int64_t p = lane; p < wa; p += 64) c += dh[col[w0 + p]];
+                c = wave_sum(c);
+                if (lane == 0) f[g0 + l] = (int64_t)wa * wa + c;
+            }
+        }
     }
 }
 
@@ -860,23 +876,6 @@ __global__ void k_prior_total(const int64_t *__restrict__ off, const int32_t *__
         int64_t t = 0;
         for (int w = 0; w < kThreads / 64; ++w) t += wpart[w];
         atomicAdd(acc, (unsigned long long)t);
-    }
-}
-
-// PRIOR costs of the long rows (one wave per row).
-__global__ void k_long_costs(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
-                             const int32_t *__restrict__ long_rows, int64_t L, const int32_t *__restrict__ dh,
-                             int64_t *__restrict__ f) {
-    const int lane = __lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t i = wave; i < L; i += nwaves) {
-        const int32_t r = long_rows[i];
-        const int64_t r0 = off[r], a = off[r + 1] - r0;
-        int64_t c = 0;
-        for (int64_t p = lane; p < a; p += 64) c += dh[col[r0 + p]];
-        c = wave_sum(c);
-        if (lane == 0) f[r] = a * a + c;
     }
 }
 
@@ -1208,32 +1207,35 @@ struct EventGuard {
 };
 }  // namespace
 
-// Sorts every row of (off, col) ascending.  ka / kb: scratch of cap keys each.
-// With f non-null, also writes the PRIOR cost of every row into f (dh: row
-// lengths).
-void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka, uint64_t *kb, int64_t cap,
-               const int32_t *dh, int64_t *f, unsigned int *dup, Allocator &tmp, hipStream_t s,
-               const std::function<void()> &while_sorting) {
+// Row sort in two parts.  sort_rows_begin enqueues the sort of every row of up
+// to kMidRow entries and, with f non-null, the PRIOR cost of every row (dh:
+// row lengths); longer rows are listed in long_rows / nlong.  sort_rows_finish
+// sorts the L listed rows (L read from nlong by the caller).  Nothing in
+// between waits for the device.
+struct LongRows {
+    DevBuf<int32_t> rows;
+    DevBuf<unsigned int> n;
+};
+
+void sort_rows_begin(const int64_t *off, int64_t N, int32_t *col, const int32_t *dh, int64_t *f,
+                     unsigned int *dup, LongRows &lr, Allocator &tmp, hipStream_t s) {
+    lr.rows = DevBuf<int32_t>(tmp, (size_t)std::max<int64_t>(N, 1));
+    lr.n = DevBuf<unsigned int>(tmp, 1);
+    fill_zero(lr.n.p, 4, s);
     if (N <= 0) return;
-    DevBuf<int32_t> long_rows(tmp, (size_t)N);
-    DevBuf<unsigned int> nlong(tmp, 1);
-    fill_zero(nlong.p, 4, s);
     const int64_t waves = std::min<int64_t>(ceil_div(N, 64), (int64_t)device_cu_count() * 64);
-    k_sort_rows<<<(unsigned)ceil_div(waves * 64, kThreads), kThreads, 0, s>>>(off, N, col, long_rows.p, nlong.p,
-                                                                               dh, f, dup);
+    k_sort_rows<<<(unsigned)ceil_div(waves * 64, kThreads), kThreads, 0, s>>>(off, N, col, lr.rows.p, lr.n.p, dh,
+                                                                               f, dup);
     TC_LAUNCH_CHECK();
-    if (while_sorting) while_sorting();  // host work that overlaps the row sort
-    unsigned int L = 0;
-    d2h(&L, nlong.p, 1, s);
-    TC_HIP(hipStreamSynchronize(s));
+}
+
+// ka / kb: scratch of cap keys each.
+void sort_rows_finish(const int64_t *off, int32_t *col, int gb, uint64_t *ka, uint64_t *kb, int64_t cap,
+                      unsigned int *dup, const LongRows &lr, unsigned int L, Allocator &tmp, hipStream_t s) {
     if (L == 0) return;
-    if (f) {
-        const int64_t cw = std::min<int64_t>(L, (int64_t)device_cu_count() * 64);
-        k_long_costs<<<(unsigned)ceil_div(cw * 64, kThreads), kThreads, 0, s>>>(off, col, long_rows.p, L, dh, f);
-        TC_LAUNCH_CHECK();
-    }
+    const int32_t *long_rows = lr.rows.p;
     DevBuf<int64_t> len(tmp, L), epos(tmp, (size_t)L + 1);
-    k_long_lengths<<<grid_for(L), kThreads, 0, s>>>(off, long_rows.p, L, len.p);
+    k_long_lengths<<<grid_for(L), kThreads, 0, s>>>(off, long_rows, L, len.p);
     TC_LAUNCH_CHECK();
     exclusive_scan(len.p, epos.p, L, true, tmp, s);
     int64_t E = 0;
@@ -1241,19 +1243,30 @@ void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka
     TC_HIP(hipStreamSynchronize(s));
     if (E > cap) throw Error(TC_ERR_DEVICE, "long-row scratch smaller than the long rows");
     const int64_t lw = std::min<int64_t>(L, (int64_t)device_cu_count() * 64);
-    k_long_keys<<<(unsigned)ceil_div(lw * 64, kThreads), kThreads, 0, s>>>(off, col, long_rows.p, epos.p, L, gb, ka);
+    k_long_keys<<<(unsigned)ceil_div(lw * 64, kThreads), kThreads, 0, s>>>(off, col, long_rows, epos.p, L, gb, ka);
     TC_LAUNCH_CHECK();
     const int lb = std::max(1, bits_for((uint64_t)(L - 1)));
     uint64_t *sorted = radix_sort_u64(ka, kb, E, 0, gb + lb, tmp, s);
-    k_long_write<<<grid_for(E, 4), kThreads, 0, s>>>(sorted, E, gb, off, long_rows.p, epos.p, col, dup);
+    k_long_write<<<grid_for(E, 4), kThreads, 0, s>>>(sorted, E, gb, off, long_rows, epos.p, col, dup);
     TC_LAUNCH_CHECK();
+}
+
+// Both parts with the long-row count read in between.
+void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka, uint64_t *kb, int64_t cap,
+               unsigned int *dup, Allocator &tmp, hipStream_t s) {
+    LongRows lr;
+    sort_rows_begin(off, N, col, nullptr, nullptr, dup, lr, tmp, s);
+    unsigned int L = 0;
+    d2h(&L, lr.n.p, 1, s);
+    TC_HIP(hipStreamSynchronize(s));
+    sort_rows_finish(off, col, gb, ka, kb, cap, dup, lr, L, tmp, s);
 }
 
 void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp, Allocator &al,
                 Allocator &tmp, hipStream_t s, Oriented &out);
 void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
                    Oriented &out, const uint64_t *okeys, int gb, int64_t *f_prior = nullptr,
-                   PresetTargets *pre = nullptr);
+                   PresetTargets *pre = nullptr, Piggyback *pb = nullptr);
 
 void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
                            Allocator &al, hipStream_t s, Oriented &out) {
@@ -1424,16 +1437,28 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
         }
         BuildParams bpr = bp;
         bpr.rounds = bp.rounds > 0 ? bp.rounds : auto_rounds(pk.k, M);
-        sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, rowlen.p, f.p, dup, tmp, s, [&] {
-            if (!htot) return;
+        LongRows lr;
+        sort_rows_begin(out.off.p, N, out.col.p, rowlen.p, f.p, dup, lr, tmp, s);
+        if (htot) {  // host work that overlaps the row sort
             TC_HIP(hipEventSynchronize(ev.e));
             pre.total = (int64_t)*htot;
             pre.targets = schedule_targets(pre.total, bpr);
-        });
-        schedule_into(pk, bp, al, tmp, s, out, nullptr, gb, f.p, &pre);
+        }
+        // the task table is enqueued behind the row sort; the long-row count
+        // and the repeat flag come back with the schedule's totals
+        Piggyback pb;
+        pb.dev[0] = lr.n.p;
+        pb.dev[1] = dup;
+        schedule_into(pk, bp, al, tmp, s, out, nullptr, gb, f.p, &pre, &pb);
+        const unsigned int L = pb.host[0];
+        if (L == 0) {
+            TC_HIP(hipStreamSynchronize(s));
+            return !(simple && pb.host[1]);  // an edge given twice: take the canonical path
+        }
+        sort_rows_finish(out.off.p, out.col.p, gb, ka.p, kb.p, M_in, dup, lr, L, tmp, s);
     } else {
         schedule_into(pk, bp, al, tmp, s, out, okeys, gb);
-        if (M > 0) sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, nullptr, nullptr, dup, tmp, s, nullptr);
+        if (M > 0) sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, dup, tmp, s);
     }
     if (simple && M > 0) {
         uint32_t hdup = 0;
@@ -1458,7 +1483,8 @@ void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const
 // Step 6 proper.  okeys (sorted pair keys) speed up the edge costs when the
 // build still holds them; otherwise costs are computed row by row.
 void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
-                   Oriented &out, const uint64_t *okeys, int gb, int64_t *f_prior, PresetTargets *pre) {
+                   Oriented &out, const uint64_t *okeys, int gb, int64_t *f_prior, PresetTargets *pre,
+                   Piggyback *pb) {
     const int64_t N = pk.N, M = out.M;
     DevBuf<int64_t> f_own;
     int64_t *f = f_prior;  // PRIOR costs computed by the caller, else computed here
@@ -1493,7 +1519,7 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
     // labels follow the degree order inside each graph, so degrees never
     // decrease inside a task
     schedule_sources(f, wmed.p, wlarge.p, N, pk.k, out.node_base.p, bpr, al, tmp, s, sc, maxd.p, &out.max_dhat, pre,
-                     out.deg.p);
+                     out.deg.p, pb);
     out.bnd = std::move(sc.bnd);
     out.gid = std::move(sc.gid);
     out.start = std::move(sc.start);
@@ -1518,7 +1544,7 @@ std::vector<int64_t> schedule_targets(int64_t total, const BuildParams &bp) {
 void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wlarge, int64_t N, int k,
                       const int64_t *node_base, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
                       Schedule &out, const int32_t *maxd_dev, int32_t *maxd_host, PresetTargets *pre,
-                      const int32_t *deg_sorted) {
+                      const int32_t *deg_sorted, Piggyback *pb) {
     DevBuf<int64_t> F(tmp, (size_t)N + 1);
     DevBuf<int64_t> pmed(tmp, (size_t)N + 1), plarge(tmp, (size_t)N + 1);
     exclusive_scan(f, F.p, N, true, tmp, s);
@@ -1529,7 +1555,46 @@ void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wl
     DevBuf<int64_t> tot4(tmp, 4);
     k_totals<<<1, 64, 0, s>>>(F.p + N, pmed.p + N, plarge.p + N, maxd_dev, tot4.p);
     TC_LAUNCH_CHECK();
+
+    // task table from targets (bnd, and for k > 1 the merged bounds and graph
+    // ids), then where each task's scan begins
+    auto make_table = [&](const std::vector<int64_t> &tg) {
+        const int64_t ntg = (int64_t)tg.size();
+        DevBuf<int32_t> bnd(al, (size_t)ntg + 1);
+        task_bounds(F.p, N, tg, bnd.p, tmp, s);
+        if (k > 1) {
+            const int64_t tot = ntg + 1 + (k - 1);
+            out.bnd = DevBuf<int32_t>(al, (size_t)tot);
+            k_merge_bounds<<<grid_for(tot), kThreads, 0, s>>>(bnd.p, ntg + 1, node_base, k, out.bnd.p);
+            TC_LAUNCH_CHECK();
+            out.tasks = tot - 1;
+            out.gid = DevBuf<int32_t>(al, (size_t)out.tasks);
+            k_task_graph<<<grid_for(out.tasks), kThreads, 0, s>>>(out.bnd.p, out.tasks, node_base, k, out.gid.p);
+            TC_LAUNCH_CHECK();
+        } else {
+            out.bnd = std::move(bnd);
+            out.gid = DevBuf<int32_t>();
+            out.tasks = ntg;
+        }
+        out.start = DevBuf<int32_t>();
+        if (deg_sorted && out.tasks > 0) {
+            out.start = DevBuf<int32_t>(al, (size_t)out.tasks);
+            k_task_starts<<<grid_for(out.tasks * 64), kThreads, 0, s>>>(out.bnd.p, out.tasks, deg_sorted,
+                                                                         out.start.p);
+            TC_LAUNCH_CHECK();
+        }
+    };
+    // Targets computed ahead (from the early total) give the task table
+    // before the totals come back; it stands if the totals agree.
+    const int64_t ahead_total = pre ? pre->total : -1;
+    if (ahead_total >= 0) make_table(pre->targets);
+
     d2h(hv, tot4.p, 4, s);
+    if (pb) {
+        for (int i = 0; i < 2; ++i)
+            if (pb->dev[i]) d2h(&pb->host[i], pb->dev[i], 1, s);
+    }
+    // (also the point after which the pinned staging of the targets is free)
     TC_HIP(hipStreamSynchronize(s));
     out.total_cost = hv[0];
     out.nmed = hv[1];
@@ -1545,32 +1610,12 @@ void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wl
         k_compact_index<<<grid_for(N, 4), kThreads, 0, s>>>(wlarge, plarge.p, N, out.big.p + out.nmed);
         TC_LAUNCH_CHECK();
     }
-
-    std::vector<int64_t> tg = (pre && pre->total == out.total_cost) ? std::move(pre->targets)
-                                                                      : schedule_targets(out.total_cost, bp);
-    const int64_t ntg = (int64_t)tg.size();
-    DevBuf<int32_t> bnd(al, (size_t)ntg + 1);
-    task_bounds(F.p, N, tg, bnd.p, tmp, s);
-    if (k > 1) {
-        const int64_t tot = ntg + 1 + (k - 1);
-        out.bnd = DevBuf<int32_t>(al, (size_t)tot);
-        k_merge_bounds<<<grid_for(tot), kThreads, 0, s>>>(bnd.p, ntg + 1, node_base, k, out.bnd.p);
-        TC_LAUNCH_CHECK();
-        out.tasks = tot - 1;
-        out.gid = DevBuf<int32_t>(al, (size_t)out.tasks);
-        k_task_graph<<<grid_for(out.tasks), kThreads, 0, s>>>(out.bnd.p, out.tasks, node_base, k, out.gid.p);
-        TC_LAUNCH_CHECK();
-    } else {
-        out.bnd = std::move(bnd);
-        out.tasks = ntg;
-    }
-    if (deg_sorted && out.tasks > 0) {
-        out.start = DevBuf<int32_t>(al, (size_t)out.tasks);
-        k_task_starts<<<grid_for(out.tasks * 64), kThreads, 0, s>>>(out.bnd.p, out.tasks, deg_sorted, out.start.p);
-        TC_LAUNCH_CHECK();
+    if (ahead_total != out.total_cost) {
+        make_table(schedule_targets(out.total_cost, bp));
+        // the pinned staging of the targets is reused by the next call
+        TC_HIP(hipStreamSynchronize(s));
     }
     // Scratch buffers are released in stream order when this scope ends.
-    TC_HIP(hipStreamSynchronize(s));
 }
 
 int32_t auto_rounds(int32_t k, int64_t M) {

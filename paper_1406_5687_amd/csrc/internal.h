@@ -100,10 +100,17 @@ struct PresetTargets {
     int64_t total = -1;
     std::vector<int64_t> targets;
 };
+// Device words copied to the host together with the schedule's totals, so
+// that one synchronisation serves both.
+struct Piggyback {
+    const uint32_t *dev[2] = {nullptr, nullptr};
+    uint32_t host[2] = {0, 0};
+};
 void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wlarge, int64_t N, int k,
                       const int64_t *node_base, const BuildParams &bp, Allocator &al, Allocator &tmp, hipStream_t s,
                       Schedule &out, const int32_t *maxd_dev = nullptr, int32_t *maxd_host = nullptr,
-                      PresetTargets *pre = nullptr, const int32_t *deg_sorted = nullptr);
+                      PresetTargets *pre = nullptr, const int32_t *deg_sorted = nullptr,
+                      Piggyback *pb = nullptr);
 std::vector<int64_t> task_targets(int64_t total, int32_t W, int64_t min_chunk, bool static_chunks = false);
 // bnd[0] = 0, bnd[j+1] = first x in [0, N] with F[x] >= targets[j] (targets < 0: N)
 void task_bounds(const int64_t *F, int64_t N, const std::vector<int64_t> &targets, int32_t *bnd, Allocator &tmp,
