@@ -85,6 +85,11 @@ void check_options(const tc_options *opt) {
         throw tc::Error(TC_ERR_INVALID_ARG, "unknown cost function");
 }
 
+// Stores a descriptor passed by value (kernel arguments need no host copy).
+__global__ void k_store_desc(tc::CountDesc d, tc::CountDesc *out) {
+    if (threadIdx.x == 0) *out = d;
+}
+
 // Per-handle descriptor used by single-handle counts (kept on the device).
 void ensure_scratch(tc_graph *g, bool per_node, hipStream_t s) {
     g->al.stream = s;
@@ -111,7 +116,8 @@ void ensure_scratch(tc_graph *g, bool per_node, hipStream_t s) {
         d.k = g->pk.k;
         d.small_max = g->small_max;
         if (!g->desc.p) g->desc = tc::DevBuf<tc::CountDesc>(g->al, 1);
-        TC_HIP(hipMemcpyAsync(g->desc.p, &d, sizeof(d), hipMemcpyHostToDevice, s));
+        k_store_desc<<<1, 64, 0, s>>>(d, g->desc.p);
+        TC_LAUNCH_CHECK();
         g->desc_has_tv = g->tv.p != nullptr;
     }
 }

@@ -523,7 +523,7 @@ __global__ void k_orient_keys(const uint64_t *__restrict__ ukeys, int64_t m, int
 // dst change value from one edge to the next (chk[2 + 2b], chk[3 + 2b]):
 // long runs of one id (an edge list made from adjacency lists) let the
 // degrees be counted from the runs instead of a histogram.
-constexpr int kCheckBlocks = 8192;  // partial counts go to the host: 16 B per workgroup
+constexpr int kCheckBlocks = 8192;  // partial counts: 16 B per workgroup
 
 __global__ void k_check_pairs(const int32_t *__restrict__ src, const int32_t *__restrict__ dst, int64_t m,
                               int64_t n, unsigned long long *__restrict__ chk) {
@@ -561,6 +561,35 @@ __global__ void k_check_pairs(const int32_t *__restrict__ src, const int32_t *__
         unsigned long long t = 0;
         for (int q = 0; q < kThreads / 64; ++q) t += part[threadIdx.x][q];
         chk[2 + 2 * blockIdx.x + threadIdx.x] = t;
+    }
+}
+
+// out[0] = chk[0] (the flags), out[1] / out[2] = the change counts of src /
+// dst summed over the nblk workgroups of k_check_pairs (one workgroup).
+__global__ void k_check_sums(const unsigned long long *__restrict__ chk, unsigned nblk,
+                             unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long part[2][kThreads / 64];
+    unsigned long long s0 = 0, s1 = 0;
+    for (unsigned b = threadIdx.x; b < nblk; b += blockDim.x) {
+        s0 += chk[2 + 2 * (size_t)b];
+        s1 += chk[3 + 2 * (size_t)b];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    if (__lane_id() == 0) {
+        part[0][threadIdx.x >> 6] = s0;
+        part[1][threadIdx.x >> 6] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t0 = 0, t1 = 0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+            t0 += part[0][w];
+            t1 += part[1][w];
+        }
+        out[0] = chk[0];
+        out[1] = t0;
+        out[2] = t1;
     }
 }
 
@@ -1002,12 +1031,16 @@ __global__ void k_node_costs(const int64_t *__restrict__ off, const int32_t *__r
     }
 }
 
-__global__ void k_totals(const int64_t *a, const int64_t *b, const int64_t *c, const int32_t *d, int64_t *out) {
+// out[0..3] = *a, *b, *c, *d; out[4], out[5] = *e0, *e1 (0 for NULL pointers)
+__global__ void k_totals(const int64_t *a, const int64_t *b, const int64_t *c, const int32_t *d, const uint32_t *e0,
+                         const uint32_t *e1, int64_t *out) {
     if (threadIdx.x == 0) {
         out[0] = *a;
         out[1] = *b;
         out[2] = *c;
         out[3] = d ? (int64_t)*d : 0;
+        out[4] = e0 ? (int64_t)*e0 : 0;
+        out[5] = e1 ? (int64_t)*e1 : 0;
     }
 }
 
@@ -1198,6 +1231,17 @@ struct PinnedStage {
 };
 thread_local PinnedStage t_stage;
 thread_local PinnedStage t_total;  // the early cost total
+thread_local PinnedStage t_words;  // small results read back at a synchronisation
+
+// Copies count words from dev to host through pinned memory (one small copy)
+// and waits for it.
+template <class T>
+void read_words(T *host, const T *dev, size_t count, hipStream_t s) {
+    void *pin = t_words.get(count * sizeof(T));
+    TC_HIP(hipMemcpyAsync(pin ? pin : (void *)host, dev, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    TC_HIP(hipStreamSynchronize(s));
+    if (pin) std::memcpy(host, pin, count * sizeof(T));
+}
 
 struct EventGuard {
     hipEvent_t e = nullptr;
@@ -1329,16 +1373,14 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
         fill_zero(chk.p, 16, s);
         k_check_pairs<<<nblk, kThreads, 0, s>>>(src, dst, M_in, N, chk.p);
         TC_LAUNCH_CHECK();
-        std::vector<unsigned long long> hc(2 + 2 * (size_t)nblk);
-        d2h(hc.data(), chk.p, hc.size(), s);
-        TC_HIP(hipStreamSynchronize(s));
+        DevBuf<unsigned long long> sums(tmp, 3);
+        k_check_sums<<<1, kThreads, 0, s>>>(chk.p, nblk, sums.p);
+        TC_LAUNCH_CHECK();
+        unsigned long long hc[3] = {0, 0, 0};
+        read_words(hc, sums.p, 3, s);
         if (hc[0] & 1u) throw Error(TC_ERR_ID_RANGE, "an edge endpoint is outside 0..n-1 of its graph");
         if (hc[0] & 2u) return false;  // a loop: take the canonical path
-        unsigned long long bs = 0, bd = 0;
-        for (unsigned b = 0; b < nblk; ++b) {
-            bs += hc[2 + 2 * b];
-            bd += hc[3 + 2 * b];
-        }
+        const unsigned long long bs = hc[1], bd = hc[2];
         // count runs when they average 4 or more edges
         runs_src = (int64_t)bs * 4 <= M_in;
         runs_dst = (int64_t)bd * 4 <= M_in;
@@ -1550,10 +1592,11 @@ void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wl
     exclusive_scan(f, F.p, N, true, tmp, s);
     exclusive_scan(wmed, pmed.p, N, true, tmp, s);
     exclusive_scan(wlarge, plarge.p, N, true, tmp, s);
-    // the three totals and the longest list in one copy
-    int64_t hv[4] = {0, 0, 0, 0};
-    DevBuf<int64_t> tot4(tmp, 4);
-    k_totals<<<1, 64, 0, s>>>(F.p + N, pmed.p + N, plarge.p + N, maxd_dev, tot4.p);
+    // the three totals, the longest list and the caller's extra words in one copy
+    int64_t hv[6] = {0, 0, 0, 0, 0, 0};
+    DevBuf<int64_t> tot6(tmp, 6);
+    k_totals<<<1, 64, 0, s>>>(F.p + N, pmed.p + N, plarge.p + N, maxd_dev, pb ? pb->dev[0] : nullptr,
+                              pb ? pb->dev[1] : nullptr, tot6.p);
     TC_LAUNCH_CHECK();
 
     // task table from targets (bnd, and for k > 1 the merged bounds and graph
@@ -1589,13 +1632,12 @@ void schedule_sources(const int64_t *f, const uint32_t *wmed, const uint32_t *wl
     const int64_t ahead_total = pre ? pre->total : -1;
     if (ahead_total >= 0) make_table(pre->targets);
 
-    d2h(hv, tot4.p, 4, s);
-    if (pb) {
-        for (int i = 0; i < 2; ++i)
-            if (pb->dev[i]) d2h(&pb->host[i], pb->dev[i], 1, s);
-    }
     // (also the point after which the pinned staging of the targets is free)
-    TC_HIP(hipStreamSynchronize(s));
+    read_words(hv, tot6.p, 6, s);
+    if (pb) {
+        pb->host[0] = (uint32_t)hv[4];
+        pb->host[1] = (uint32_t)hv[5];
+    }
     out.total_cost = hv[0];
     out.nmed = hv[1];
     out.nbig = hv[1] + hv[2];
