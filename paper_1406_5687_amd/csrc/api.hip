@@ -90,6 +90,17 @@ __global__ void k_store_desc(tc::CountDesc d, tc::CountDesc *out) {
     if (threadIdx.x == 0) *out = d;
 }
 
+// Zeroes the queue heads (4 words), the totals (k) and, when tv is given, the
+// per-node counters (n): one launch for what a count starts from.
+__global__ void k_count_reset(uint32_t *heads, int64_t *totals, int64_t k, int64_t *tv, int64_t n) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    if (i0 < 4) heads[i0] = 0u;
+    for (int64_t i = i0; i < k; i += st) totals[i] = 0;
+    if (tv)
+        for (int64_t i = i0; i < n; i += st) tv[i] = 0;
+}
+
 // Per-handle descriptor used by single-handle counts (kept on the device).
 void ensure_scratch(tc_graph *g, bool per_node, hipStream_t s) {
     g->al.stream = s;
@@ -336,9 +347,13 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
                 g->timed = true;
             }
         } else {
-            tc::fill_zero(g->heads.p, 16, s);
-            tc::fill_zero(g->totals.p, k * sizeof(int64_t), s);
-            if (want_tv) tc::fill_zero(g->tv.p, (size_t)g->pk.N * sizeof(int64_t), s);
+            {
+                const int64_t n = want_tv ? g->pk.N : 0;
+                const int64_t words = std::max<int64_t>({n, (int64_t)k, 4});
+                const unsigned blocks = (unsigned)std::min<int64_t>((words + 1023) / 1024, 2048);
+                k_count_reset<<<blocks, 256, 0, s>>>(g->heads.p, g->totals.p, k, want_tv ? g->tv.p : nullptr, n);
+                TC_LAUNCH_CHECK();
+            }
             tc::CountLaunch L{};
             L.descs = g->desc.p;
             L.ndesc = 1;

@@ -1232,6 +1232,7 @@ struct PinnedStage {
 thread_local PinnedStage t_stage;
 thread_local PinnedStage t_total;  // the early cost total
 thread_local PinnedStage t_words;  // small results read back at a synchronisation
+thread_local PinnedStage t_bases;  // node and edge offsets of the packed graphs
 
 // Copies count words from dev to host through pinned memory (one small copy)
 // and waits for it.
@@ -1352,9 +1353,23 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
     const int gb = std::max(1, bits_for((uint64_t)std::max<int64_t>(N - 1, 1)));  // bits of a packed label
 
     out.node_base = DevBuf<int64_t>(al, (size_t)k + 1);
-    TC_HIP(hipMemcpyAsync(out.node_base.p, pk.node_base.data(), (k + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
     DevBuf<int64_t> edge_base(tmp, (size_t)k + 1);
-    TC_HIP(hipMemcpyAsync(edge_base.p, pk.edge_base.data(), (k + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    {
+        // both tables in one copy from pinned memory (a copy from pageable
+        // memory is staged and waited for); the staging is free again at the
+        // check pass's read-back, before any later build writes it
+        const size_t bytes = (size_t)(k + 1) * sizeof(int64_t);
+        auto *pin = static_cast<int64_t *>(t_bases.get(2 * bytes));
+        if (pin) {
+            std::memcpy(pin, pk.node_base.data(), bytes);
+            std::memcpy(pin + (k + 1), pk.edge_base.data(), bytes);
+            TC_HIP(hipMemcpyAsync(out.node_base.p, pin, bytes, hipMemcpyHostToDevice, s));
+            TC_HIP(hipMemcpyAsync(edge_base.p, pin + (k + 1), bytes, hipMemcpyHostToDevice, s));
+        } else {
+            TC_HIP(hipMemcpyAsync(out.node_base.p, pk.node_base.data(), bytes, hipMemcpyHostToDevice, s));
+            TC_HIP(hipMemcpyAsync(edge_base.p, pk.edge_base.data(), bytes, hipMemcpyHostToDevice, s));
+        }
+    }
     DevBuf<uint32_t> err(tmp, 4);  // [0]: input errors, [1]: repeated entry
     fill_zero(err.p, 16, s);
 
