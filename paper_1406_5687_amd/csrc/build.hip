@@ -647,6 +647,80 @@ __global__ void k_orient_pairs(const int32_t *__restrict__ src, const int32_t *_
     }
 }
 
+// Oriented keys as k_orient_pairs, written in the tiles of the radix passes
+// that order them (kRadixTile keys per workgroup, same XCD mapping), with the
+// digit table of the first pass (key bits shift .. shift + bits) counted on
+// the way.  Inside a tile any thread may make any key: kOrientTileThreads
+// threads make kRadixTile / kOrientTileThreads keys each.
+constexpr int kOrientTileThreads = 512;
+constexpr int kOrientTileWaves = kOrientTileThreads / 64;
+__global__ __launch_bounds__(kOrientTileThreads) void k_orient_pairs_hist(const int32_t *__restrict__ src,
+                                                           const int32_t *__restrict__ dst, int64_t m, int gb,
+                                                           const int32_t *__restrict__ rank,
+                                                           uint64_t *__restrict__ okeys, int shift, int bits,
+                                                           int64_t tiles, uint32_t *__restrict__ hist) {
+    constexpr int kRounds = kRadixTile / kOrientTileThreads;
+    __shared__ uint32_t hw[kOrientTileWaves][256];  // one table per wave
+    for (int i = threadIdx.x; i < kOrientTileWaves * 256; i += kOrientTileThreads) (&hw[0][0])[i] = 0u;
+    __syncthreads();
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const int64_t t = xcd_tile(blockIdx.x, tiles);
+    const int64_t base = t * kRadixTile + (int64_t)wave * (64 * kRounds) + lane;
+    const bool full = m - t * kRadixTile >= kRadixTile;  // every lane holds a key
+    const uint32_t dmask = (1u << bits) - 1u;
+    // all endpoints are loaded, then all ranks gathered, before any key is made
+    int32_t u[kRounds], v[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t i = base + r * 64;
+        u[r] = i < m ? __builtin_nontemporal_load(&src[i]) : 0;
+        v[r] = i < m ? __builtin_nontemporal_load(&dst[i]) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t i = base + r * 64;
+        u[r] = i < m ? rank[u[r]] : 0;
+        v[r] = i < m ? rank[v[r]] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t i = base + r * 64;
+        const uint32_t ra = (uint32_t)u[r], rb = (uint32_t)v[r];
+        const uint64_t key = ((uint64_t)(ra < rb ? ra : rb) << gb) | (ra < rb ? rb : ra);
+        if (i < m) __builtin_nontemporal_store(key, &okeys[i]);
+        const uint32_t d = i < m ? (uint32_t)(key >> shift) & dmask : 256u;  // 256: past the end
+        // lanes holding the same digit (all of them when the first lane's
+        // digit is everyone's, else one ballot per digit bit); the first of
+        // them adds their number, so no counter gets two writes in a round
+        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+        uint64_t peers = ~0ull;
+        if (__ballot(d == d0) != ~0ull) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                if (b < bits) {
+                    const bool bit = (d >> b) & 1u;
+                    const uint64_t bal = __ballot(bit);
+                    peers &= bit ? bal : ~bal;
+                }
+            }
+            if (!full) {
+                const bool past = d >> 8;
+                const uint64_t bal = __ballot(past);
+                peers &= past ? bal : ~bal;
+            }
+        }
+        if (d < 256u && lane == __ffsll((unsigned long long)peers) - 1) hw[wave][d] += (uint32_t)popc64(peers);
+        wave_lds_sync();
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 256; i += kOrientTileThreads) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kOrientTileWaves; ++w) c += hw[w][i];
+        hist[(int64_t)i * tiles + t] = c;
+    }
+}
+
 // Step 5b: rows sorted ascending.  The pair sort above orders by s only, so
 // each row holds its entries in input order.  A wave takes 64 consecutive
 // rows: rows of up to 8 entries are sorted by their own lane with a sorting
@@ -1446,14 +1520,26 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
     fill_zero(rowlen.p, rowlen.bytes(), s);
     uint64_t *okeys = nullptr;
     if (M > 0) {
-        if (pairs)
-            k_orient_pairs<<<grid_for(M, 4 * kOrientUnroll), kThreads, 0, s>>>(src, dst, M, gb, rank.p, spare);
-        else
-            k_orient_keys<<<grid_for(M, 4 * kOrientUnroll), kThreads, 0, s>>>(ukeys, M, gb, rank.p, spare);
-        TC_LAUNCH_CHECK();
         // order by s >> kGroupBits, then place each group of rows (in key
         // order inside a row: rows are sorted below)
-        okeys = gb > kGroupBits ? radix_sort_u64(spare, ukeys, M, gb + kGroupBits, 2 * gb, tmp, s) : spare;
+        if (pairs && gb > kGroupBits) {
+            // the keys come out in the radix passes' tiles with the first
+            // pass's digit table, so that pass does not read them to count
+            const int64_t tiles = ceil_div(M, (int64_t)kRadixTile);
+            const int shift = gb + kGroupBits, bits = std::min(8, 2 * gb - shift);
+            DevBuf<uint32_t> h1(tmp, (size_t)tiles * 256);
+            k_orient_pairs_hist<<<(unsigned)tiles, kOrientTileThreads, 0, s>>>(src, dst, M, gb, rank.p, spare, shift,
+                                                                                bits, tiles, h1.p);
+            TC_LAUNCH_CHECK();
+            okeys = radix_sort_u64_hist(spare, ukeys, M, shift, 2 * gb, h1.p, tmp, s);
+        } else {
+            if (pairs)
+                k_orient_pairs<<<grid_for(M, 4 * kOrientUnroll), kThreads, 0, s>>>(src, dst, M, gb, rank.p, spare);
+            else
+                k_orient_keys<<<grid_for(M, 4 * kOrientUnroll), kThreads, 0, s>>>(ukeys, M, gb, rank.p, spare);
+            TC_LAUNCH_CHECK();
+            okeys = gb > kGroupBits ? radix_sort_u64(spare, ukeys, M, gb + kGroupBits, 2 * gb, tmp, s) : spare;
+        }
         const int64_t ngroups = ceil_div(N, (int64_t)kGroupRows);
         DevBuf<int64_t> gstart(tmp, (size_t)ngroups + 1);
         k_group_bounds<<<grid_for(ngroups + 1), kThreads, 0, s>>>(okeys, M, gb, ngroups, gstart.p);

@@ -20,6 +20,15 @@ uint32_t *radix_sort_u32(uint32_t *keys, uint32_t *tmp, int64_t n, int begin_bit
                          hipStream_t s);
 uint32_t *radix_sort_u32_from(const uint32_t *first, uint32_t *keys, uint32_t *tmp, int64_t n, int begin_bit,
                               int end_bit, Allocator &al, hipStream_t s);
+// Tiles of the radix passes: kRadixTile keys each, tile t taken by workgroup b
+// with xcd_tile(b, tiles) == t, keys t * kRadixTile + w * 1024 + r * 64 + lane
+// (w = wave of 4, r = round of 16).  A pass's digit table is digit-major:
+// hist[d * tiles + t] = keys of tile t whose digit is d.
+constexpr int kRadixTile = 4096;
+// The same as radix_sort_u64, with the first pass's digit table (256 * tiles
+// words) computed by the caller while it wrote the keys.
+uint64_t *radix_sort_u64_hist(uint64_t *keys, uint64_t *tmp, int64_t n, int begin_bit, int end_bit,
+                              const uint32_t *first_hist, Allocator &al, hipStream_t s);
 
 // build.hip -------------------------------------------------------------
 

@@ -17,6 +17,7 @@ constexpr int kSortWaves = 4;
 constexpr int kSortThreads = kSortWaves * 64;
 constexpr int kSortRounds = 16;                        // keys per lane
 constexpr int kSortTile = kSortThreads * kSortRounds;  // 4096 keys per block
+static_assert(kSortTile == kRadixTile && kSortWaves == 4 && kSortRounds == 16, "tile layout shared with callers");
 constexpr int kRadix = 256;
 
 // Key r of lane l in wave w sits at tile offset w * 64 * kSortRounds + r * 64 + l:
@@ -202,9 +203,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const K *__restr
 
 // With `first` given, the first pass reads it instead of keys (first is
 // never written; the result is in keys or tmp).
+// With first_hist given, the first pass takes that digit table instead of
+// counting one.
 template <class K>
 K *radix_sort_impl(K *keys, K *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al, hipStream_t s,
-                   const K *first = nullptr) {
+                   const K *first = nullptr, const uint32_t *first_hist = nullptr) {
     if (n <= 1 || end_bit <= begin_bit) {
         if (first && n > 0) TC_HIP(hipMemcpyAsync(keys, first, (size_t)n * sizeof(K), hipMemcpyDeviceToDevice, s));
         return keys;
@@ -221,9 +224,13 @@ K *radix_sort_impl(K *keys, K *tmp, int64_t n, int begin_bit, int end_bit, Alloc
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
         const int bits = std::min(8, end_bit - shift);
         K *outp = first && shift == begin_bit ? a : b;
-        k_radix_hist<K><<<(unsigned)nb, kSortThreads, 0, s>>>(in, n, shift, bits, nb, hist.p);
-        TC_LAUNCH_CHECK();
-        exclusive_scan(hist.p, base.p, nb * kRadix, false, al, s);
+        if (first_hist && shift == begin_bit) {
+            exclusive_scan(first_hist, base.p, nb * kRadix, false, al, s);
+        } else {
+            k_radix_hist<K><<<(unsigned)nb, kSortThreads, 0, s>>>(in, n, shift, bits, nb, hist.p);
+            TC_LAUNCH_CHECK();
+            exclusive_scan(hist.p, base.p, nb * kRadix, false, al, s);
+        }
         k_radix_scatter<K><<<(unsigned)nb, kSortThreads, 0, s>>>(in, outp, n, shift, bits, nb, base.p);
         TC_LAUNCH_CHECK();
         if (!(first && shift == begin_bit)) {
@@ -243,6 +250,11 @@ K *radix_sort_impl(K *keys, K *tmp, int64_t n, int begin_bit, int end_bit, Alloc
 uint64_t *radix_sort_u64(uint64_t *keys, uint64_t *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al,
                          hipStream_t s) {
     return radix_sort_impl<uint64_t>(keys, tmp, n, begin_bit, end_bit, al, s);
+}
+
+uint64_t *radix_sort_u64_hist(uint64_t *keys, uint64_t *tmp, int64_t n, int begin_bit, int end_bit,
+                              const uint32_t *first_hist, Allocator &al, hipStream_t s) {
+    return radix_sort_impl<uint64_t>(keys, tmp, n, begin_bit, end_bit, al, s, nullptr, first_hist);
 }
 
 uint32_t *radix_sort_u32(uint32_t *keys, uint32_t *tmp, int64_t n, int begin_bit, int end_bit, Allocator &al,
