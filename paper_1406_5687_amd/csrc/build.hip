@@ -10,8 +10,8 @@
 //   3. degree order        -- sort (g, d_x, v): position r in the sorted list is the
 //                             new label of x (Section III-A order, ties by id)
 //   4. orientation         -- edge {a, b} stored at the lower label s as (s, t);
-//                             stable radix passes order the keys by s >> 4, one
-//                             wave per 16 rows places them into the rows
+//                             stable radix passes order the keys by s >> 12,
+//                             chunks of each 4096-row group place them into the rows
 //   5. CSR                 -- col = t, off = exclusive scan of row lengths; each row
 //                             then sorted ascending on its own
 //   6. costs and tasks     -- f per node (Sections IV-B, IV-F, V-A), prefix sums,
@@ -347,15 +347,24 @@ __global__ __launch_bounds__(kHistThreads) void k_bucket_hist(const uint32_t *__
 
 // Step 4b: rows by group.  The oriented keys (s << gb) | t are sorted by
 // s >> kGroupBits (stable radix passes over the label bits above
-// kGroupBits); one wave per group of kGroupRows rows then counts the rows,
-// writes their lengths and offsets, and puts every key at its row's next
-// slot inside the group's part of col (rows are sorted on their own
-// afterwards).  Counts and slots live in the wave's LDS counters; lanes
-// holding the same row are found with one ballot per label bit, so every
-// counter is read and written by one lane per round (no LDS atomics).
-constexpr int kGroupBits = 4;
+// kGroupBits: one pass for up to 2^20 labels).  Each group's keys are cut
+// into chunks of at most kChunkKeys, one workgroup per chunk, so a group of
+// millions of keys (rows of a power-law graph's middle degrees) is shared
+// out like any other:
+//   k_chunk_count  counts the chunk's keys per row of its group in LDS;
+//   k_chunk_scan   (one workgroup per group) turns those counts into each
+//                  chunk's offset inside each row, and writes row lengths
+//                  and offsets;
+//   k_chunk_place  puts every key at its row's next slot (LDS cursors).
+// The order inside a row is whatever the slot atomics give: rows are sorted
+// on their own afterwards.  Among 64 keys two rarely share one of 4096 rows,
+// so the LDS atomics seldom conflict.
+constexpr int kGroupBits = 12;
 constexpr int kGroupRows = 1 << kGroupBits;
-constexpr int kGroupUnroll = 4;  // rounds of 64 keys loaded together
+constexpr int kChunkThreads = 1024;
+constexpr int kChunkUnroll = 8;  // keys per thread loaded together
+constexpr int64_t kChunkKeys = (int64_t)kChunkThreads * kChunkUnroll * 2;
+constexpr int kRowsPerThread = kGroupRows / kChunkThreads;
 
 __global__ void k_group_bounds(const uint64_t *__restrict__ keys, int64_t m, int shift, int64_t ngroups,
                                int64_t *__restrict__ gstart) {
@@ -373,88 +382,157 @@ __global__ void k_group_bounds(const uint64_t *__restrict__ keys, int64_t m, int
     }
 }
 
-// Lanes holding the same row (0 .. kGroupRows; kGroupRows = no key).
-__device__ __forceinline__ uint64_t same_row(uint32_t row) {
-    uint64_t peers = ~0ull;
-#pragma unroll
-    for (int b = 0; b <= kGroupBits; ++b) {
-        const bool bit = (row >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
-    }
-    return peers;
+// chunks of group g: cfirst[g] .. cfirst[g + 1] (cfirst = exclusive scan of this)
+__global__ void k_group_chunks(const int64_t *__restrict__ gstart, int64_t ngroups, int64_t *__restrict__ nchunk) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += (int64_t)gridDim.x * blockDim.x)
+        nchunk[g] = (gstart[g + 1] - gstart[g] + kChunkKeys - 1) / kChunkKeys;
 }
 
-__global__ __launch_bounds__(kThreads) void k_group_place(const uint64_t *__restrict__ keys, int shift,
-                                                          const int64_t *__restrict__ gstart, int64_t ngroups,
-                                                          int64_t N, int32_t *__restrict__ rowlen,
-                                                          int64_t *__restrict__ off, int32_t *__restrict__ col) {
-    __shared__ uint32_t ctr[kThreads / 64][kGroupRows];
-    const int lane = __lane_id();
-    uint32_t *c = ctr[threadIdx.x >> 6];
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+// Chunk c's group and key range (cfirst: chunk starts per group, ngroups + 1
+// entries; c < cfirst[ngroups]).
+__device__ __forceinline__ int64_t chunk_group(const int64_t *__restrict__ cfirst, int64_t ngroups, int64_t c) {
+    int64_t lo = 0, hi = ngroups;  // last g with cfirst[g] <= c
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cfirst[mid] <= c)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kChunkThreads) void k_chunk_count(const uint64_t *__restrict__ keys, int shift,
+                                                               const int64_t *__restrict__ gstart,
+                                                               const int64_t *__restrict__ cfirst, int64_t ngroups,
+                                                               uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t lc[kGroupRows];
+    const int64_t nchunks = cfirst[ngroups];
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t g = chunk_group(cfirst, ngroups, c);
+        const int64_t b = gstart[g] + (c - cfirst[g]) * kChunkKeys;
+        const int64_t e = min(gstart[g + 1], b + kChunkKeys);
+        for (int r = threadIdx.x; r < kGroupRows; r += kChunkThreads) lc[r] = 0u;
+        __syncthreads();
+        for (int64_t p0 = b + threadIdx.x; p0 < e; p0 += (int64_t)kChunkThreads * kChunkUnroll) {
+            uint64_t k[kChunkUnroll];
+#pragma unroll
+            for (int u = 0; u < kChunkUnroll; ++u) {
+                const int64_t p = p0 + (int64_t)u * kChunkThreads;
+                k[u] = p < e ? keys[p] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kChunkUnroll; ++u)
+                if (p0 + (int64_t)u * kChunkThreads < e) atomicAdd(&lc[(uint32_t)(k[u] >> shift) & (kGroupRows - 1)], 1u);
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < kGroupRows; r += kChunkThreads) cnt[c * kGroupRows + r] = lc[r];
+        __syncthreads();
+    }
+}
+
+// One workgroup per group: cnt[c][r] becomes the number of keys of row r in
+// the group's chunks before c; row lengths and offsets of the group's rows.
+__global__ __launch_bounds__(kChunkThreads) void k_chunk_scan(const int64_t *__restrict__ gstart,
+                                                              const int64_t *__restrict__ cfirst, int64_t ngroups,
+                                                              int64_t N, uint32_t *__restrict__ cnt,
+                                                              int32_t *__restrict__ rowlen,
+                                                              int64_t *__restrict__ off) {
+    __shared__ uint32_t wtot[kChunkThreads / 64];
+    const int tid = threadIdx.x, lane = __lane_id(), wave = threadIdx.x >> 6;
+    for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const int64_t c0 = cfirst[g], c1 = cfirst[g + 1];
+        // rows tid + j * kChunkThreads (coalesced over the chunk tables)
+        uint32_t len[kRowsPerThread];
+#pragma unroll
+        for (int j = 0; j < kRowsPerThread; ++j) len[j] = 0u;
+        // four chunks' counts are loaded before any is rewritten
+        int64_t c = c0;
+        for (; c + 4 <= c1; c += 4) {
+            uint32_t v[4][kRowsPerThread];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < kRowsPerThread; ++j) v[i][j] = cnt[(c + i) * kGroupRows + tid + j * kChunkThreads];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < kRowsPerThread; ++j) {
+                    cnt[(c + i) * kGroupRows + tid + j * kChunkThreads] = len[j];
+                    len[j] += v[i][j];
+                }
+        }
+        for (; c < c1; ++c) {
+#pragma unroll
+            for (int j = 0; j < kRowsPerThread; ++j) {
+                uint32_t *q = &cnt[c * kGroupRows + tid + j * kChunkThreads];
+                const uint32_t v = *q;
+                *q = len[j];
+                len[j] += v;
+            }
+        }
+        // row starts: exclusive scan over the group's rows in row order
+        // (row r = tid + j * kChunkThreads: scan j-major, threads inside)
+        const int64_t x0 = g << kGroupBits, gs = gstart[g];
+        uint32_t carry = 0;
+#pragma unroll
+        for (int j = 0; j < kRowsPerThread; ++j) {
+            const uint32_t inc = wave_inclusive_sum(len[j]);
+            if (lane == 63) wtot[wave] = inc;
+            __syncthreads();
+            uint32_t before = 0, all = 0;
+            for (int w = 0; w < kChunkThreads / 64; ++w) {
+                const uint32_t t = wtot[w];
+                before += w < wave ? t : 0u;
+                all += t;
+            }
+            const uint32_t start = carry + before + inc - len[j];
+            const int64_t x = x0 + tid + j * kChunkThreads;
+            if (x < N) {
+                rowlen[x] = (int32_t)len[j];
+                off[x] = gs + start;
+            }
+            carry += all;
+            __syncthreads();
+        }
+        if (g == ngroups - 1 && tid == 0) off[N] = gstart[ngroups];
+    }
+}
+
+__global__ __launch_bounds__(kChunkThreads) void k_chunk_place(const uint64_t *__restrict__ keys, int shift,
+                                                               const int64_t *__restrict__ gstart,
+                                                               const int64_t *__restrict__ cfirst, int64_t ngroups,
+                                                               int64_t N, const uint32_t *__restrict__ cnt,
+                                                               const int64_t *__restrict__ off,
+                                                               int32_t *__restrict__ col) {
+    __shared__ uint32_t lc[kGroupRows];
     const uint64_t mask = (1ull << shift) - 1;
-    constexpr int64_t kStep = 64 * kGroupUnroll;
-    for (int64_t g = wave; g < ngroups; g += nwaves) {
-        const int64_t gs = gstart[g], ge = gstart[g + 1];
+    const int64_t nchunks = cfirst[ngroups];
+    for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const int64_t g = chunk_group(cfirst, ngroups, c);
+        const int64_t gs = gstart[g];
+        const int64_t b = gs + (c - cfirst[g]) * kChunkKeys;
+        const int64_t e = min(gstart[g + 1], b + kChunkKeys);
         const int64_t x0 = g << kGroupBits;
-        const int nrows = (int)min((int64_t)kGroupRows, N - x0);
-        if (lane < kGroupRows) c[lane] = 0;
-        wave_lds_sync();
-        // 1. row counts: per round, the first lane of each row adds the
-        // number of lanes holding that row (no two lanes write one counter)
-        for (int64_t b0 = gs; b0 < ge; b0 += kStep) {
-            uint64_t k[kGroupUnroll];
+        for (int r = threadIdx.x; r < kGroupRows; r += kChunkThreads)
+            lc[r] = x0 + r < N ? (uint32_t)(off[x0 + r] - gs) + cnt[c * kGroupRows + r] : 0u;
+        __syncthreads();
+        for (int64_t p0 = b + threadIdx.x; p0 < e; p0 += (int64_t)kChunkThreads * kChunkUnroll) {
+            uint64_t k[kChunkUnroll];
 #pragma unroll
-            for (int u = 0; u < kGroupUnroll; ++u) {
-                const int64_t p = b0 + u * 64 + lane;
-                k[u] = p < ge ? keys[p] : 0;
+            for (int u = 0; u < kChunkUnroll; ++u) {
+                const int64_t p = p0 + (int64_t)u * kChunkThreads;
+                k[u] = p < e ? keys[p] : 0;
             }
 #pragma unroll
-            for (int u = 0; u < kGroupUnroll; ++u) {
-                if (b0 + u * 64 >= ge) break;
-                const bool valid = b0 + u * 64 + lane < ge;
-                const uint32_t row = valid ? (uint32_t)(k[u] >> shift) & (kGroupRows - 1) : (uint32_t)kGroupRows;
-                const uint64_t peers = same_row(row);
-                if (valid && lane == __ffsll((unsigned long long)peers) - 1) c[row] += (uint32_t)popc64(peers);
-                wave_lds_sync();
+            for (int u = 0; u < kChunkUnroll; ++u) {
+                if (p0 + (int64_t)u * kChunkThreads < e) {
+                    const uint32_t slot = atomicAdd(&lc[(uint32_t)(k[u] >> shift) & (kGroupRows - 1)], 1u);
+                    col[gs + slot] = (int32_t)(k[u] & mask);
+                }
             }
         }
-        // 2. row starts; lengths and offsets
-        const uint32_t v = lane < kGroupRows ? c[lane] : 0u;
-        const uint32_t start = wave_inclusive_sum(v) - v;
-        if (lane < nrows) {
-            rowlen[x0 + lane] = (int32_t)v;
-            off[x0 + lane] = gs + start;
-        }
-        if (g == ngroups - 1 && lane == 0) off[N] = ge;
-        wave_lds_sync();
-        if (lane < kGroupRows) c[lane] = start;
-        wave_lds_sync();
-        // 3. every key to its row's next slot: the row's cursor plus the
-        // number of lower lanes holding the same row
-        for (int64_t b0 = gs; b0 < ge; b0 += kStep) {
-            uint64_t k[kGroupUnroll];
-#pragma unroll
-            for (int u = 0; u < kGroupUnroll; ++u) {
-                const int64_t p = b0 + u * 64 + lane;
-                k[u] = p < ge ? keys[p] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < kGroupUnroll; ++u) {
-                if (b0 + u * 64 >= ge) break;
-                const bool valid = b0 + u * 64 + lane < ge;
-                const uint32_t row = valid ? (uint32_t)(k[u] >> shift) & (kGroupRows - 1) : (uint32_t)kGroupRows;
-                const uint64_t peers = same_row(row);
-                const uint32_t base = valid ? c[row] : 0u;
-                wave_lds_sync();
-                if (valid && lane == __ffsll((unsigned long long)peers) - 1) c[row] = base + (uint32_t)popc64(peers);
-                wave_lds_sync();
-                if (valid) col[gs + base + (uint32_t)popc64(peers & lanemask_lt())] = (int32_t)(k[u] & mask);
-            }
-        }
-        wave_lds_sync();
+        __syncthreads();
     }
 }
 
@@ -1544,9 +1622,23 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
         DevBuf<int64_t> gstart(tmp, (size_t)ngroups + 1);
         k_group_bounds<<<grid_for(ngroups + 1), kThreads, 0, s>>>(okeys, M, gb, ngroups, gstart.p);
         TC_LAUNCH_CHECK();
-        const int64_t gw = std::min<int64_t>(ngroups, (int64_t)device_cu_count() * 64);  // waves
-        k_group_place<<<(unsigned)ceil_div(gw * 64, kThreads), kThreads, 0, s>>>(okeys, gb, gstart.p, ngroups, N,
-                                                                                  rowlen.p, out.off.p, out.col.p);
+        // chunks of at most kChunkKeys keys per group; their number is only
+        // known on the device, so the kernels loop over an upper bound
+        DevBuf<int64_t> cfirst(tmp, (size_t)ngroups + 1);
+        k_group_chunks<<<grid_for(ngroups), kThreads, 0, s>>>(gstart.p, ngroups, cfirst.p);
+        TC_LAUNCH_CHECK();
+        exclusive_scan(cfirst.p, cfirst.p, ngroups, true, tmp, s);  // in place: tile-local staging
+        const int64_t max_chunks = ceil_div(M, kChunkKeys) + ngroups;
+        DevBuf<uint32_t> cnt(tmp, (size_t)max_chunks * kGroupRows);
+        const int64_t wg = (int64_t)device_cu_count() * 2;  // resident 1024-thread workgroups
+        k_chunk_count<<<(unsigned)std::min<int64_t>(max_chunks, wg), kChunkThreads, 0, s>>>(okeys, gb, gstart.p,
+                                                                                           cfirst.p, ngroups, cnt.p);
+        TC_LAUNCH_CHECK();
+        k_chunk_scan<<<(unsigned)std::min<int64_t>(ngroups, wg), kChunkThreads, 0, s>>>(
+            gstart.p, cfirst.p, ngroups, N, cnt.p, rowlen.p, out.off.p);
+        TC_LAUNCH_CHECK();
+        k_chunk_place<<<(unsigned)std::min<int64_t>(max_chunks, wg), kChunkThreads, 0, s>>>(
+            okeys, gb, gstart.p, cfirst.p, ngroups, N, cnt.p, out.off.p, out.col.p);
         TC_LAUNCH_CHECK();
     } else {
         exclusive_scan(rowlen.p, out.off.p, N, true, tmp, s);
