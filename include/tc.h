@@ -153,6 +153,27 @@ tc_status tc_count_per_node(tc_graph *g, const tc_options *opt, int64_t *per_nod
 tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, int64_t *totals,
                          int64_t *const *per_node);
 
+/* A count of ng handles captured once as a HIP graph and replayed as one graph
+ * launch (Fig. 11: the worker loop of one count, with its queue resets and
+ * reductions, as a unit the host launches).  tc_count_capture records on a
+ * private stream the work tc_count_batch(gs, ng, opt, totals, per_node) would
+ * enqueue: clearing its scratch, the persistent count kernels, the per-node
+ * scatter and the copy of the totals.  The scratch is allocated once, through
+ * opt's allocator, before the capture.  Outputs must be device pointers
+ * (outputs_on_device = 1); every replay rewrites them.  The handles and the
+ * outputs must outlive the captured count; a handle rescheduled or freed
+ * after the capture must not be replayed.  Errors as tc_count_batch, and
+ * TC_ERR_DEVICE if the runtime refuses the capture. */
+typedef struct tc_count_graph tc_count_graph;
+tc_status tc_count_capture(tc_graph *const *gs, int32_t ng, const tc_options *opt, int64_t *totals,
+                           int64_t *const *per_node, tc_count_graph **out);
+/* Launches the captured count on opt->stream (NULL opt: the null stream);
+ * returns after enqueuing it. */
+tc_status tc_count_replay(tc_count_graph *c, const tc_options *opt);
+/* Waits for the last replay, then releases the captured count and its
+ * scratch.  NULL is a no-op. */
+void tc_count_graph_free(tc_count_graph *c);
+
 /* Clustering coefficients from the per-node counts (Section I names them as
  * applications; textbook definitions): coeff[v] = T_v / C(d_v, 2), 0 when
  * d_v < 2, in the caller's labels, packed graph after graph (sum of n_i

@@ -1,47 +1,56 @@
-"""Replays of a handle's count as one captured HIP graph.
+"""Replays of a count as one captured HIP graph (tc_count_capture /
+tc_count_replay of the C ABI).
 
-The count path is stream ordered and, once its per-handle scratch exists,
-allocates nothing and issues no memset: reset kernels, the persistent
-counting kernels, the per-node scatter and a device-to-device copy of the
-totals.  Capturing it once (torch.cuda.graph drives hipStreamBeginCapture on
-the library's stream) turns every later count of the same handle into a
-single graph launch.
+The library records the count on a stream of its own: reset of its scratch,
+the persistent counting kernels, the per-node scatter and the copy of the
+totals.  Each replay is one graph launch on the caller's stream.  torch only
+supplies the output tensors and the stream.
 """
 from __future__ import annotations
+
+import ctypes
+from typing import Sequence
 
 from . import tc
 
 
 class CapturedCount:
-    """Captures graph.count_total / count_per_node into device outputs."""
+    """A captured count of one handle (or of several, as one batch) into device
+    outputs: ``totals`` (int64[sum of k]) and, with per_node, ``per_node_out``
+    (int64[n] of the first handle) or ``per_node_outs`` (one per handle)."""
 
-    def __init__(self, graph: "tc.Graph", per_node: bool = False):
+    def __init__(self, graph, per_node: bool = False):
         import torch
 
-        self.graph = graph
+        graphs: Sequence = list(graph) if isinstance(graph, (list, tuple)) else [graph]
+        self.graphs = graphs
         self.per_node = per_node
-        self.totals = torch.zeros(max(graph.k, 1), dtype=torch.int64, device="cuda")
-        self.per_node_out = (torch.zeros(max(graph.n_total, 1), dtype=torch.int64, device="cuda")
-                             if per_node else None)
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            self._run()  # creates the handle's scratch outside the capture
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        self.cuda_graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.cuda_graph):
-            self._run()
-        torch.cuda.synchronize()
+        self.totals = torch.zeros(max(sum(g.k for g in graphs), 1), dtype=torch.int64, device="cuda")
+        self.per_node_outs = ([torch.zeros(max(g.n_total, 1), dtype=torch.int64, device="cuda") for g in graphs]
+                              if per_node else None)
+        self.per_node_out = self.per_node_outs[0] if per_node else None
+        hs, pn = tc._device_batch_args(graphs, self.totals, self.per_node_outs)
+        o = graphs[0]._opts(outputs_on_device=True)
+        h = ctypes.c_void_p(0)
+        tc._raise(tc.load().tc_count_capture(hs, len(graphs), ctypes.byref(o), ctypes.c_void_p(self.totals.data_ptr()),
+                                             pn, ctypes.byref(h)))
+        self._h = h
 
-    def _run(self):
-        if self.per_node:
-            self.graph.count_per_node(out=self.per_node_out, totals=self.totals)
-        else:
-            self.graph.count_total(out=self.totals)
-
-    def replay(self):
-        """Launches the captured count on the current stream; outputs are
-        self.totals (and self.per_node_out) once the stream reaches them."""
-        self.cuda_graph.replay()
+    def replay(self, stream=None):
+        """Launches the captured count on `stream` (default: the current torch
+        stream); outputs are self.totals (and self.per_node_out) once the
+        stream reaches them."""
+        o = tc.make_options(stream=stream, torch_allocator=False)
+        tc._raise(tc.load().tc_count_replay(self._h, ctypes.byref(o)))
         return self.totals, self.per_node_out
+
+    def free(self):
+        if self._h and self._h.value:
+            tc.load().tc_count_graph_free(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -38,6 +38,20 @@ struct tc_graph {
     }
 };
 
+// A count captured as a HIP graph (tc_count_capture): its own scratch and the
+// instantiated graph; the handles it counts are referenced, not owned.
+struct tc_count_graph {
+    tc::Allocator al;
+    tc::DevBuf<uint8_t> scratch;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last = nullptr;  // stream of the last replay
+    ~tc_count_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -136,6 +150,131 @@ void ensure_scratch(tc_graph *g, bool per_node, hipStream_t s) {
 void copy_out(void *dst, const void *src, size_t bytes, bool dst_on_device, hipStream_t s) {
     if (bytes == 0) return;
     TC_HIP(hipMemcpyAsync(dst, src, bytes, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+}
+
+tc_status check_batch_args(tc_graph *const *gs, int32_t ng, const int64_t *totals) {
+    if (!gs || ng < 1 || !totals) return fail(TC_ERR_INVALID_ARG, "graphs, ng >= 1 and totals are required");
+    for (int32_t i = 0; i < ng; ++i) {
+        if (!gs[i]) return fail(TC_ERR_INVALID_ARG, "NULL graph in batch");
+        if (gs[i]->part) return fail(TC_ERR_INVALID_ARG, "a partitioned handle cannot join a batch");
+    }
+    return TC_OK;
+}
+
+// Scratch of one batch count, at byte offsets from its base: the queue heads,
+// the totals of every graph, the per-node accumulators (degree-order labels,
+// handle after handle) and the count descriptors of the handles.
+struct BatchLayout {
+    std::vector<int64_t> kbase, nbase;  // ng+1: first total / accumulator of each handle
+    bool want_tv = false;
+    size_t tot_off = 0, tv_off = 0, zero_bytes = 0, desc_off = 0, bytes = 0;
+};
+
+BatchLayout batch_layout(tc_graph *const *gs, int32_t ng, int64_t *const *per_node) {
+    BatchLayout b;
+    b.kbase.assign((size_t)ng + 1, 0);
+    b.nbase.assign((size_t)ng + 1, 0);
+    if (per_node)
+        for (int32_t i = 0; i < ng; ++i) b.want_tv = b.want_tv || (per_node[i] != nullptr && gs[i]->pk.N > 0);
+    for (int32_t i = 0; i < ng; ++i) {
+        b.kbase[i + 1] = b.kbase[i] + gs[i]->pk.k;
+        b.nbase[i + 1] = b.nbase[i] + (b.want_tv ? gs[i]->pk.N : 0);
+    }
+    b.tot_off = 256;
+    b.tv_off = b.tot_off + (size_t)b.kbase[ng] * 8;
+    b.zero_bytes = b.tv_off + (size_t)b.nbase[ng] * 8;
+    b.desc_off = (b.zero_bytes + 255) & ~(size_t)255;
+    b.bytes = b.desc_off + (size_t)ng * sizeof(tc::CountDesc);
+    return b;
+}
+
+// Descriptors stored by kernels whose arguments carry them: no host buffer
+// has to outlive the call, so the upload can be captured in a graph.
+constexpr int kDescPack = 16;
+struct DescPack {
+    tc::CountDesc d[kDescPack];
+};
+static_assert(sizeof(DescPack) <= 3072, "descriptor pack must fit the kernel argument space");
+
+__global__ void k_store_descs(DescPack p, int n, tc::CountDesc *out) {
+    const int i = (int)threadIdx.x;
+    if (i < n) out[i] = p.d[i];
+}
+
+// Zeroes the heads, totals and accumulators in `base`, stores the handles'
+// descriptors and launches the persistent count over all of their tasks.
+void launch_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, const BatchLayout &lay, uint8_t *base,
+                  bool descs_by_kernel, hipStream_t s) {
+    tc::fill_zero(base, lay.zero_bytes, s);
+    uint32_t *heads = (uint32_t *)base;
+    int64_t *tot = (int64_t *)(base + lay.tot_off);
+    int64_t *tv = (int64_t *)(base + lay.tv_off);
+    tc::CountDesc *ddesc = (tc::CountDesc *)(base + lay.desc_off);
+    std::vector<tc::CountDesc> hd((size_t)ng);
+    int64_t task_base = 0, med_base = 0, large_base = 0;
+    int32_t workers = 0, lds_max = tc::max_lds_list();
+    for (int32_t i = 0; i < ng; ++i) {
+        const tc_graph *g = gs[i];
+        tc::CountDesc &d = hd[i];
+        d = tc::CountDesc{};
+        d.off = g->o.off.p;
+        d.col = g->o.col.p;
+        d.bnd = g->o.bnd.p;
+        d.start = g->o.start.p;
+        d.gid = g->pk.k > 1 ? g->o.gid.p : nullptr;
+        d.node_base = g->o.node_base.p;
+        d.big = g->o.big.p;
+        d.m = g->o.M;
+        d.totals = tot + lay.kbase[i];
+        d.tv = lay.want_tv ? tv + lay.nbase[i] : nullptr;
+        d.nmed = g->o.nmed;
+        d.nbig = g->o.nbig;
+        d.task_base = task_base;
+        d.med_base = med_base;
+        d.large_base = large_base;
+        d.k = g->pk.k;
+        d.small_max = g->small_max;
+        task_base += g->o.tasks;
+        med_base += g->o.nmed;
+        large_base += g->o.nbig - g->o.nmed;
+        workers = std::max(workers, g->workers);
+        lds_max = std::min(lds_max, g->lds_max);
+    }
+    if (descs_by_kernel) {
+        for (int32_t b = 0; b < ng; b += kDescPack) {
+            DescPack p;
+            const int c = std::min<int32_t>(kDescPack, ng - b);
+            std::memcpy(p.d, hd.data() + b, (size_t)c * sizeof(tc::CountDesc));
+            k_store_descs<<<1, 64, 0, s>>>(p, c, ddesc + b);
+            TC_LAUNCH_CHECK();
+        }
+    } else {
+        TC_HIP(hipMemcpyAsync(ddesc, hd.data(), ng * sizeof(tc::CountDesc), hipMemcpyHostToDevice, s));
+    }
+    tc::CountLaunch L{};
+    L.descs = ddesc;
+    L.ndesc = ng;
+    L.total_tasks = task_base;
+    L.total_med = med_base;
+    L.total_large = large_base;
+    L.max_m = 0;
+    for (int32_t i = 0; i < ng; ++i) L.max_m = std::max<int64_t>(L.max_m, gs[i]->max_graph_m);
+    L.heads = heads;
+    L.workers = opt && opt->workers > 0 ? opt->workers : workers;
+    L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : lds_max;
+    L.per_node = lay.want_tv;
+    tc::count_launch(L, s);
+}
+
+// Device outputs of a batch count: per-node counts scattered to caller
+// labels, totals copied out.
+void write_device_outputs(tc_graph *const *gs, int32_t ng, const BatchLayout &lay, const uint8_t *base,
+                          int64_t *totals, int64_t *const *per_node, hipStream_t s) {
+    const int64_t *tv = (const int64_t *)(base + lay.tv_off);
+    for (int32_t i = 0; i < ng && per_node; ++i)
+        if (per_node[i] && gs[i]->pk.N > 0)
+            tc::scatter_per_node(tv + lay.nbase[i], gs[i]->o.perm.p, gs[i]->pk.N, per_node[i], s);
+    copy_out(totals, base + lay.tot_off, (size_t)lay.kbase[ng] * 8, true, s);
 }
 
 }  // namespace
@@ -411,93 +550,96 @@ tc_status tc_count_per_node(tc_graph *g, const tc_options *opt, int64_t *per_nod
 
 tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, int64_t *totals,
                          int64_t *const *per_node) {
-    if (!gs || ng < 1 || !totals) return fail(TC_ERR_INVALID_ARG, "graphs, ng >= 1 and totals are required");
-    for (int32_t i = 0; i < ng; ++i) {
-        if (!gs[i]) return fail(TC_ERR_INVALID_ARG, "NULL graph in batch");
-        if (gs[i]->part) return fail(TC_ERR_INVALID_ARG, "a partitioned handle cannot join a batch");
-    }
+    const tc_status bad = check_batch_args(gs, ng, totals);
+    if (bad != TC_OK) return bad;
     return guarded([&] {
         check_options(opt);
         const bool on_dev = opt && opt->outputs_on_device;
         hipStream_t s = opt ? (hipStream_t)opt->stream : nullptr;
         tc::Allocator al = make_allocator(opt);
         al.budget = 0;
-        bool want_tv = false;
-        if (per_node)
-            for (int32_t i = 0; i < ng; ++i) want_tv = want_tv || (per_node[i] != nullptr && gs[i]->pk.N > 0);
-        std::vector<int64_t> kbase(ng + 1, 0), nbase(ng + 1, 0);
-        for (int32_t i = 0; i < ng; ++i) {
-            kbase[i + 1] = kbase[i] + gs[i]->pk.k;
-            nbase[i + 1] = nbase[i] + (want_tv ? gs[i]->pk.N : 0);
-        }
-        // one scratch block: heads | totals | per-node accumulators
-        const size_t head_words = 4;
-        const size_t bytes = head_words * 4 + (size_t)kbase[ng] * 8 + (size_t)nbase[ng] * 8;
-        tc::DevBuf<uint8_t> scratch(al, bytes);
-        tc::fill_zero(scratch.p, bytes, s);
-        uint32_t *heads = (uint32_t *)scratch.p;
-        int64_t *tot = (int64_t *)(scratch.p + head_words * 4);
-        int64_t *tv = tot + kbase[ng];
-        std::vector<tc::CountDesc> hd((size_t)ng);
-        int64_t task_base = 0, med_base = 0, large_base = 0;
-        int32_t workers = 0, lds_max = tc::max_lds_list();
-        for (int32_t i = 0; i < ng; ++i) {
-            const tc_graph *g = gs[i];
-            tc::CountDesc &d = hd[i];
-            d.off = g->o.off.p;
-            d.col = g->o.col.p;
-            d.bnd = g->o.bnd.p;
-            d.start = g->o.start.p;
-            d.gid = g->pk.k > 1 ? g->o.gid.p : nullptr;
-            d.node_base = g->o.node_base.p;
-            d.big = g->o.big.p;
-            d.m = g->o.M;
-            d.totals = tot + kbase[i];
-            d.tv = want_tv ? tv + nbase[i] : nullptr;
-            d.nmed = g->o.nmed;
-            d.nbig = g->o.nbig;
-            d.task_base = task_base;
-            d.med_base = med_base;
-            d.large_base = large_base;
-            d.k = g->pk.k;
-            d.small_max = g->small_max;
-            task_base += g->o.tasks;
-            med_base += g->o.nmed;
-            large_base += g->o.nbig - g->o.nmed;
-            workers = std::max(workers, g->workers);
-            lds_max = std::min(lds_max, g->lds_max);
-        }
-        tc::DevBuf<tc::CountDesc> ddesc(al, (size_t)ng);
-        TC_HIP(hipMemcpyAsync(ddesc.p, hd.data(), ng * sizeof(tc::CountDesc), hipMemcpyHostToDevice, s));
-        tc::CountLaunch L{};
-        L.descs = ddesc.p;
-        L.ndesc = ng;
-        L.total_tasks = task_base;
-        L.total_med = med_base;
-        L.total_large = large_base;
-        L.max_m = 0;
-        for (int32_t i = 0; i < ng; ++i) L.max_m = std::max<int64_t>(L.max_m, gs[i]->max_graph_m);
-        L.heads = heads;
-        L.workers = opt && opt->workers > 0 ? opt->workers : workers;
-        L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : lds_max;
-        L.per_node = want_tv;
-        tc::count_launch(L, s);
+        const BatchLayout lay = batch_layout(gs, ng, per_node);
+        tc::DevBuf<uint8_t> buf(al, lay.bytes);
+        launch_batch(gs, ng, opt, lay, buf.p, false, s);
+        const int64_t *tot = (const int64_t *)(buf.p + lay.tot_off);
+        const int64_t *tv = (const int64_t *)(buf.p + lay.tv_off);
         for (int32_t i = 0; i < ng && per_node; ++i) {
             if (!per_node[i] || gs[i]->pk.N == 0) continue;
             const int64_t n = gs[i]->pk.N;
             if (on_dev) {
-                tc::scatter_per_node(tv + nbase[i], gs[i]->o.perm.p, n, per_node[i], s);
+                tc::scatter_per_node(tv + lay.nbase[i], gs[i]->o.perm.p, n, per_node[i], s);
             } else {
                 tc::DevBuf<int64_t> stage(al, (size_t)n);
-                tc::scatter_per_node(tv + nbase[i], gs[i]->o.perm.p, n, stage.p, s);
+                tc::scatter_per_node(tv + lay.nbase[i], gs[i]->o.perm.p, n, stage.p, s);
                 copy_out(per_node[i], stage.p, (size_t)n * 8, false, s);
                 TC_HIP(hipStreamSynchronize(s));
             }
         }
-        copy_out(totals, tot, (size_t)kbase[ng] * 8, on_dev, s);
+        copy_out(totals, tot, (size_t)lay.kbase[ng] * 8, on_dev, s);
         if (!on_dev) TC_HIP(hipStreamSynchronize(s));
         // device descriptors and scratch are released in stream order here
     });
+}
+
+tc_status tc_count_capture(tc_graph *const *gs, int32_t ng, const tc_options *opt, int64_t *totals,
+                           int64_t *const *per_node, tc_count_graph **out) {
+    const tc_status bad = check_batch_args(gs, ng, totals);
+    if (bad != TC_OK) return bad;
+    if (!out) return fail(TC_ERR_INVALID_ARG, "out must be non-NULL");
+    if (!opt || !opt->outputs_on_device)
+        return fail(TC_ERR_INVALID_ARG, "a captured count writes device outputs only (outputs_on_device = 1)");
+    std::unique_ptr<tc_count_graph> c(new (std::nothrow) tc_count_graph());
+    if (!c) return fail(TC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    const tc_status st = guarded([&] {
+        check_options(opt);
+        hipStream_t s = (hipStream_t)opt->stream;
+        c->al = make_allocator(opt);
+        c->al.budget = 0;
+        c->last = s;
+        const BatchLayout lay = batch_layout(gs, ng, per_node);
+        c->scratch = tc::DevBuf<uint8_t>(c->al, lay.bytes);
+        // the scratch must exist before any replay, on whatever stream
+        TC_HIP(hipStreamSynchronize(s));
+        hipStream_t cs = nullptr;
+        TC_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        struct StreamGuard {
+            hipStream_t s;
+            ~StreamGuard() { (void)hipStreamDestroy(s); }
+        } guard{cs};
+        TC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            launch_batch(gs, ng, opt, lay, c->scratch.p, true, cs);
+            write_device_outputs(gs, ng, lay, c->scratch.p, totals, per_node, cs);
+        } catch (...) {
+            hipGraph_t partial = nullptr;
+            (void)hipStreamEndCapture(cs, &partial);
+            if (partial) (void)hipGraphDestroy(partial);
+            (void)hipGetLastError();
+            throw;
+        }
+        TC_HIP(hipStreamEndCapture(cs, &c->graph));
+        TC_HIP(hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+    });
+    if (st != TC_OK) return st;
+    *out = c.release();
+    return TC_OK;
+}
+
+tc_status tc_count_replay(tc_count_graph *c, const tc_options *opt) {
+    if (!c || !c->exec) return fail(TC_ERR_INVALID_ARG, "captured count must be non-NULL");
+    return guarded([&] {
+        hipStream_t s = opt ? (hipStream_t)opt->stream : nullptr;
+        TC_HIP(hipGraphLaunch(c->exec, s));
+        c->last = s;
+        c->al.stream = s;
+    });
+}
+
+void tc_count_graph_free(tc_count_graph *c) {
+    if (!c) return;
+    // the last replay may still read the scratch
+    if (c->exec) (void)hipStreamSynchronize(c->last);
+    delete c;
 }
 
 tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info) {
@@ -634,7 +776,11 @@ tc_status tc_worker_times(const tc_graph *g, const tc_options *opt, int64_t *tim
 
 void tc_graph_free(tc_graph *g) {
     if (!g) return;
-    delete g;  // buffers are returned in order on the last stream the handle used
+    // Without callbacks the buffers go back in order on the last stream the
+    // handle used.  A caller's allocator may hand them to another stream at
+    // once, so wait for the handle's work first.
+    if (g->al.fn_free) (void)hipStreamSynchronize(g->al.stream);
+    delete g;
 }
 
 }  // extern "C"

@@ -23,7 +23,8 @@ COST_ONE, COST_DEGREE, COST_PRIOR, COST_NEW = range(4)
 EXPORTED = [
     "tc_options_default", "tc_build_oriented", "tc_count_total", "tc_count_per_node", "tc_count_batch",
     "tc_graph_info", "tc_export_csr", "tc_export_schedule", "tc_graph_free", "tc_status_str", "tc_last_error",
-    "tc_graph_reschedule", "tc_worker_times", "tc_clustering",
+    "tc_graph_reschedule", "tc_worker_times", "tc_clustering", "tc_count_capture", "tc_count_replay",
+    "tc_count_graph_free",
 ]
 
 
@@ -120,6 +121,11 @@ def load(path: str = LIB_PATH):
     lib.tc_count_per_node.argtypes = [P, ctypes.POINTER(Options), P, P]
     lib.tc_count_batch.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(Options), P,
                                    ctypes.POINTER(P)]
+    lib.tc_count_capture.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(Options), P,
+                                     ctypes.POINTER(P), ctypes.POINTER(P)]
+    lib.tc_count_replay.argtypes = [P, ctypes.POINTER(Options)]
+    lib.tc_count_graph_free.argtypes = [P]
+    lib.tc_count_graph_free.restype = None
     lib.tc_graph_info.argtypes = [P, ctypes.POINTER(GraphInfo)]
     lib.tc_graph_reschedule.argtypes = [P, ctypes.POINTER(Options)]
     lib.tc_export_csr.argtypes = [P, ctypes.POINTER(Options), P, P, P]
@@ -136,7 +142,7 @@ def load(path: str = LIB_PATH):
     lib.tc_last_error.argtypes = []
     lib.tc_last_error.restype = ctypes.c_char_p
     for name in ("tc_build_oriented", "tc_count_total", "tc_count_per_node", "tc_count_batch", "tc_graph_info",
-                 "tc_export_csr", "tc_export_schedule", "tc_graph_reschedule"):
+                 "tc_export_csr", "tc_export_schedule", "tc_graph_reschedule", "tc_count_capture", "tc_count_replay"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -472,6 +478,22 @@ def count_batch(graphs: Sequence[Graph], per_node: bool = False, **over):
     if per_node:
         outs = [a[: g.n_total] for a, g in zip(outs, graphs)]
     return res_tot, outs
+
+
+def _device_batch_args(graphs, totals, per_node):
+    ng = len(graphs)
+    hs = (ctypes.c_void_p * ng)(*[g._h.value for g in graphs])
+    if totals.numel() < sum(g.k for g in graphs):
+        raise ValueError("totals holds fewer entries than the graphs of the batch")
+    pn = None
+    if per_node is not None:
+        if len(per_node) != ng:
+            raise ValueError("one per-node output (or None) per handle")
+        for t, g in zip(per_node, graphs):
+            if t is not None and t.numel() < g.n_total:
+                raise ValueError("per-node output shorter than its handle's node count")
+        pn = (ctypes.c_void_p * ng)(*[(t.data_ptr() if t is not None else None) for t in per_node])
+    return hs, pn
 
 
 def count(n, src, dst, per_node: bool = True, **kw):

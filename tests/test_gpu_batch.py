@@ -105,5 +105,47 @@ def test_packed_batch_equals_plain_launches(tc):
     np.testing.assert_array_equal(np.concatenate(tots), packed)
     for hh in hs:
         hh.free()
-    for i in (0, 1, 17, 63):
-        assert packed[i] == oracle.count(gs[i].n, gs[i].src, gs[i].dst, per_node=False)[0]
+    for i, g in enumerate(gs):
+        assert packed[i] == oracle.count(g.n, g.src, g.dst, per_node=False)[0]
+
+
+def test_captured_batch_through_abi(tc):
+    """tc_count_capture over three handles (one packed), per-node outputs,
+    replayed on a side stream and on the current stream with eager work in
+    between; every replay equals the oracle."""
+    import torch
+
+    from paper_1406_5687_amd.capture import CapturedCount
+
+    gs = batch_graphs(6, seed=11)
+    extra = graphgen.chung_lu(5000, 60_000, 2.1, 12)
+    hs = [tc.build_oriented([(g.n, g.src, g.dst) for g in gs[:4]]),
+          tc.build_oriented([(gs[4].n, gs[4].src, gs[4].dst)]),
+          tc.build_oriented([(extra.n, extra.src, extra.dst)])]
+    refs = [oracle.count(g.n, g.src, g.dst) for g in gs[:5] + [extra]]
+    cap = CapturedCount(hs, per_node=True)
+    side = torch.cuda.Stream()
+    for rep in range(6):
+        cap.totals.fill_(-1)
+        for t in cap.per_node_outs:
+            t.fill_(-1)
+        if rep % 2:
+            side.wait_stream(torch.cuda.current_stream())
+            cap.replay(stream=side.cuda_stream)
+            side.synchronize()
+        else:
+            cap.replay()
+            torch.cuda.synchronize()
+        tot = cap.totals.cpu().numpy()
+        np.testing.assert_array_equal(tot, [r[0] for r in refs])
+        tv0 = cap.per_node_outs[0].cpu().numpy()
+        base = 0
+        for g, r in zip(gs[:4], refs[:4]):
+            np.testing.assert_array_equal(tv0[base:base + g.n], r[1])
+            base += g.n
+        np.testing.assert_array_equal(cap.per_node_outs[1].cpu().numpy(), refs[4][1])
+        np.testing.assert_array_equal(cap.per_node_outs[2].cpu().numpy(), refs[5][1])
+        hs[2].count_per_node()  # eager work on the handle's own scratch between replays
+    cap.free()
+    for h in hs:
+        h.free()
