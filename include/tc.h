@@ -153,6 +153,23 @@ tc_status tc_count_per_node(tc_graph *g, const tc_options *opt, int64_t *per_nod
 tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, int64_t *totals,
                          int64_t *const *per_node);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the count of
+ * tc_count_batch with the same arguments and results, whose scratch (queue
+ * heads, totals, per-node accumulators, handle descriptors) lives in a fixed
+ * device array of TC_STATIC_SCRATCH_BYTES per GPU, held by the library until
+ * the process ends, instead of memory allocated per call.  It calls no device
+ * allocator.  Outputs must be device pointers (opt->outputs_on_device = 1,
+ * else TC_ERR_INVALID_ARG).  The scratch needed is 256 + 8 * (sum of k) +
+ * 8 * (sum of n over the handles, when any per-node output is asked for),
+ * rounded up to 256, + 168 * ng bytes; a batch that needs more returns
+ * TC_ERR_TOO_LARGE before any launch.  Every call on one GPU uses the same
+ * array and clears what it reads before the count: calls that overlap on one
+ * GPU (two streams, two threads) race and must be serialised by the caller. */
+#define TC_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+tc_status tc_count_batch_static(tc_graph *const *gs, int32_t ng, const tc_options *opt, int64_t *totals,
+                                int64_t *const *per_node);
+
 /* A count of ng handles captured once as a HIP graph and replayed as one graph
  * launch (Fig. 11: the worker loop of one count, with its queue resets and
  * reductions, as a unit the host launches).  tc_count_capture records on a

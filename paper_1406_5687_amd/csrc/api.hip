@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "internal.h"
 
@@ -195,6 +196,7 @@ struct DescPack {
     tc::CountDesc d[kDescPack];
 };
 static_assert(sizeof(DescPack) <= 3072, "descriptor pack must fit the kernel argument space");
+static_assert(sizeof(tc::CountDesc) == 168, "tc.h states the scratch of tc_count_batch_static with 168-byte descriptors");
 
 __global__ void k_store_descs(DescPack p, int n, tc::CountDesc *out) {
     const int i = (int)threadIdx.x;
@@ -275,6 +277,35 @@ void write_device_outputs(tc_graph *const *gs, int32_t ng, const BatchLayout &la
         if (per_node[i] && gs[i]->pk.N > 0)
             tc::scatter_per_node(tv + lay.nbase[i], gs[i]->o.perm.p, gs[i]->pk.N, per_node[i], s);
     copy_out(totals, base + lay.tot_off, (size_t)lay.kbase[ng] * 8, true, s);
+}
+
+// Scratch of tc_count_batch_static: one array per GPU, held until the process
+// ends.  Host code reaches it only through the device address that
+// hipGetSymbolAddress gives for the current device (the symbol's host-side
+// name is not a device address).
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+std::mutex g_static_mu;
+std::vector<void *> g_static_ptr;  // per device ordinal
+
+void *static_scratch(int dev) {
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_ptr.empty()) {
+        int count = 0;
+        TC_HIP(hipGetDeviceCount(&count));
+        g_static_ptr.assign((size_t)std::max(count, 1), nullptr);
+    }
+    if (dev < 0 || dev >= (int)g_static_ptr.size()) throw tc::Error(TC_ERR_DEVICE, "current device out of range");
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            throw tc::Error(TC_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_static_ptr[dev] = p;
+    }
+    return g_static_ptr[dev];
 }
 
 }  // namespace
@@ -578,6 +609,28 @@ tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt,
         copy_out(totals, tot, (size_t)lay.kbase[ng] * 8, on_dev, s);
         if (!on_dev) TC_HIP(hipStreamSynchronize(s));
         // device descriptors and scratch are released in stream order here
+    });
+}
+
+tc_status tc_count_batch_static(tc_graph *const *gs, int32_t ng, const tc_options *opt, int64_t *totals,
+                                int64_t *const *per_node) {
+    const tc_status bad = check_batch_args(gs, ng, totals);
+    if (bad != TC_OK) return bad;
+    if (!opt || !opt->outputs_on_device)
+        return fail(TC_ERR_INVALID_ARG, "tc_count_batch_static writes device outputs only (outputs_on_device = 1)");
+    return guarded([&] {
+        check_options(opt);
+        hipStream_t s = (hipStream_t)opt->stream;
+        const BatchLayout lay = batch_layout(gs, ng, per_node);
+        if (lay.bytes > kStaticScratchBytes)
+            throw tc::Error(TC_ERR_TOO_LARGE, "batch needs " + std::to_string(lay.bytes) +
+                                                  " bytes of scratch; the static array holds " +
+                                                  std::to_string(kStaticScratchBytes));
+        int dev = 0;
+        TC_HIP(hipGetDevice(&dev));
+        uint8_t *base = (uint8_t *)static_scratch(dev);
+        launch_batch(gs, ng, opt, lay, base, true, s);
+        write_device_outputs(gs, ng, lay, base, totals, per_node, s);
     });
 }
 

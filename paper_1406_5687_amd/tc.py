@@ -24,8 +24,10 @@ EXPORTED = [
     "tc_options_default", "tc_build_oriented", "tc_count_total", "tc_count_per_node", "tc_count_batch",
     "tc_graph_info", "tc_export_csr", "tc_export_schedule", "tc_graph_free", "tc_status_str", "tc_last_error",
     "tc_graph_reschedule", "tc_worker_times", "tc_clustering", "tc_count_capture", "tc_count_replay",
-    "tc_count_graph_free",
+    "tc_count_graph_free", "tc_count_batch_static",
 ]
+
+STATIC_SCRATCH_BYTES = 32 << 20  # TC_STATIC_SCRATCH_BYTES
 
 
 class TcError(RuntimeError):
@@ -121,6 +123,8 @@ def load(path: str = LIB_PATH):
     lib.tc_count_per_node.argtypes = [P, ctypes.POINTER(Options), P, P]
     lib.tc_count_batch.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(Options), P,
                                    ctypes.POINTER(P)]
+    lib.tc_count_batch_static.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(Options), P,
+                                          ctypes.POINTER(P)]
     lib.tc_count_capture.argtypes = [ctypes.POINTER(P), ctypes.c_int32, ctypes.POINTER(Options), P,
                                      ctypes.POINTER(P), ctypes.POINTER(P)]
     lib.tc_count_replay.argtypes = [P, ctypes.POINTER(Options)]
@@ -142,7 +146,8 @@ def load(path: str = LIB_PATH):
     lib.tc_last_error.argtypes = []
     lib.tc_last_error.restype = ctypes.c_char_p
     for name in ("tc_build_oriented", "tc_count_total", "tc_count_per_node", "tc_count_batch", "tc_graph_info",
-                 "tc_export_csr", "tc_export_schedule", "tc_graph_reschedule", "tc_count_capture", "tc_count_replay"):
+                 "tc_export_csr", "tc_export_schedule", "tc_graph_reschedule", "tc_count_batch_static",
+                 "tc_count_capture", "tc_count_replay"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -494,6 +499,17 @@ def _device_batch_args(graphs, totals, per_node):
                 raise ValueError("per-node output shorter than its handle's node count")
         pn = (ctypes.c_void_p * ng)(*[(t.data_ptr() if t is not None else None) for t in per_node])
     return hs, pn
+
+
+def count_batch_static(graphs: Sequence[Graph], totals, per_node=None, **over):
+    """tc_count_batch_static: the batch count into device tensors (totals:
+    int64[sum of k]; per_node: None or one int64 tensor / None per handle),
+    with the library's fixed per-GPU scratch instead of allocated memory.
+    Asynchronous on the current stream."""
+    hs, pn = _device_batch_args(graphs, totals, per_node)
+    o = graphs[0]._opts(outputs_on_device=True, torch_allocator=False, **over)
+    _raise(load().tc_count_batch_static(hs, len(graphs), ctypes.byref(o), ctypes.c_void_p(totals.data_ptr()), pn))
+    return totals, per_node
 
 
 def count(n, src, dst, per_node: bool = True, **kw):
