@@ -7,11 +7,15 @@ sort, task table (tc_build_oriented), then the persistent counting kernels
 with per-node counts and their scatter back to caller labels
 (tc_count_per_node).  value = oriented edges / second of whole steps.
 
-Default workload: preferential attachment, 10^6 nodes, 50 distinct targets
-per new node (49,998,725 edges), seed 1.
+Default workload: R-MAT scale 24, edge factor 16, (a, b, c, d) = (0.57,
+0.19, 0.19, 0.05), seed 1 (268,435,456 draws, 260,372,937 distinct edges).
+The same run also times preferential attachment PA(n=10^6, d=50) and reports
+it under "detail".  Both results are checked against the expected values the
+CPU oracle wrote (tests/golden/fullsize_*.txt): T and the SHA-256 of the
+per-node counts; a mismatch exits non-zero without a result line.
 
-Prints one JSON line.  The CPU baseline is the plain oracle (single thread)
-timed on a smaller graph of the same family.
+Prints one JSON line.  The CPU baseline is the plain oracle (one thread)
+timed on R-MAT scale 20 of the same generator.
 """
 from __future__ import annotations
 
@@ -25,7 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "count_pa1e6_d50_counters.json")
+COUNTERS = {"rmat": os.path.join(ROOT, "profiles", "count_rmat24_counters.json"),
+            "pa": os.path.join(ROOT, "profiles", "count_pa1e6_d50_counters.json")}
 COUNT_SOURCE = os.path.join(ROOT, "paper_1406_5687_amd", "csrc", "count.hip")
 
 
@@ -46,51 +51,164 @@ def make_workload(name: str):
 
 
 def algorithmic_bytes(off, col, n: int, per_node: bool) -> tuple[int, int]:
-    """B_alg = 4 m + 4 sum_{s->t} |N_t| + 8 (n+1) + 8 n [per-node]:
-    each source list once, each target list once per stored edge, the row
-    offsets once and the per-node counts once.  Returns (bytes, sum |N_t|)."""
+    """B_alg = 4 m + 4 sum |N_t| + 8 (n+1) + 8 n [per-node]: each source list
+    once, each target list once per stored edge (v, t) that is not the last
+    entry of N_v, the row offsets once and the per-node counts once.  The last
+    entry t of N_v is the largest label in N_v, and every member of N_t is
+    larger still, so that intersection is empty by the order alone and its
+    list is never read.  Returns (bytes, sum |N_t|)."""
     import numpy as np
 
     dh = np.diff(off)
-    sum_dt = int(dh[col].sum()) if len(col) else 0
     m = len(col)
+    if not m:
+        return 8 * (n + 1) + (8 * n if per_node else 0), 0
+    sum_dt = int(dh[col].sum())
+    last = off[1:][dh > 0] - 1
+    sum_dt -= int(dh[col[last]].sum())
     return 4 * m + 4 * sum_dt + 8 * (n + 1) + (8 * n if per_node else 0), sum_dt
 
 
 def measured_traffic(workload: str):
-    """HBM bytes per per-node count launch from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by
-    what the same counters read for a plain copy of known size), or None when
-    there is no summary for this workload or the count kernel source has
-    changed since the counters were taken."""
+    """HBM bytes per per-node count from the committed rocprofv3 counter
+    summary of the workload (FETCH_SIZE and WRITE_SIZE in KiB per dispatch of
+    each count kernel, summed, scaled by what the same counters read for a
+    plain copy of known size), or None when there is no summary for this
+    workload or the count kernel source has changed since it was taken."""
     import hashlib
 
     try:
-        with open(COUNTERS) as fh:
+        with open(COUNTERS[workload]) as fh:
             c = json.load(fh)
         with open(COUNT_SOURCE, "rb") as fh:
             sha = hashlib.sha256(fh.read()).hexdigest()
-    except (OSError, ValueError):
+    except (KeyError, OSError, ValueError):
         return None
-    if c.get("workload") != workload or c.get("count_source_sha256") != sha:
+    if c.get("count_source_sha256") != sha or "fetch_kib_per_count" not in c:
         return None
-    return (c["fetch_kib_per_dispatch"] * 1024 * c["fetch_factor"]
-            + c["write_kib_per_dispatch"] * 1024 * c["write_factor"])
+    return (c["fetch_kib_per_count"] * 1024 * c["fetch_factor"]
+            + c["write_kib_per_count"] * 1024 * c["write_factor"])
 
 
-def cpu_baseline(seconds_hint: float = 20.0) -> dict:
-    """The oracle as it stands (single thread) on PA(2.5e5, 50): whole path,
-    edge list to per-node counts."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scale: int = 20) -> dict:
+    """The oracle as it stands (plain C, one thread) on R-MAT scale `scale`
+    from the same generator and parameters as the headline workload: its build
+    (canonical edges, degree order, orientation, row sort) and its count phase
+    (node iterator of Fig. 1 with per-node counts) timed separately; value =
+    oriented edges / second of the count phase."""
     import graphgen
     import oracle
 
-    g = graphgen.preferential_attachment(250_000, 50, 1)
+    g = graphgen.rmat(scale, 16, 0.57, 0.19, 0.19, 1)
     t0 = time.perf_counter()
-    T, tv, m = oracle.count(g.n, g.src, g.dst, per_node=True)
-    dt = time.perf_counter() - t0
-    return {"value": m / dt, "unit": "oriented edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"PA(n=2.5e5, d=50) seed 1, m={m}: full oracle run (canonical edges, degree order, "
-                      f"orientation, row sort, node iterator with per-node counts) in {dt:.2f} s"}
+    m, off, col, _ = oracle.orient(g.n, g.src, g.dst)
+    t1 = time.perf_counter()
+    T, _ = oracle.count_oriented(g.n, off, col, per_node=True)
+    t2 = time.perf_counter()
+    return {"value": m / (t2 - t1), "unit": "oriented edges/s", "cores": 1, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "sample": f"R-MAT scale {scale}, ef 16, (0.57,0.19,0.19,0.05), seed 1 (same generator as the headline, "
+                      f"2^{scale} nodes), m={m}, T={T}: oracle count phase (Fig. 1 node iterator, per-node counts) "
+                      f"{t2 - t1:.2f} s on one thread; its build (canonical edges, degree order, orientation, row "
+                      f"sort) {t1 - t0:.2f} s more",
+            "build_seconds": t1 - t0, "count_seconds": t2 - t1}
+
+
+def expected(workload: str):
+    """Oracle-written expected T and T_v digest of a workload, or None."""
+    from tests import fullsize
+
+    name = {"rmat": "rmat24", "pa": "pa", "er": "er"}[workload]
+    return fullsize.load(name) if fullsize.available(name) else None
+
+
+def run_single(workload: str, steps: int, warmup: int) -> dict:
+    """Times whole steps (tc_build_oriented + tc_count_per_node) on one
+    workload whose edge list is resident in HBM, and checks T and the per-node
+    counts against the oracle-written expected values."""
+    import numpy as np
+    import torch
+
+    import paper_1406_5687_amd as tc
+    from tests import fullsize
+
+    t0 = time.time()
+    g, wl_name = make_workload(workload)
+    log(f"generated {wl_name}: n={g.n} input edges={g.m} in {time.time() - t0:.1f} s")
+    src = torch.from_numpy(g.src).cuda()
+    dst = torch.from_numpy(g.dst).cuda()
+    n, m_in = g.n, g.m
+    del g
+    out = torch.zeros(n, dtype=torch.int64, device="cuda")
+    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    # sizes for the byte model (outside the timed region)
+    with tc.build_oriented([(n, src, dst)]) as h:
+        info = h.info()
+        off, col, _ = h.export_csr()
+    m = info["m"]
+    b_alg, sum_dt = algorithmic_bytes(off, col, n, per_node=True)
+    del off, col
+    log(f"m={m} max|N_v|={info['max_out_degree']} tasks={info['tasks']} sum|N_t|={sum_dt} B_alg={b_alg / 1e9:.3f} GB")
+
+    def step():
+        h = tc.build_oriented([(n, src, dst)])
+        h.count_per_node(out=out, totals=tot, time_kernels=True)
+        ms = h.info()["last_count_ms"]  # waits for the counting kernels
+        h.free()
+        return ms
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({warmup} steps)")
+    kernel_ms = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        kernel_ms.append(step())
+    ev1.record()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t_start) * 1e3 / steps
+    ms_per_step = max(wall_ms, ev0.elapsed_time(ev1) / steps)
+    T = int(tot.item())
+    tv = out.cpu().numpy()
+    log(f"T={T} ms/step={ms_per_step:.3f} count kernels ms={np.mean(kernel_ms):.3f}")
+
+    # one separate timing of the build alone (reported, not the metric)
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    h = tc.build_oriented([(n, src, dst)])
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - tb0) * 1e3
+    h.free()
+    del src, dst, out, tot
+
+    exp = expected(workload)
+    parity = None
+    if exp is not None:
+        parity = (T == exp["T"] and m == exp["m"] and fullsize.tv_sha256(tv) == exp["sha256"])
+        log(f"oracle-written expected values: T={exp['T']} m={exp['m']}; GPU result identical: {parity}")
+    k_ms = float(np.mean(kernel_ms))
+    achieved = b_alg / (k_ms * 1e-3) / 1e9
+    return {"workload": wl_name, "n": n, "m": m, "m_input": m_in, "ms_per_step": ms_per_step, "k_ms": k_ms,
+            "kernel_ms_min": float(np.min(kernel_ms)), "kernel_ms_max": float(np.max(kernel_ms)),
+            "build_ms": build_ms, "b_alg": b_alg, "sum_dt": sum_dt, "achieved": achieved, "T": T,
+            "parity": parity, "max_out_degree": info["max_out_degree"]}
 
 
 def bench_batch(args) -> int:
@@ -476,7 +594,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pa", choices=["pa", "er", "rmat", "batch", "serve"])
+    ap.add_argument("--workload", default="rmat", choices=["pa", "er", "rmat", "batch", "serve"])
+    ap.add_argument("--no-detail", action="store_true", help="headline workload only (no PA leg)")
     ap.add_argument("--requests", type=int, default=20000, help="requests in the serve workload")
     ap.add_argument("--streams", type=int, default=4, help="serve: workers (one HIP stream each)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="serve: device budget for admission")
@@ -521,88 +640,53 @@ def main() -> int:
     if args.ablation == "idle":
         return bench_ablation_idle(args)
 
-    t0 = time.time()
-    g, wl_name = make_workload(args.workload)
-    log(f"generated {wl_name}: n={g.n} input edges={g.m} in {time.time() - t0:.1f} s")
-    src = torch.from_numpy(g.src).cuda()
-    dst = torch.from_numpy(g.dst).cuda()
-    out = torch.zeros(g.n, dtype=torch.int64, device="cuda")
-    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
-
-    # sizes for the byte model (outside the timed region)
-    with tc.build_oriented([(g.n, src, dst)]) as h:
-        info = h.info()
-        off, col, _ = h.export_csr()
-    m = info["m"]
-    b_alg, sum_dt = algorithmic_bytes(off, col, g.n, per_node=True)
-    del off, col
-    log(f"m={m} max|N_v|={info['max_out_degree']} tasks={info['tasks']} sum|N_t|={sum_dt} B_alg={b_alg / 1e9:.3f} GB")
-
-    def step():
-        h = tc.build_oriented([(g.n, src, dst)])
-        h.count_per_node(out=out, totals=tot, time_kernels=True)
-        ms = h.info()["last_count_ms"]  # waits for the counting kernels
-        h.free()
-        return ms
-
-    for i in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
-    kernel_ms = []
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    ev0.record()
-    for i in range(args.steps):
-        kernel_ms.append(step())
-    ev1.record()
-    torch.cuda.synchronize()
-    t_end = time.perf_counter()
-    wall_ms = (t_end - t_start) * 1e3 / args.steps
-    ms_per_step = max(wall_ms, ev0.elapsed_time(ev1) / args.steps)
-    T = int(tot.item())
-    log(f"T={T} ms/step={ms_per_step:.3f} count kernels ms={np.mean(kernel_ms):.3f}")
-
-    # one separate timing of the build alone and of the count alone (reported, not the metric)
-    torch.cuda.synchronize()
-    tb0 = time.perf_counter()
-    h = tc.build_oriented([(g.n, src, dst)])
-    torch.cuda.synchronize()
-    build_ms = (time.perf_counter() - tb0) * 1e3
-    h.free()
-
-    k_ms = float(np.mean(kernel_ms))
-    achieved = b_alg / (k_ms * 1e-3) / 1e9
+    r = run_single(args.workload, args.steps, args.warmup)
+    if r["parity"] is False:
+        log("FAILED: the GPU result differs from the oracle-written expected values")
+        return 1
     res = {
         "metric": "oriented edges/s",
-        "value": m / (ms_per_step * 1e-3),
+        "value": r["m"] / (r["ms_per_step"] * 1e-3),
         "unit": "oriented edges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32 ids, int64 counts",
         "data": "synthetic",
-        "config": {"workload": wl_name, "n": g.n, "m": m, "m_input": g.m, "per_node": True,
+        "config": {"workload": r["workload"], "n": r["n"], "m": r["m"], "m_input": r["m_input"], "per_node": True,
                    "step": "tc_build_oriented + tc_count_per_node, edge list resident in HBM"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(args.workload),
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.00 + WRITE_SIZE x1.00)",
-                     "kernel": "k_count_small (+ k_count_wide when lists exceed 128 entries)",
-                     "alg_bytes_per_launch": b_alg, "kernel_ms": k_ms},
-        "detail": {"triangles": T, "count_kernel_ms": k_ms, "build_ms_single": build_ms,
-                   "count_only_edges_per_s": m / (k_ms * 1e-3), "sum_target_list_len": sum_dt},
+        "roofline": roofline(r, args.workload),
+        "detail": {"triangles": r["T"], "identical_to_oracle": r["parity"], "count_kernel_ms": r["k_ms"],
+                   "build_ms_single": r["build_ms"], "count_only_edges_per_s": r["m"] / (r["k_ms"] * 1e-3),
+                   "sum_target_list_len": r["sum_dt"]},
     }
+    rc = 0
+    if args.workload == "rmat" and not args.no_detail:
+        p = run_single("pa", min(args.steps, 10), min(args.warmup, 3))
+        if p["parity"] is False:
+            log("FAILED: the PA result differs from the oracle-written expected values")
+            rc = 1
+        res["detail"]["pa"] = {"workload": p["workload"], "m": p["m"], "value": p["m"] / (p["ms_per_step"] * 1e-3),
+                               "ms_per_step": p["ms_per_step"], "count_kernel_ms": p["k_ms"],
+                               "build_ms_single": p["build_ms"], "triangles": p["T"],
+                               "identical_to_oracle": p["parity"], "roofline": roofline(p, "pa")}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline ...")
         res["cpu_baseline"] = cpu_baseline()
     print(json.dumps(res), flush=True)
-    return 0
+    return rc
+
+
+def roofline(r: dict, workload: str) -> dict:
+    return {"bound": "hbm", "achieved": r["achieved"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": r["achieved"] / PEAK_HBM_GBS, "traffic": measured_traffic(workload),
+            "traffic_unit": "HBM bytes per count (rocprofv3 FETCH_SIZE x2.00 + WRITE_SIZE x1.00, count kernels)",
+            "kernel": "count kernels: k_count_small, k_count_wide (4- and 8-wave tiers), launched back to back",
+            "alg_bytes_per_launch": r["b_alg"], "kernel_ms": r["k_ms"]}
 
 
 if __name__ == "__main__":
