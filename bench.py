@@ -14,6 +14,12 @@ it under "detail".  Both results are checked against the expected values the
 CPU oracle wrote (tests/golden/fullsize_*.txt): T and the SHA-256 of the
 per-node counts; a mismatch exits non-zero without a result line.
 
+The default run also reports, under "detail", the batch of 4096 graphs
+counted by one captured launch against one plain launch per graph, and the
+20,000-request serving stream at 0.7 x its measured capacity against a plain
+build-and-count loop (p50 / p99 latency), each checked against the
+oracle-written expected values.
+
 Prints one JSON line.  The CPU baseline is the plain oracle (one thread)
 timed on R-MAT scale 20 of the same generator.
 """
@@ -211,10 +217,11 @@ def run_single(workload: str, steps: int, warmup: int) -> dict:
             "parity": parity, "max_out_degree": info["max_out_degree"]}
 
 
-def bench_batch(args) -> int:
+def run_batch(K: int, steps: int, warmup: int, tune: bool = False) -> dict:
     """Packed batch: all graphs in one handle, counted by one captured
     persistent launch, against one plain count launch per graph (separate
-    handles, launched back to back on one stream, one final synchronisation)."""
+    handles, launched back to back on one stream, one final synchronisation).
+    Totals are checked against the oracle-written expected values."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -224,8 +231,8 @@ def bench_batch(args) -> int:
     import paper_1406_5687_amd as tc
     from paper_1406_5687_amd.autotune import Autotuner
     from paper_1406_5687_amd.capture import CapturedCount
+    from tests import fullsize
 
-    K = args.batch_graphs
     t0 = time.time()
     specs = graphgen.batch_specs(K, seed=1)
     with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
@@ -238,33 +245,34 @@ def bench_batch(args) -> int:
     info = h.info()
     m = info["m"]
     log(f"packed build: n={info['n']} m={m} tasks={info['tasks']} wide={info['wide_nodes']} in {time.time() - t0:.1f} s")
-    if args.tune:
-        p = Autotuner().tune(h, per_node=False)
-        log(f"autotuned: {p}")
+    tuned = None
+    if tune:
+        tuned = Autotuner().tune(h, per_node=False)
+        log(f"autotuned: {tuned}")
     cap = CapturedCount(h, per_node=False)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         cap.replay()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         cap.replay()
     ev1.record()
     torch.cuda.synchronize()
-    batch_ms = ev0.elapsed_time(ev1) / args.steps
+    batch_ms = ev0.elapsed_time(ev1) / steps
     packed = cap.totals.cpu().numpy()[:K].copy()
+    cap.free()
     h.free()
-    del cap
-
     t0 = time.time()
     hs = [tc.build_oriented([(g.n, g.src, g.dst)]) for g in graphs]
     torch.cuda.synchronize()
     log(f"{K} separate builds in {time.time() - t0:.1f} s")
+    del graphs
     out = torch.zeros(K, dtype=torch.int64, device="cuda")
     for i, hh in enumerate(hs):
         hh.count_total(out=out[i:i + 1])
     torch.cuda.synchronize()
-    reps = max(1, min(args.steps, 3))
+    reps = max(1, min(steps, 3))
     ev0.record()
     for _ in range(reps):
         for i, hh in enumerate(hs):
@@ -276,18 +284,33 @@ def bench_batch(args) -> int:
     same = bool(np.array_equal(plain, packed))
     for hh in hs:
         hh.free()
+    parity = None
+    if fullsize.available("batch4096") and K == 4096:
+        exp = fullsize.load("batch4096")
+        parity = bool(np.array_equal(packed, [r[4] for r in exp["rows"]]) and m == exp["sum_m"])
+        log(f"batch totals identical to the oracle-written values: {parity}")
+    log(f"batch: captured {batch_ms:.2f} ms, plain {plain_ms:.2f} ms, ratio {plain_ms / batch_ms:.2f}")
+    return {"graphs": K, "m": m, "m_input": m_in, "batch_ms": batch_ms, "plain_ms": plain_ms,
+            "batched_over_plain": plain_ms / batch_ms, "identical_counts": same, "identical_to_oracle": parity,
+            "tasks": info["tasks"], "wide_nodes": info["wide_nodes"], "tuned": str(tuned) if tuned else None}
+
+
+def bench_batch(args) -> int:
+    r = run_batch(args.batch_graphs, args.steps, args.warmup, args.tune)
     res = {
-        "metric": "oriented edges/s", "value": m / (batch_ms * 1e-3), "unit": "oriented edges/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": batch_ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int32 ids, int64 counts", "data": "synthetic",
-        "config": {"workload": f"batch of {K} graphs (n log-uniform 1e3..2e5; even: G(n,m) mean degree U(8,64); "
-                               f"odd: Chung-Lu beta 2.1, 16n pairs), seed 1", "graphs": K, "m": m, "m_input": m_in,
+        "metric": "oriented edges/s", "value": r["m"] / (r["batch_ms"] * 1e-3), "unit": "oriented edges/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["batch_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32 ids, int64 counts",
+        "data": "synthetic",
+        "config": {"workload": f"batch of {r['graphs']} graphs (n log-uniform 1e3..2e5; even: G(n,m) mean degree "
+                               f"U(8,64); odd: Chung-Lu beta 2.1, 16n pairs), seed 1", "graphs": r["graphs"],
+                   "m": r["m"], "m_input": r["m_input"],
                    "step": "one captured persistent count launch over the packed handle (totals)"},
-        "detail": {"plain_ms": plain_ms, "batched_over_plain": plain_ms / batch_ms, "identical_counts": same,
-                   "tasks": info["tasks"], "wide_nodes": info["wide_nodes"]},
+        "detail": {k: r[k] for k in ("plain_ms", "batched_over_plain", "identical_counts", "identical_to_oracle",
+                                     "tasks", "wide_nodes", "tuned")},
     }
     print(json.dumps(res), flush=True)
-    return 0 if same else 1
+    return 0 if (r["identical_counts"] and r["identical_to_oracle"] is not False) else 1
 
 
 def bench_partitioned(args) -> int:
@@ -353,11 +376,14 @@ def bench_partitioned(args) -> int:
     return rc
 
 
-def bench_serve(args) -> int:
+def run_serve(N: int, streams: int, budget_gb: float, max_batch_edges: int, full: bool = True) -> dict:
     """Serving form: requests (one graph each) with Poisson arrivals, served
     by continuous batching; compared with a plain loop of one build and count
-    per request.  value = distinct edges of all requests / makespan at an
-    arrival rate of 0.7 x the measured capacity."""
+    per request.  Saturated capacity first (all requests waiting), then the
+    arrival rate 0.7 x that capacity; with `full`, also the overload rate
+    1.2 x and 200 requests served alone.  Every run's totals and per-node
+    digests must agree, and the 0.7 x run is checked against the
+    oracle-written expected values."""
     import concurrent.futures as cf
 
     import numpy as np
@@ -365,15 +391,15 @@ def bench_serve(args) -> int:
 
     import graphgen
     from paper_1406_5687_amd import serve
+    from tests import fullsize
 
-    N = args.requests
     t0 = time.time()
     specs = graphgen.serve_specs(N, seed=1)
     with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
         gs = []
         for i, g in enumerate(ex.map(lambda sp: sp.make(), specs)):
             gs.append(g)
-            if (i + 1) % 2000 == 0:
+            if (i + 1) % 5000 == 0:
                 log(f"generated {i + 1}/{N} requests ({time.time() - t0:.0f} s)")
     arena = serve.Arena([g.n for g in gs], [g.m for g in gs])
     for i, g in enumerate(gs):
@@ -381,8 +407,7 @@ def bench_serve(args) -> int:
     del gs
     m_in = int(arena.eoff[-1])
     log(f"generated {N} requests, {m_in} input edges, in the ingest arena after {time.time() - t0:.1f} s")
-    mk = dict(streams=args.streams, hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)),
-              max_batch_edges=args.max_batch_edges)
+    mk = dict(streams=streams, hbm_budget_bytes=int(budget_gb * (1 << 30)), max_batch_edges=max_batch_edges)
 
     # warm-up (allocator pools, kernels), then capacity with every request waiting
     serve.Server(**mk).run(arena)
@@ -399,44 +424,61 @@ def bench_serve(args) -> int:
     dig_run, tot_run = arena.digests(), arena.tot[:N].copy()
     log(f"lambda {lam:.0f}/s: makespan {run.makespan:.3f} s p50 {run.percentile_ms(50):.2f} ms "
         f"p99 {run.percentile_ms(99):.2f} ms, {len(run.batches)} batches")
-    rng = np.random.default_rng(7)
-    keep = sorted(rng.choice(N, size=min(200, N), replace=False).tolist())
-    alone_ok = True
-    for i in keep:
-        T, tv, _ = serve.serve_alone(arena, i)
-        alone_ok = alone_ok and T == arena.tot[i] and bool(np.array_equal(tv, arena.per_node(i)))
-    arena.clear_results()
-    over = serve.Server(**mk).run(arena, graphgen.poisson_arrivals(N, 1.2 * cap_rps, 2))
-    log(f"overload {1.2 * cap_rps:.0f}/s: p50 {over.percentile_ms(50):.2f} ms p99 {over.percentile_ms(99):.2f} ms")
-    same_runs = bool(np.array_equal(tot_sat, tot_run) and np.array_equal(dig_sat, dig_run)
-                     and np.array_equal(arena.tot[:N], tot_run) and np.array_equal(arena.digests(), dig_run))
-    log(f"alone == mixed on {len(keep)} ids: {alone_ok}; identical across runs: {same_runs}")
+    parity = None
+    if fullsize.available(f"serve{N}"):
+        exp = fullsize.load(f"serve{N}")
+        parity = bool(np.array_equal(tot_run, [r[4] for r in exp["rows"]]) and run.m_canonical == exp["sum_m"]
+                      and all(fullsize.tv_sha256(arena.per_node(i))[:16] == r[5] for i, r in enumerate(exp["rows"])))
+        log(f"served results identical to the oracle-written values: {parity}")
+    res = {"requests": N, "m_input": m_in, "m": run.m_canonical, "arrival_rate_per_s": lam,
+           "capacity_req_per_s": cap_rps, "saturated_edges_per_s": sat.m_canonical / sat.makespan,
+           "makespan_s": run.makespan, "edges_per_s": run.m_canonical / run.makespan,
+           "p50_ms": run.percentile_ms(50), "p99_ms": run.percentile_ms(99), "batches": len(run.batches),
+           "identical_to_oracle": parity}
+    same_runs = bool(np.array_equal(tot_sat, tot_run) and np.array_equal(dig_sat, dig_run))
+    if full:
+        rng = np.random.default_rng(7)
+        keep = sorted(rng.choice(N, size=min(200, N), replace=False).tolist())
+        alone_ok = True
+        for i in keep:
+            T, tv, _ = serve.serve_alone(arena, i)
+            alone_ok = alone_ok and T == arena.tot[i] and bool(np.array_equal(tv, arena.per_node(i)))
+        arena.clear_results()
+        over = serve.Server(**mk).run(arena, graphgen.poisson_arrivals(N, 1.2 * cap_rps, 2))
+        log(f"overload {1.2 * cap_rps:.0f}/s: p50 {over.percentile_ms(50):.2f} ms p99 {over.percentile_ms(99):.2f} ms")
+        same_runs = same_runs and bool(np.array_equal(arena.tot[:N], tot_run)
+                                       and np.array_equal(arena.digests(), dig_run))
+        log(f"alone == mixed on {len(keep)} ids: {alone_ok}")
+        res.update(overload_rate_per_s=1.2 * cap_rps, overload_p50_ms=over.percentile_ms(50),
+                   overload_p99_ms=over.percentile_ms(99), alone_equals_mixed_200=alone_ok)
     arena.clear_results()
     plain_s, plain_m = serve.run_plain(arena)
-    same_runs = same_runs and bool(np.array_equal(arena.tot[:N], tot_run))
-    log(f"plain loop: {plain_s:.2f} s, {plain_m / plain_s / 1e9:.3f} G edges/s")
-    value = run.m_canonical / run.makespan
+    same_runs = same_runs and bool(np.array_equal(arena.tot[:N], tot_run)
+                                   and np.array_equal(arena.digests(), dig_run))
+    log(f"plain loop: {plain_s:.2f} s, {plain_m / plain_s / 1e9:.3f} G edges/s; identical across runs: {same_runs}")
+    res.update(plain_seconds=plain_s, plain_edges_per_s=plain_m / plain_s,
+               served_over_plain=res["edges_per_s"] / (plain_m / plain_s),
+               saturated_over_plain=res["saturated_edges_per_s"] / (plain_m / plain_s),
+               identical_across_runs=same_runs)
+    return res
+
+
+def bench_serve(args) -> int:
+    r = run_serve(args.requests, args.streams, args.serve_budget_gb, args.max_batch_edges, full=True)
     res = {
-        "metric": "oriented edges/s", "value": value, "unit": "oriented edges/s", "n_gpus": 1,
-        "steps": 1, "warmup": 1, "ms_per_step": run.makespan * 1e3, "higher_is_better": True,
+        "metric": "oriented edges/s", "value": r["edges_per_s"], "unit": "oriented edges/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": r["makespan_s"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32 ids, int64 counts", "data": "synthetic",
-        "config": {"workload": f"serving: {N} requests, edges log-normal (median 5e4, sigma 1.5, clipped "
+        "config": {"workload": f"serving: {r['requests']} requests, edges log-normal (median 5e4, sigma 1.5, clipped "
                                f"[1e3, 2e7]); even: PA(d=20), odd: R-MAT ef 16; Poisson arrivals, seed 1",
-                   "requests": N, "m": run.m_canonical, "m_input": m_in, "per_node": True,
-                   "streams": args.streams, "hbm_budget_bytes": mk["hbm_budget_bytes"],
+                   "requests": r["requests"], "m": r["m"], "m_input": r["m_input"], "per_node": True,
+                   "streams": args.streams, "hbm_budget_bytes": int(args.serve_budget_gb * (1 << 30)),
                    "step": "all requests served (arrival to per-node counts in host memory) at 0.7 x capacity"},
-        "detail": {"arrival_rate_per_s": lam, "capacity_req_per_s": cap_rps,
-                   "saturated_edges_per_s": sat.m_canonical / sat.makespan,
-                   "p50_ms": run.percentile_ms(50), "p99_ms": run.percentile_ms(99),
-                   "overload_rate_per_s": 1.2 * cap_rps, "overload_p50_ms": over.percentile_ms(50),
-                   "overload_p99_ms": over.percentile_ms(99), "batches": len(run.batches),
-                   "plain_seconds": plain_s, "plain_edges_per_s": plain_m / plain_s,
-                   "served_over_plain": value / (plain_m / plain_s),
-                   "saturated_over_plain": (sat.m_canonical / sat.makespan) / (plain_m / plain_s),
-                   "alone_equals_mixed_200": alone_ok, "identical_across_runs": same_runs},
+        "detail": {k: v for k, v in r.items() if k not in ("requests", "m", "m_input", "edges_per_s", "makespan_s")},
     }
     print(json.dumps(res), flush=True)
-    return 0 if (alone_ok and same_runs) else 1
+    ok = r["alone_equals_mixed_200"] and r["identical_across_runs"] and r["identical_to_oracle"] is not False
+    return 0 if ok else 1
 
 
 def bench_ablation_surrogate(args) -> int:
@@ -595,7 +637,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rmat", choices=["pa", "er", "rmat", "batch", "serve"])
-    ap.add_argument("--no-detail", action="store_true", help="headline workload only (no PA leg)")
+    ap.add_argument("--no-detail", action="store_true",
+                    help="headline workload only (no PA, batch and serve legs under detail)")
     ap.add_argument("--requests", type=int, default=20000, help="requests in the serve workload")
     ap.add_argument("--streams", type=int, default=4, help="serve: workers (one HIP stream each)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="serve: device budget for admission")
@@ -674,9 +717,22 @@ def main() -> int:
                                "ms_per_step": p["ms_per_step"], "count_kernel_ms": p["k_ms"],
                                "build_ms_single": p["build_ms"], "triangles": p["T"],
                                "identical_to_oracle": p["parity"], "roofline": roofline(p, "pa")}
+    if args.workload == "rmat" and not args.no_detail:
+        b = run_batch(args.batch_graphs, 5, 2)
+        res["detail"]["batch"] = b
+        if not b["identical_counts"] or b["identical_to_oracle"] is False:
+            log("FAILED: batched totals differ from the plain launches or the oracle-written values")
+            rc = 1
+        sv = run_serve(args.requests, args.streams, args.serve_budget_gb, args.max_batch_edges, full=False)
+        res["detail"]["serve"] = sv
+        if not sv["identical_across_runs"] or sv["identical_to_oracle"] is False:
+            log("FAILED: served results differ across runs or from the oracle-written values")
+            rc = 1
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline ...")
         res["cpu_baseline"] = cpu_baseline()
+    if rc:
+        return rc
     print(json.dumps(res), flush=True)
     return rc
 

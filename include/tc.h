@@ -102,8 +102,21 @@ typedef struct {
                              partition (the surrogate scheme); same results, for comparison */
     int32_t static_chunks; /* schedule: 1 = W tasks of equal cost instead of the shrinking tasks of
                               Eq. (1)/(2); same results, for comparison */
-    int32_t reserved[3];
+    int32_t intersect;    /* how a list counted by one wave (small_max entries at most; Fig. 1:
+                             S = N_v intersect N_u for each u in N_v) meets the list N_u of each
+                             of its entries u:
+                             TC_INTERSECT_AUTO: N_u is walked against a hash of N_v, unless N_u is
+                             longer than search_ratio times the entries of N_v after u (the only
+                             candidates), which are then looked up in N_u by binary search;
+                             TC_INTERSECT_WALK: always walked; TC_INTERSECT_SEARCH: always
+                             searched.  Same results either way.  Set at build or reschedule
+                             time; a count call with a non-zero intersect or search_ratio uses
+                             its own for that call */
+    int32_t search_ratio; /* R of TC_INTERSECT_AUTO, 1 .. 2^20; 0 = automatic (32) */
+    int32_t reserved[1];
 } tc_options;
+
+enum { TC_INTERSECT_AUTO = 0, TC_INTERSECT_WALK = 1, TC_INTERSECT_SEARCH = 2 };
 
 /* Fills *opt with the defaults (all zero except cost_fn = TC_COST_PRIOR). */
 void tc_options_default(tc_options *opt);
@@ -128,7 +141,8 @@ typedef struct tc_graph tc_graph;
 tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options *opt, tc_graph **out);
 
 /* Rebuilds the task table of an existing handle with the schedule options of
- * opt (workers, cost_fn, min_chunk, small_max; 0 = automatic, as in
+ * opt (workers, cost_fn, min_chunk, small_max, rounds, static_chunks; and the
+ * count settings intersect, search_ratio, lds_list_max; 0 = automatic, as in
  * tc_build_oriented) without touching the adjacency: per-node costs f
  * (Sections IV-B, IV-F, V-A), the split between lists counted by one wave and
  * by a whole workgroup, and the tasks of Eq. (1)/(2).  Counts are unchanged
@@ -220,7 +234,11 @@ typedef struct {
     int64_t streamed_bytes; /* partitioned form: host-to-device bytes moved by the last count */
     uint64_t peak_device_bytes; /* largest device footprint of the handle so far (build included) */
     int32_t rounds;         /* rounds of the current task table (see tc_options.rounds) */
-    int32_t reserved[3];
+    int32_t search_ratio;   /* intersection of later counts (one-wave lists): -1 = every row
+                               searched,
+                               0 = every row walked, R > 0 = rows longer than R times their
+                               candidates searched (see tc_options.intersect) */
+    int32_t reserved[2];
 } tc_graph_info_t;
 
 tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info);

@@ -1,10 +1,13 @@
-"""Autotuner for the task schedule: picks the rounds of Eq. (1) (how many tasks
-the first half of the cost is cut into per worker), the wave/workgroup list
-threshold, the task floor of Eq. (2) and the cost function for a built handle
-by timing the counting kernels on the data itself, and caches the choice per
-device and graph shape in a JSON file.  The search has two stages: rounds with
-the other parameters at their defaults, then the other parameters with the
-best rounds.
+"""Autotuner for the task schedule and the intersection: picks the rounds of
+Eq. (1) (how many tasks the first half of the cost is cut into per worker), the
+wave/workgroup list threshold, the task floor of Eq. (2), the cost function,
+the intersection variant of one-wave lists (hash walk, binary search, or the
+ratio rule between them) and the longest list a workgroup keeps in LDS, for a
+built handle, by timing the counting kernels on the data itself, and caches
+the choice per device and graph shape in a JSON file.  The search has three
+stages: rounds with the other parameters at their defaults, then threshold,
+floor and cost function with the best rounds, then the intersection and the
+LDS cap with the best of those.
 
 Counts do not depend on any of these choices (Section V-D: any task split
 counts every triangle once); only the time does.  The search reschedules the
@@ -30,6 +33,9 @@ class Params:
     floor_div: int = 128      # min_chunk = total_cost / (workers * floor_div)
     cost_fn: int = tc.COST_PRIOR
     rounds: int = 0           # Eq. (1) with W = workers * rounds; 0 = the library's choice
+    intersect: int = tc.INTERSECT_AUTO  # one-wave lists: ratio rule, hash walk only, or search only
+    search_ratio: int = 0     # R of the ratio rule; 0 = the library's choice
+    lds_list_max: int = 0     # longest list a workgroup hashes in LDS; 0 = the library's choice
 
     def min_chunk(self, total_cost: int, workers: int) -> int:
         return max(256, total_cost // (workers * self.floor_div + 1))
@@ -46,6 +52,20 @@ def candidates(rounds: int = 0) -> list:
             for floor_div in (16, 64, 128, 512):
                 out.append(Params(small_max, floor_div, cost_fn, rounds))
     return out
+
+
+def intersections(base: Params) -> list:
+    """Third-stage grid: the intersection variants and LDS caps around `base`."""
+    from dataclasses import replace
+
+    out = [replace(base, intersect=tc.INTERSECT_WALK), replace(base, intersect=tc.INTERSECT_SEARCH)]
+    out += [replace(base, intersect=tc.INTERSECT_AUTO, search_ratio=r) for r in SEARCH_RATIOS]
+    out += [replace(base, lds_list_max=c) for c in LDS_CAPS]
+    return out
+
+
+SEARCH_RATIOS = (8, 16, 64, 128)
+LDS_CAPS = (768, 1024, 1536)
 
 
 def features(info: dict) -> str:
@@ -111,14 +131,16 @@ class Autotuner:
         info = graph.info()
         graph.reschedule(workers=info["workers"], cost_fn=p.cost_fn,
                          min_chunk=p.min_chunk(info["total_cost"], info["workers"]), small_max=p.small_max,
-                         rounds=p.rounds)
+                         rounds=p.rounds, intersect=p.intersect, search_ratio=p.search_ratio,
+                         lds_list_max=p.lds_list_max)
 
     def tune(self, graph, per_node: bool = False, force: bool = False) -> Params:
         """Returns the chosen parameters and leaves the handle scheduled with them."""
         info = graph.info()
         key = self._key(info, per_node)
         if not force and key in self.cache:
-            p = Params(**self.cache[key]["params"])
+            known = {f for f in Params.__dataclass_fields__}
+            p = Params(**{k: v for k, v in self.cache[key]["params"].items() if k in known})
             self._apply(graph, p)
             return p
         best, best_t, trials = None, float("inf"), []
@@ -137,6 +159,7 @@ class Autotuner:
         else:
             run([Params(rounds=r) for r in ROUNDS])
             run([p for p in candidates(best.rounds) if p != best])
+            run([p for p in intersections(best) if p != best])
         self._apply(graph, best)
         self.cache[key] = {"params": asdict(best), "ms": best_t, "trials": len(trials)}
         self._save()

@@ -17,14 +17,16 @@ struct tc_graph {
     int32_t rounds = 0;       // as asked (0 = automatic)
     int32_t workers = 0;
     int32_t small_max = 128;
-    int32_t lds_max = 4096;
+    int32_t lds_max = 1920;  // as tc::max_lds_list(); set at build
     int32_t cost_fn = TC_COST_PRIOR;
+    int32_t search = 32;  // one-wave lists: search ratio of the descriptors (-1 every row, 0 none)
     // persistent count scratch: queue heads, totals, per-node accumulators
     tc::DevBuf<uint32_t> heads;
     tc::DevBuf<int64_t> totals;
     tc::DevBuf<int64_t> tv;
     tc::DevBuf<tc::CountDesc> desc;  // one descriptor pointing at the buffers above
     bool desc_has_tv = false;
+    int32_t desc_search = 0;  // search ratio written into desc
     // optional device timing of the counting kernels
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool timed = false;
@@ -98,6 +100,27 @@ void check_options(const tc_options *opt) {
         throw tc::Error(TC_ERR_INVALID_ARG, "negative option value");
     if (opt->cost_fn < TC_COST_ONE || opt->cost_fn > TC_COST_NEW)
         throw tc::Error(TC_ERR_INVALID_ARG, "unknown cost function");
+    if (opt->intersect < TC_INTERSECT_AUTO || opt->intersect > TC_INTERSECT_SEARCH)
+        throw tc::Error(TC_ERR_INVALID_ARG, "unknown intersection variant");
+    if (opt->search_ratio < 0 || opt->search_ratio > (1 << 20))
+        throw tc::Error(TC_ERR_INVALID_ARG, "search_ratio outside 0 .. 2^20");
+}
+
+constexpr int32_t kDefaultSearchRatio = 32;
+
+// Descriptor encoding of the intersection choice: -1 = search every row,
+// 0 = walk every row, R > 0 = search rows longer than R times their candidates.
+int32_t resolve_search(int32_t intersect, int32_t ratio) {
+    if (intersect == TC_INTERSECT_WALK) return 0;
+    if (intersect == TC_INTERSECT_SEARCH) return -1;
+    return ratio > 0 ? ratio : kDefaultSearchRatio;
+}
+
+// The search setting of a count call: its own when it names one, else the handle's.
+int32_t count_search(const tc_graph *g, const tc_options *opt) {
+    if (opt && (opt->intersect != TC_INTERSECT_AUTO || opt->search_ratio != 0))
+        return resolve_search(opt->intersect, opt->search_ratio);
+    return g->search;
 }
 
 // Stores a descriptor passed by value (kernel arguments need no host copy).
@@ -117,12 +140,12 @@ __global__ void k_count_reset(uint32_t *heads, int64_t *totals, int64_t k, int64
 }
 
 // Per-handle descriptor used by single-handle counts (kept on the device).
-void ensure_scratch(tc_graph *g, bool per_node, hipStream_t s) {
+void ensure_scratch(tc_graph *g, bool per_node, int32_t search, hipStream_t s) {
     g->al.stream = s;
     if (!g->heads.p) g->heads = tc::DevBuf<uint32_t>(g->al, 4);  // 3 queue heads
     if (!g->totals.p) g->totals = tc::DevBuf<int64_t>(g->al, (size_t)std::max(g->pk.k, 1));
     if (per_node && !g->tv.p) g->tv = tc::DevBuf<int64_t>(g->al, (size_t)std::max<int64_t>(g->pk.N, 1));
-    if (!g->part && (!g->desc.p || (per_node && !g->desc_has_tv))) {
+    if (!g->part && (!g->desc.p || (per_node && !g->desc_has_tv) || g->desc_search != search)) {
         tc::CountDesc d{};
         d.off = g->o.off.p;
         d.col = g->o.col.p;
@@ -141,10 +164,12 @@ void ensure_scratch(tc_graph *g, bool per_node, hipStream_t s) {
         d.large_base = 0;
         d.k = g->pk.k;
         d.small_max = g->small_max;
+        d.search_ratio = search;
         if (!g->desc.p) g->desc = tc::DevBuf<tc::CountDesc>(g->al, 1);
         k_store_desc<<<1, 64, 0, s>>>(d, g->desc.p);
         TC_LAUNCH_CHECK();
         g->desc_has_tv = g->tv.p != nullptr;
+        g->desc_search = search;
     }
 }
 
@@ -236,6 +261,7 @@ void launch_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, const 
         d.large_base = large_base;
         d.k = g->pk.k;
         d.small_max = g->small_max;
+        d.search_ratio = count_search(g, opt);
         task_base += g->o.tasks;
         med_base += g->o.nmed;
         large_base += g->o.nbig - g->o.nmed;
@@ -368,6 +394,7 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
         g->cost_fn = o.cost_fn;
         g->min_chunk = o.min_chunk;
         g->rounds = o.rounds;
+        g->search = resolve_search(o.intersect, o.search_ratio);
         tc::BuildParams bp;
         bp.workers = g->workers;
         bp.cost_fn = o.cost_fn;
@@ -481,6 +508,8 @@ tc_status tc_graph_reschedule(tc_graph *g, const tc_options *opt) {
         g->workers = bp.workers;
         g->small_max = bp.small_max;
         g->cost_fn = bp.cost_fn;
+        g->search = resolve_search(o.intersect, o.search_ratio);
+        g->lds_max = o.lds_list_max > 0 ? std::max(2, std::min(o.lds_list_max, tc::max_lds_list())) : tc::max_lds_list();
         // the per-handle count descriptor caches the wide list and small_max
         g->desc.release();
         g->desc_has_tv = false;
@@ -493,7 +522,8 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
         const bool on_dev = opt && opt->outputs_on_device;
         hipStream_t s = opt ? (hipStream_t)opt->stream : nullptr;
         const bool want_tv = per_node != nullptr;
-        ensure_scratch(g, want_tv, s);
+        const int32_t search = count_search(g, opt);
+        ensure_scratch(g, want_tv, search, s);
         const size_t k = (size_t)g->pk.k;
         const bool timing = opt && opt->time_kernels;
         if (timing) {
@@ -510,7 +540,7 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
             bp.static_chunks = g->static_chunks;
             const int32_t lds = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
             if (timing) TC_HIP(hipEventRecord(g->ev[0], s));
-            tc::count_partitioned(*g->part, bp, lds, g->al, s, g->totals.p, want_tv ? g->tv.p : nullptr,
+            tc::count_partitioned(*g->part, bp, lds, search, g->al, s, g->totals.p, want_tv ? g->tv.p : nullptr,
                                   g->heads.p);
             if (timing) {
                 TC_HIP(hipEventRecord(g->ev[1], s));
@@ -714,6 +744,7 @@ tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info) {
     info->workers = g->workers;
     info->small_max = g->small_max;
     info->cost_fn = g->cost_fn;
+    info->search_ratio = g->search;
     info->last_count_ms = -1.0;
     if (g->timed) {
         float ms = 0.f;

@@ -22,6 +22,14 @@
 //     up to 768 entries, 8 waves up to 1920; lists longer than the LDS table
 //     (lds_max) are probed by binary search in device memory instead.
 //
+// Search variant (one-wave lists): a target row N_{t_i} much longer than the
+// part of L after t_i (the only entries that can be in it: every member of
+// N_{t_i} lies after t_i) is not walked.  Instead each candidate L[j], j > i,
+// is looked up in N_{t_i} by binary search in device memory, 64 (i, j) pairs
+// per wave step.  A row takes this path when its length exceeds R times the
+// a - 1 - i candidates (R = the descriptor's search_ratio; -1 = every row,
+// 0 = none); results do not depend on the choice.
+//
 // Per-node counts (Section II): a triangle {s, t_i, w} found at probe w adds
 // one to each of s, t_i and w.  Counts for entries of L are gathered in LDS
 // counters indexed by list position and flushed with one device atomic per
@@ -304,8 +312,89 @@ struct alignas(16) SmallLds {
     int32_t cnt[kSmallMax];        // per-position counts (per-node mode)
     uint8_t pos[kSmallHash];       // list position of each hashed id
     uint8_t tpos[kSmallMax];       // list position of each target row
+    int32_t slen[kSmallMax];       // length of each searched row
     alignas(4) uint8_t flag[kFlagBytes];
 };
+
+// The searched rows of one source (flags q0 / q1 of lanes i and 64 + i, row
+// lengths l0 / l1 and starts r0 / r1 relative to the row reader): the pairs
+// (i, j), j = i+1 .. a-1, of all of them are numbered in order.  Searched row
+// k sits at slot kSmallMax - 1 - k of base / tpos / slen and its first pair
+// number at P[kSmallMax - k]; the walk uses slots below its own row count,
+// which is at most te minus the searched rows, so the two never meet.
+// Returns the number of pairs; *nrows receives the number of searched rows.
+template <bool IDX32>
+__device__ __forceinline__ int32_t search_setup(SmallLds<IDX32> &S, bool q0, bool q1, int32_t l0, int32_t l1,
+                                                idx_t<IDX32> r0, idx_t<IDX32> r1, uint64_t Q0, uint64_t Q1,
+                                                int32_t a, int *nrows) {
+    const int lane = __lane_id();
+    const int32_t c0 = q0 ? a - 1 - lane : 0, c1 = q1 ? a - 65 - lane : 0;
+    const int32_t ic0 = wave_inclusive_sum(c0);
+    const int32_t ic1 = readlane32(ic0, 63) + wave_inclusive_sum(c1);
+    const int ns0 = popc64(Q0);
+    if (q0) {
+        const int k = mbcnt64(Q0), sl = kSmallMax - 1 - k;
+        S.base[sl] = r0;
+        S.slen[sl] = l0;
+        S.tpos[sl] = (uint8_t)lane;
+        S.P[kSmallMax - k] = ic0 - c0;
+    }
+    if (q1) {
+        const int k = ns0 + mbcnt64(Q1), sl = kSmallMax - 1 - k;
+        S.base[sl] = r1;
+        S.slen[sl] = l1;
+        S.tpos[sl] = (uint8_t)(64 + lane);
+        S.P[kSmallMax - k] = ic1 - c1;
+    }
+    *nrows = uniform32(ns0 + popc64(Q1));
+    return uniform32(readlane32(ic1, 63));
+}
+
+// Looks the pairs of the searched rows up, 64 per step: lane p finds its row
+// by binary search over the rows' first pair numbers, takes L[j] from the
+// lanes holding the list (x0 / x1), and looks it up in N_{t_i} by a
+// branch-free binary search in device memory.  A hit is the triangle
+// {s, t_i, L[j]}.
+template <bool PER_NODE, bool IDX32>
+__device__ __forceinline__ uint32_t search_pairs(SmallLds<IDX32> &S, const ColReader<IDX32> &rd, int32_t npairs,
+                                                 int ns, int32_t a, int32_t x0, int32_t x1) {
+    const int lane = __lane_id();
+    uint32_t hits = 0;
+    for (int32_t p0 = 0; p0 < npairs; p0 += 64) {
+        const int32_t p = p0 + lane;
+        const bool okp = p < npairs;
+        int lo = 0, hi = ns - 1;  // last searched row whose first pair is <= p
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (S.P[kSmallMax - mid] <= p)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int sl = kSmallMax - 1 - lo;
+        const int i = S.tpos[sl];
+        const int j = min(i + 1 + (p - S.P[kSmallMax - lo]), a - 1);
+        const int32_t xa = __shfl(x0, j & 63, 64), xb = __shfl(x1, j & 63, 64);
+        const int32_t x = j < 64 ? xa : xb;
+        const idx_t<IDX32> rb = S.base[sl];
+        int32_t n = okp ? S.slen[sl] : 1;
+        int32_t at = 0;
+        while (n > 1) {  // at: the last entry <= x so far (or 0), N_t[at .. at + n) still open
+            const int32_t half = n >> 1;
+            if (rd.load(rb + at + half, true) <= x) at += half;
+            n -= half;
+        }
+        const bool hit = okp && rd.load(rb + at, true) == x;
+        if (hit) {
+            ++hits;
+            if (PER_NODE) {
+                atomicAdd(&S.cnt[i], 1);
+                atomicAdd(&S.cnt[j], 1);
+            }
+        }
+    }
+    return hits;
+}
 
 // One source s whose list (a entries, 2 <= a <= 128) is already in registers:
 // x0 = L[lane], x1 = L[64 + lane] (clamped copies beyond a).  The first te
@@ -315,7 +404,8 @@ template <bool PER_NODE, bool IDX32, bool SLICE>
 __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColReader<IDX32> &rd,
                                                  gptr_t<const int32_t> gcol, gptr_t<const int64_t> off,
                                                  int64_t *__restrict__ tv, int32_t s, int32_t a, int32_t te,
-                                                 int32_t row_lo, int64_t ebase, int32_t x0, int32_t x1, int lane) {
+                                                 int32_t row_lo, int64_t ebase, int32_t x0, int32_t x1, int lane,
+                                                 int32_t sr) {
     const bool h0 = lane < a, h1 = lane + 64 < a;
     if (h0) {
         uint32_t sl = hash_slot(x0, kSmallHashBits);
@@ -333,8 +423,13 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     const int32_t y1 = SLICE ? (lane + 64 < te ? x1 - row_lo : 0) : x1;
     const int64_t r0 = off[y0], e0r = off[y0 + 1];
     const int64_t r1 = off[y1], e1r = off[y1 + 1];
-    const int32_t b0 = lane < te ? (int32_t)(e0r - r0) : 0;
-    const int32_t b1 = lane + 64 < te ? (int32_t)(e1r - r1) : 0;
+    const int32_t l0 = lane < te ? (int32_t)(e0r - r0) : 0;
+    const int32_t l1 = lane + 64 < te ? (int32_t)(e1r - r1) : 0;
+    // rows searched instead of walked: longer than sr times the candidates
+    // after the target (a - 1 - i >= 1 for every target i < te)
+    const bool q0 = sr != 0 && l0 > 0 && (sr < 0 || l0 > sr * (a - 1 - lane));
+    const bool q1 = sr != 0 && l1 > 0 && (sr < 0 || l1 > sr * (a - 65 - lane));
+    const int32_t b0 = q0 ? 0 : l0, b1 = q1 ? 0 : l1;
     const uint64_t m0 = __ballot(b0 > 0), m1 = __ballot(b1 > 0);
     const int n0 = popc64(m0);
     const int32_t inc0 = wave_inclusive_sum(b0);
@@ -355,10 +450,16 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     }
     const int nt = n0 + popc64(m1);
     if (lane == 0) S.P[nt] = total;
+    const uint64_t Q0 = __ballot(q0), Q1 = __ballot(q1);
+    int ns = 0;
+    const int32_t npairs = (Q0 | Q1) ? search_setup<IDX32>(S, q0, q1, l0, l1, (idx_t<IDX32>)(r0 - ebase),
+                                                             (idx_t<IDX32>)(r1 - ebase), Q0, Q1, a, &ns)
+                                     : 0;
     wave_lds_sync();
 
+    uint32_t hits = npairs ? search_pairs<PER_NODE, IDX32>(S, rd, npairs, ns, a, x0, x1) : 0u;
     const int32_t e_end = ((total + kStep - 1) / kStep) * kStep;
-    const uint32_t hits = walk_steps<kSmallHashBits, PER_NODE, true, IDX32, false, uint8_t>(
+    hits += walk_steps<kSmallHashBits, PER_NODE, true, IDX32, false, uint8_t>(
         S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag, rd, gcol, nt, total, 0, 0, e_end, 0, a, 0, tv);
     if (PER_NODE) {
         const uint64_t hs = wave_sum((uint64_t)hits);
@@ -425,6 +526,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
         }
         const ColReader<IDX32> rd(descs[h].col + ebase, mg);
         const int small_max = descs[h].small_max;
+        const int32_t sr = uniform32(descs[h].search_ratio);
         uint64_t tri = 0;
         for (int32_t s0 = v0; s0 < v1; s0 += 64) {
             const int32_t sv = min(s0 + lane, v1 - 1);
@@ -456,7 +558,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
                 const int32_t te = readlane32(tl, j);
                 const int32_t sl = SLICE ? readlane32(lab, j) : s0 + j;
                 tri += source_small<PER_NODE, IDX32, SLICE>(S, rd, col, off, tv, sl, a, te, row_lo, ebase, x0, x1,
-                                                            lane);
+                                                            lane, sr);
                 j = jn;
                 a = an;
                 rs = rn;

@@ -175,8 +175,9 @@ void build_partitioned(const int32_t *src, const int32_t *dst, bool on_device, c
 
 // Counts a partitioned graph slice by slice; totals (1 entry) and tv (N
 // entries, degree-order labels, may be NULL) are device arrays, zeroed here.
-void count_partitioned(Partitioned &pg, const BuildParams &bp, int32_t lds_max, Allocator &al, hipStream_t s,
-                       int64_t *totals, int64_t *tv, uint32_t *heads);
+// search: the one-wave intersection choice of the descriptors (CountDesc).
+void count_partitioned(Partitioned &pg, const BuildParams &bp, int32_t lds_max, int32_t search, Allocator &al,
+                       hipStream_t s, int64_t *totals, int64_t *tv, uint32_t *heads);
 
 // count.hip --------------------------------------------------------------
 
@@ -206,6 +207,10 @@ struct CountDesc {
     const int32_t *sid;
     const int32_t *tcnt;
     int32_t row_lo;
+    // one-wave lists: a target row longer than search_ratio times the list
+    // entries after the target is binary-searched instead of walked; -1 =
+    // every row, 0 = none
+    int32_t search_ratio;
 };
 
 struct CountLaunch {

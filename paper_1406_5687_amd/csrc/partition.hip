@@ -627,8 +627,8 @@ void build_partitioned(const int32_t *src, const int32_t *dst, bool on_device, c
     out.batch.push_back(R);
 }
 
-void count_partitioned(Partitioned &pg, const BuildParams &bp, int32_t lds_max, Allocator &al, hipStream_t s,
-                       int64_t *totals, int64_t *tv, uint32_t *heads) {
+void count_partitioned(Partitioned &pg, const BuildParams &bp, int32_t lds_max, int32_t search, Allocator &al,
+                       hipStream_t s, int64_t *totals, int64_t *tv, uint32_t *heads) {
     fill_zero(totals, 8, s);
     if (tv) fill_zero(tv, (size_t)std::max<int64_t>(pg.N, 1) * 8, s);
     pg.streamed_bytes = 0;
@@ -698,6 +698,7 @@ void count_partitioned(Partitioned &pg, const BuildParams &bp, int32_t lds_max, 
             d.nbig = sc.nbig;
             d.k = 1;
             d.small_max = bp.small_max;
+            d.search_ratio = search;
             d.soff = moff.p;
             d.scol = mcol.p;
             d.sid = rv.p;
