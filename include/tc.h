@@ -105,9 +105,10 @@ typedef struct {
     int32_t intersect;    /* how a list counted by one wave (small_max entries at most; Fig. 1:
                              S = N_v intersect N_u for each u in N_v) meets the list N_u of each
                              of its entries u:
-                             TC_INTERSECT_AUTO: N_u is walked against a hash of N_v, unless N_u is
-                             longer than search_ratio times the entries of N_v after u (the only
-                             candidates), which are then looked up in N_u by binary search;
+                             TC_INTERSECT_AUTO: N_u is walked against a hash of N_v, unless N_u
+                             holds 256 entries or more and is longer than search_ratio times the
+                             entries of N_v after u (the only candidates), which are then looked
+                             up in N_u by binary search;
                              TC_INTERSECT_WALK: always walked; TC_INTERSECT_SEARCH: always
                              searched.  Same results either way.  Set at build or reschedule
                              time; a count call with a non-zero intersect or search_ratio uses

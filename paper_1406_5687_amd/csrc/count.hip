@@ -26,9 +26,10 @@
 // part of L after t_i (the only entries that can be in it: every member of
 // N_{t_i} lies after t_i) is not walked.  Instead each candidate L[j], j > i,
 // is looked up in N_{t_i} by binary search in device memory, 64 (i, j) pairs
-// per wave step.  A row takes this path when its length exceeds R times the
-// a - 1 - i candidates (R = the descriptor's search_ratio; -1 = every row,
-// 0 = none); results do not depend on the choice.
+// per wave step.  A row takes this path when it holds at least a whole walk
+// step (256 ids) and its length exceeds R times the a - 1 - i candidates
+// (R = the descriptor's search_ratio; -1 = every row, 0 = none); results do
+// not depend on the choice.
 //
 // Per-node counts (Section II): a triangle {s, t_i, w} found at probe w adds
 // one to each of s, t_i and w.  Counts for entries of L are gathered in LDS
@@ -425,10 +426,11 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     const int64_t r1 = off[y1], e1r = off[y1 + 1];
     const int32_t l0 = lane < te ? (int32_t)(e0r - r0) : 0;
     const int32_t l1 = lane + 64 < te ? (int32_t)(e1r - r1) : 0;
-    // rows searched instead of walked: longer than sr times the candidates
-    // after the target (a - 1 - i >= 1 for every target i < te)
-    const bool q0 = sr != 0 && l0 > 0 && (sr < 0 || l0 > sr * (a - 1 - lane));
-    const bool q1 = sr != 0 && l1 > 0 && (sr < 0 || l1 > sr * (a - 65 - lane));
+    // rows searched instead of walked: at least a whole step long and longer
+    // than sr times the candidates after the target (a - 1 - i >= 1 for
+    // every target i < te); a shorter row shares its walk steps with others
+    const bool q0 = sr != 0 && l0 > 0 && (sr < 0 || (l0 >= kStep && l0 > sr * (a - 1 - lane)));
+    const bool q1 = sr != 0 && l1 > 0 && (sr < 0 || (l1 >= kStep && l1 > sr * (a - 65 - lane)));
     const int32_t b0 = q0 ? 0 : l0, b1 = q1 ? 0 : l1;
     const uint64_t m0 = __ballot(b0 > 0), m1 = __ballot(b1 > 0);
     const int n0 = popc64(m0);

@@ -26,7 +26,7 @@ def tc():
 def _workloads():
     return [
         ("rmat14", graphgen.rmat(14, 16, seed=31)),
-        ("rmat16", graphgen.rmat(16, 16, seed=37)),
+        ("rmat17", graphgen.rmat(17, 16, seed=37)),  # one-wave lists with target rows of 256+
         ("chung_lu", graphgen.chung_lu(20_000, 320_000, 2.1, 32)),
         ("pa", graphgen.preferential_attachment(20_000, 12, 33)),
         ("er", graphgen.erdos_renyi(5000, 60_000, 34)),
