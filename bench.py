@@ -112,18 +112,32 @@ def cpu_baseline(scale: int = 20) -> dict:
     from the same generator and parameters as the headline workload: its build
     (canonical edges, degree order, orientation, row sort) and its count phase
     (node iterator of Fig. 1 with per-node counts) timed separately; value =
-    oriented edges / second of the count phase."""
+    oriented edges / second of the count phase.  Beside it, under "threaded",
+    the oracle's task count on all host threads (Fig. 10/11 with the tasks of
+    Eq. (1)/(2) for W = threads)."""
     import graphgen
     import oracle
 
     g = graphgen.rmat(scale, 16, 0.57, 0.19, 0.19, 1)
     t0 = time.perf_counter()
-    m, off, col, _ = oracle.orient(g.n, g.src, g.dst)
+    m, off, col, deg = oracle.orient(g.n, g.src, g.dst)
     t1 = time.perf_counter()
     T, _ = oracle.count_oriented(g.n, off, col, per_node=True)
     t2 = time.perf_counter()
+    # the same count on all host threads, tasks of Eq. (1)/(2) for W = threads
+    # handed out by an atomic counter (the oracle's timing variant)
+    nth = max(1, min(64, os.cpu_count() or 1))
+    f = oracle.costs(off, col, deg, oracle.COST_PRIOR)
+    bnd = oracle.schedule(f, nth, 256)
+    t3 = time.perf_counter()
+    T2, _ = oracle.dynamic_count_threaded(off, col, bnd, nth, per_node=True)
+    t4 = time.perf_counter()
+    if T2 != T:
+        raise RuntimeError("threaded oracle count differs from the single-threaded one")
     return {"value": m / (t2 - t1), "unit": "oriented edges/s", "cores": 1, "kind": "oracle",
             "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "threaded": {"value": m / (t4 - t3), "threads": nth, "count_seconds": t4 - t3, "tasks": len(bnd) - 1,
+                         "schedule": "Eq. (1)/(2), W = threads, PRIOR costs, floor 256"},
             "sample": f"R-MAT scale {scale}, ef 16, (0.57,0.19,0.19,0.05), seed 1 (same generator as the headline, "
                       f"2^{scale} nodes), m={m}, T={T}: oracle count phase (Fig. 1 node iterator, per-node counts) "
                       f"{t2 - t1:.2f} s on one thread; its build (canonical edges, degree order, orientation, row "

@@ -37,7 +37,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, single-threaded)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC], check=True)
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC], check=True)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -59,6 +59,8 @@ def _load():
     lib.orc_schedule.argtypes = [ctypes.c_int32, _I64P, ctypes.c_int32, ctypes.c_int64, _I32P, ctypes.c_int64,
                                  _I64P]
     lib.orc_dynamic_count.argtypes = [ctypes.c_int32, _I64P, _I32P, _I32P, ctypes.c_int64, _I64P, _I64P]
+    lib.orc_dynamic_count_threaded.argtypes = [ctypes.c_int32, _I64P, _I32P, _I32P, ctypes.c_int64, ctypes.c_int32,
+                                               _I64P, _I64P]
     lib.orc_surrogate_count.argtypes = [ctypes.c_int32, _I64P, _I32P, ctypes.c_int32, _I32P, _I64P, _I64P,
                                         _I64P, _I64P]
     lib.orc_adj_build.argtypes = [ctypes.c_int32, ctypes.c_int64, _I32P, _I32P]
@@ -185,6 +187,21 @@ def dynamic_count(off, col, bnd, per_node: bool = True):
     Tv = np.zeros(max(n, 1), np.int64) if per_node else None
     _rc(lib.orc_dynamic_count(n, _p64(off), _p32(col), _p32(bnd), bnd.shape[0] - 1, _p64(T),
                               _p64(Tv) if per_node else None), "dynamic_count")
+    return int(T[0]), (Tv[:n] if per_node else None)
+
+
+def dynamic_count_threaded(off, col, bnd, threads: int, per_node: bool = True):
+    """dynamic_count with `threads` host threads pulling the tasks from one
+    atomic counter (for timing the CPU baseline; same results)."""
+    lib = _load()
+    off = np.ascontiguousarray(off, np.int64)
+    n = off.shape[0] - 1
+    col = _i32(col) if len(col) else np.zeros(1, np.int32)
+    bnd = _i32(bnd)
+    T = np.zeros(1, np.int64)
+    Tv = np.zeros(max(n, 1), np.int64) if per_node else None
+    _rc(lib.orc_dynamic_count_threaded(n, _p64(off), _p32(col), _p32(bnd), bnd.shape[0] - 1, int(threads), _p64(T),
+                                       _p64(Tv) if per_node else None), "dynamic_count_threaded")
     return int(T[0]), (Tv[:n] if per_node else None)
 
 

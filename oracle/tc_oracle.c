@@ -18,6 +18,7 @@
  *   - task schedule (initial half, shrinking tasks) .... Section V-B, Eq. (1) and Eq. (2)
  *   - space-efficient surrogate algorithm .............. Section IV-C, Fig. 2 and Fig. 3
  *   - task-based counting .............................. Section V-C, Fig. 10 and Fig. 11
+ *     (also on several host threads, for the CPU baseline's timing only)
  *
  * Readings where the paper is silent (stated once here, used throughout):
  *   - input edges may contain loops and repeated or reversed pairs; loops are
@@ -25,6 +26,8 @@
  *   - T_v counts every triangle that contains v (Section II), not only those
  *     whose lowest-ordered vertex is v.
  */
+#include <pthread.h>
+#include <stdatomic.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -428,6 +431,70 @@ int orc_dynamic_count(int32_t n, const int64_t *off, const int32_t *col, const i
     }
     *T_out = T;
     return ORC_OK;
+}
+
+/* Fig. 10/11 with `threads` workers on the host's cores: the same tasks and
+ * the same per-task node iterator as orc_dynamic_count, handed out in order
+ * by an atomic counter (the coordinator of Fig. 11), each worker adding its
+ * triangles into a private total and private per-node counts that are summed
+ * at the end.  For timing the CPU baseline only; its results equal those of
+ * orc_dynamic_count. */
+typedef struct {
+    const int64_t *off;
+    const int32_t *col;
+    const int32_t *bnd;
+    int64_t ntasks;
+    int32_t n;
+    atomic_llong *next;
+    int64_t T;
+    int64_t *Tv;
+} orc_worker;
+
+static void *orc_worker_run(void *arg) {
+    orc_worker *w = (orc_worker *)arg;
+    for (;;) {
+        const int64_t k = atomic_fetch_add(w->next, 1);
+        if (k >= w->ntasks) break;
+        int64_t Tk = 0;
+        count_task(w->off, w->col, w->bnd[k], w->bnd[k + 1], &Tk, w->Tv);
+        w->T += Tk;
+    }
+    return NULL;
+}
+
+int orc_dynamic_count_threaded(int32_t n, const int64_t *off, const int32_t *col, const int32_t *bnd,
+                               int64_t ntasks, int32_t threads, int64_t *T_out, int64_t *Tv) {
+    if (n < 0 || !off || !bnd || ntasks < 0 || !T_out || threads < 1 || threads > 1024) return ORC_EINVAL;
+    orc_worker *ws = (orc_worker *)calloc((size_t)threads, sizeof(orc_worker));
+    pthread_t *tid = (pthread_t *)calloc((size_t)threads, sizeof(pthread_t));
+    atomic_llong next;
+    atomic_init(&next, 0);
+    int rc = ws && tid ? ORC_OK : ORC_ENOMEM;
+    for (int32_t i = 0; i < threads && rc == ORC_OK; ++i) {
+        ws[i] = (orc_worker){off, col, bnd, ntasks, n, &next, 0, NULL};
+        if (Tv) {
+            ws[i].Tv = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+            if (!ws[i].Tv) rc = ORC_ENOMEM;
+        }
+    }
+    int32_t started = 0;
+    for (int32_t i = 0; i < threads && rc == ORC_OK; ++i, ++started)
+        if (pthread_create(&tid[i], NULL, orc_worker_run, &ws[i]) != 0) rc = ORC_ENOMEM;
+    for (int32_t i = 0; i < started; ++i) pthread_join(tid[i], NULL);
+    if (rc == ORC_OK) {
+        int64_t T = 0;
+        if (Tv) memset(Tv, 0, (size_t)n * sizeof(int64_t));
+        for (int32_t i = 0; i < threads; ++i) {
+            T += ws[i].T;
+            if (Tv)
+                for (int32_t v = 0; v < n; ++v) Tv[v] += ws[i].Tv[v];
+        }
+        *T_out = T;
+    }
+    for (int32_t i = 0; ws && i < threads; ++i) free(ws[i].Tv);
+    free(ws);
+    free(tid);
+    return rc;
 }
 
 /* Space-efficient algorithm of Fig. 3, with P processors simulated one after

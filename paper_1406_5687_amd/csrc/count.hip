@@ -230,10 +230,10 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
                 sl[q] = hash_slot(w[q], HBITS);
                 k[q] = key[sl[q]];
             }
-            uint64_t chain = 0;
+            bool need = false;
 #pragma unroll
-            for (int q = 0; q < kWin; ++q) chain |= __ballot(k[q] != w[q] && k[q] != -1);
-            if (chain) {
+            for (int q = 0; q < kWin; ++q) need = need || (k[q] != w[q] && k[q] != -1);
+            if (__ballot(need)) {
 #pragma unroll
                 for (int q = 0; q < kWin; ++q) {
                     while (k[q] != w[q] && k[q] != -1) {  // collision chain (rare)

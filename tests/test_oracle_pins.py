@@ -323,6 +323,22 @@ def test_schedule_properties(kind, W, floor):
     np.testing.assert_array_equal(Tv2, Tv)
 
 
+@pytest.mark.parametrize("threads", [1, 2, 3, 8])
+def test_threaded_task_count_equals_node_iterator(threads):
+    """The host-threaded task count (timing baseline only) gives the node
+    iterator's T and T_v, for schedules of several sizes."""
+    for g in (graphgen.rmat(12, 16, seed=21), graphgen.preferential_attachment(3000, 7, 22),
+              graphgen.erdos_renyi(500, 4000, 23)):
+        m, off, col, deg = oracle.orient(g.n, g.src, g.dst)
+        T, Tv = oracle.count_oriented(g.n, off, col)
+        f = oracle.costs(off, col, deg, oracle.COST_PRIOR)
+        for W in (1, threads, 64):
+            bnd = oracle.schedule(f, W, 1)
+            T2, Tv2 = oracle.dynamic_count_threaded(off, col, bnd, threads)
+            assert T2 == T
+            np.testing.assert_array_equal(Tv2, Tv)
+
+
 def test_cost_functions_closed_forms():
     # K_5: degrees all 4; ids break ties so N_v = {v+1..4}, dhat_v = 4 - v.
     n, s, d = gs.complete(5)
