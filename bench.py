@@ -231,7 +231,25 @@ def run_single(workload: str, steps: int, warmup: int) -> dict:
             "parity": parity, "max_out_degree": info["max_out_degree"]}
 
 
-def run_batch(K: int, steps: int, warmup: int, tune: bool = False) -> dict:
+def packed_alg_bytes(h) -> tuple[int, int]:
+    """B_alg of a packed handle's total-only count (no per-node term), from
+    its exported adjacency, in chunks; (bytes, sum |N_t|)."""
+    import numpy as np
+
+    off, col, _ = h.export_csr()
+    n = off.shape[0] - 1
+    dh = np.diff(off)
+    sum_dt = 0
+    step = 1 << 26
+    for a in range(0, col.shape[0], step):
+        sum_dt += int(dh[col[a:a + step]].sum())
+    last = off[1:][dh > 0] - 1
+    for a in range(0, last.shape[0], step):
+        sum_dt -= int(dh[col[last[a:a + step]]].sum())
+    return 4 * col.shape[0] + 4 * sum_dt + 8 * (n + 1), sum_dt
+
+
+def run_batch(K: int, steps: int, warmup: int, tune: bool = False, alg_bytes: bool = False) -> dict:
     """Packed batch: all graphs in one handle, counted by one captured
     persistent launch, against one plain count launch per graph (separate
     handles, launched back to back on one stream, one final synchronisation).
@@ -263,6 +281,10 @@ def run_batch(K: int, steps: int, warmup: int, tune: bool = False) -> dict:
     if tune:
         tuned = Autotuner().tune(h, per_node=False)
         log(f"autotuned: {tuned}")
+    b_alg = sum_dt = None
+    if alg_bytes:
+        b_alg, sum_dt = packed_alg_bytes(h)
+        log(f"packed handle: sum|N_t|={sum_dt} B_alg={b_alg / 1e9:.1f} GB")
     cap = CapturedCount(h, per_node=False)
     for _ in range(warmup):
         cap.replay()
@@ -306,11 +328,13 @@ def run_batch(K: int, steps: int, warmup: int, tune: bool = False) -> dict:
     log(f"batch: captured {batch_ms:.2f} ms, plain {plain_ms:.2f} ms, ratio {plain_ms / batch_ms:.2f}")
     return {"graphs": K, "m": m, "m_input": m_in, "batch_ms": batch_ms, "plain_ms": plain_ms,
             "batched_over_plain": plain_ms / batch_ms, "identical_counts": same, "identical_to_oracle": parity,
-            "tasks": info["tasks"], "wide_nodes": info["wide_nodes"], "tuned": str(tuned) if tuned else None}
+            "tasks": info["tasks"], "wide_nodes": info["wide_nodes"], "tuned": str(tuned) if tuned else None,
+            "alg_bytes": b_alg, "sum_target_list_len": sum_dt,
+            "hbm_frac": (b_alg / (batch_ms * 1e-3) / 1e9 / PEAK_HBM_GBS) if b_alg else None}
 
 
 def bench_batch(args) -> int:
-    r = run_batch(args.batch_graphs, args.steps, args.warmup, args.tune)
+    r = run_batch(args.batch_graphs, args.steps, args.warmup, args.tune, args.alg_bytes)
     res = {
         "metric": "oriented edges/s", "value": r["m"] / (r["batch_ms"] * 1e-3), "unit": "oriented edges/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["batch_ms"],
@@ -321,7 +345,8 @@ def bench_batch(args) -> int:
                    "m": r["m"], "m_input": r["m_input"],
                    "step": "one captured persistent count launch over the packed handle (totals)"},
         "detail": {k: r[k] for k in ("plain_ms", "batched_over_plain", "identical_counts", "identical_to_oracle",
-                                     "tasks", "wide_nodes", "tuned")},
+                                     "tasks", "wide_nodes", "tuned", "alg_bytes", "sum_target_list_len",
+                                     "hbm_frac")},
     }
     print(json.dumps(res), flush=True)
     return 0 if (r["identical_counts"] and r["identical_to_oracle"] is not False) else 1
@@ -659,6 +684,8 @@ def main() -> int:
     ap.add_argument("--max-batch-edges", type=int, default=1 << 26, help="serve: input edges per batch at most")
     ap.add_argument("--batch-graphs", type=int, default=4096, help="graphs in the batch workload")
     ap.add_argument("--tune", action="store_true", help="autotune the batch schedule before timing")
+    ap.add_argument("--alg-bytes", action="store_true",
+                    help="batch: compute the count's algorithmic bytes from the packed adjacency (slow)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ablation", choices=["surrogate", "idle"], default=None,
                     help="surrogate: direct vs surrogate streaming of the partitioned form (--partitions slices); "

@@ -23,6 +23,15 @@ that fits:
   * while one worker's batch is on the device, the others build or count
     theirs on their own streams.
 
+Resident adjacency.  With resident_bytes > 0 the handle built for a batch
+stays on the device after its results are out, up to that many device bytes
+(least recently used handles are released first).  Requests carry a graph key
+(by default their index): a request whose key is resident is answered from
+the cached adjacency with a count launch only (tc_count_batch over the cached
+handles it needs), without copying or building its edges again.  A batch is
+either a run of consecutive requests none of which is resident (copied, built
+and counted, then cached) or a run of consecutive resident ones (counted).
+
 Latency of a request = completion (results in the result arena) - arrival.
 """
 from __future__ import annotations
@@ -56,10 +65,14 @@ class Arena:
     Request i: edges src[eoff[i]:eoff[i+1]], dst[...] (int32 node ids in
     0..ns[i]-1); results T = tot[i], T_v = out[noff[i]:noff[i+1]]."""
 
-    def __init__(self, ns: Sequence[int], ms: Sequence[int], pinned: bool = True):
+    def __init__(self, ns: Sequence[int], ms: Sequence[int], pinned: bool = True, keys: Optional[Sequence] = None):
         self.ns = np.asarray(ns, np.int64)
         self.ms = np.asarray(ms, np.int64)
         self.N = int(self.ns.shape[0])
+        # graph identity of each request: equal keys name the same graph
+        self.keys = list(range(self.N)) if keys is None else list(keys)
+        if len(self.keys) != self.N:
+            raise ValueError("one key per request")
         self.eoff = np.zeros(self.N + 1, np.int64)
         np.cumsum(self.ms, out=self.eoff[1:])
         self.noff = np.zeros(self.N + 1, np.int64)
@@ -113,16 +126,109 @@ class ServeResult:
     batches: List[Tuple[int, int]]  # request ranges [a, b) in start order
     m_canonical: int                # distinct edges over all requests
     makespan: float                 # seconds from the start to the last completion
+    builds: int = 0                 # batches copied to the device and built
+    resident_hits: int = 0          # requests answered from a resident adjacency
 
     def percentile_ms(self, q: float) -> float:
         return float(np.percentile(self.latency, q) * 1e3)
+
+
+class _Resident:
+    """A cached handle: the built adjacency of one served batch."""
+
+    def __init__(self, graph, nbytes: int, m_of: List[int]):
+        self.graph = graph
+        self.nbytes = nbytes
+        self.m_of = m_of      # distinct edges of each packed graph
+        self.users = 0        # batches counting it right now
+        self.last = 0
+
+
+class ResidentCache:
+    """Handles kept on the device after their batch, least recently used
+    released first once their device bytes pass `limit` (0: none kept).
+    key -> (handle, graph index in the handle, first node of the graph)."""
+
+    def __init__(self, limit: int):
+        self.limit = int(limit)
+        self.lock = threading.Lock()
+        self.where = {}
+        self.handles = []
+        self.bytes = 0
+        self.clock = 0
+
+    def has(self, key) -> bool:
+        return self.limit > 0 and key in self.where
+
+    def pin(self, keys):
+        """(handle, graph index, first node) of every key, with the handles
+        held against release; None unless every key is resident."""
+        if self.limit <= 0:
+            return None
+        with self.lock:
+            ent = [self.where.get(k) for k in keys]
+            if any(e is None for e in ent):
+                return None
+            self.clock += 1
+            for h, _, _ in ent:
+                h.users += 1
+                h.last = self.clock
+            return ent
+
+    def unpin(self, ent):
+        with self.lock:
+            for h, _, _ in ent:
+                h.users -= 1
+            self._evict()
+
+    def keep(self, graph, keys, ns, ms) -> bool:
+        """Caches a served batch's handle; False when nothing is kept (the
+        caller frees it)."""
+        if self.limit <= 0:
+            return False
+        nbytes = int(graph.info()["device_bytes"])
+        if nbytes > self.limit:
+            return False
+        off = graph.export_offsets()  # degree-order labels: graph g owns a label range
+        nb = np.zeros(len(keys) + 1, np.int64)
+        np.cumsum(np.asarray(ns, np.int64), out=nb[1:])
+        h = _Resident(graph, nbytes, [int(off[nb[g + 1]] - off[nb[g]]) for g in range(len(keys))])
+        with self.lock:
+            self.clock += 1
+            h.last = self.clock
+            first = 0
+            for g, (k, n) in enumerate(zip(keys, ns)):
+                self.where[k] = (h, g, first)
+                first += int(n)
+            self.handles.append(h)
+            self.bytes += nbytes
+            self._evict()
+        return True
+
+    def _evict(self):
+        while self.bytes > self.limit:
+            idle = [h for h in self.handles if h.users == 0]
+            if not idle:
+                return
+            h = min(idle, key=lambda x: x.last)
+            self.handles.remove(h)
+            self.bytes -= h.nbytes
+            for k in [k for k, e in self.where.items() if e[0] is h]:
+                del self.where[k]
+            h.graph.free()
+
+    def clear(self):
+        with self.lock:
+            for h in self.handles:
+                h.graph.free()
+            self.handles, self.where, self.bytes = [], {}, 0
 
 
 class Server:
     """Continuous batching of triangle-count requests on one GPU."""
 
     def __init__(self, *, streams: int = 4, hbm_budget_bytes: int = 32 << 30, max_batch_edges: int = 1 << 26,
-                 max_batch_graphs: int = 4096, per_node: bool = True):
+                 max_batch_graphs: int = 4096, per_node: bool = True, resident_bytes: int = 0):
         if streams < 1:
             raise ValueError("streams must be >= 1")
         self.streams = streams
@@ -130,6 +236,8 @@ class Server:
         self.max_batch_edges = int(max_batch_edges)
         self.max_batch_graphs = int(max_batch_graphs)
         self.per_node = per_node
+        self.resident_bytes = int(resident_bytes)
+        self.cache = ResidentCache(self.resident_bytes)
 
     # ---------------------------------------------------------- scheduling
 
@@ -149,9 +257,11 @@ class Server:
                 a = st["taken"]
                 if a < st["arrived"]:
                     b, edges, charge = a, 0, 0
+                    hit = self.cache.has(arena.keys[a])
                     while b < st["arrived"]:
                         m = int(arena.ms[b])
-                        if b > a and (edges + m > self.max_batch_edges or b - a >= self.max_batch_graphs):
+                        if b > a and (edges + m > self.max_batch_edges or b - a >= self.max_batch_graphs
+                                      or self.cache.has(arena.keys[b]) != hit):
                             break
                         if charge + fp[b] > st["free"]:
                             # nothing else in flight: a request larger than the
@@ -190,6 +300,58 @@ class Server:
     def _run_batch(self, st, ws, a: int, b: int) -> int:
         """Counts requests [a, b) on this worker's stream; results land in the
         arena when this returns.  Returns the batch's distinct edges."""
+        arena = st["arena"]
+        pinned = self.cache.pin([arena.keys[i] for i in range(a, b)])
+        if pinned is not None:
+            try:
+                return self._run_resident(st, ws, a, b, pinned)
+            finally:
+                self.cache.unpin(pinned)
+        return self._run_build(st, ws, a, b)
+
+    def _run_resident(self, st, ws, a: int, b: int, entries) -> int:
+        """Requests [a, b), all resident: one tc_count_batch over the cached
+        handles they need (their own scratch, so handles shared with other
+        workers are safe), then each request's slice of its handle's results."""
+        import torch
+
+        arena = st["arena"]
+        stream = ws["stream"]
+        handles = []
+        slot = {}
+        for h, _, _ in entries:
+            if id(h) not in slot:
+                slot[id(h)] = len(handles)
+                handles.append(h)
+        with torch.cuda.stream(stream):
+            ktot = sum(h.graph.k for h in handles)
+            tot = torch.empty(max(ktot, 1), dtype=torch.int64, device="cuda")
+            outs = ([torch.empty(max(h.graph.n_total, 1), dtype=torch.int64, device="cuda") for h in handles]
+                    if self.per_node else None)
+            tc.count_batch_device([h.graph for h in handles], tot, outs, stream=stream.cuda_stream)
+            kbase = np.zeros(len(handles) + 1, np.int64)
+            np.cumsum([h.graph.k for h in handles], out=kbase[1:])
+            tot_pin = torch.empty(max(ktot, 1), dtype=torch.int64, pin_memory=True)
+            tot_pin.copy_(tot, non_blocking=True)
+            out_pin = None
+            if self.per_node:
+                out_pin = [torch.empty(max(h.graph.n_total, 1), dtype=torch.int64, pin_memory=True) for h in handles]
+                for o_p, o in zip(out_pin, outs):
+                    o_p.copy_(o, non_blocking=True)
+            stream.synchronize()
+        m = 0
+        for i, (h, g, n0) in zip(range(a, b), entries):
+            j = slot[id(h)]
+            arena.tot[i] = int(tot_pin[kbase[j] + g])
+            if self.per_node and arena.ns[i] > 0:
+                n = int(arena.ns[i])
+                arena.out[arena.noff[i]:arena.noff[i] + n] = out_pin[j].numpy()[n0:n0 + n]
+            m += h.m_of[g]
+        with st["lock"]:
+            st["hits"] += b - a
+        return m
+
+    def _run_build(self, st, ws, a: int, b: int) -> int:
         import torch
 
         arena = st["arena"]
@@ -216,7 +378,11 @@ class Server:
                 arena.t_tot[a:b].copy_(tot, non_blocking=True)
                 stream.synchronize()
             finally:
-                h.free()
+                if not self.cache.keep(h, [arena.keys[i] for i in range(a, b)], arena.ns[a:b],
+                                       arena.ms[a:b]):
+                    h.free()
+        with st["lock"]:
+            st["builds"] += 1
         return m_can
 
     def _worker(self, st, wid: int):
@@ -253,6 +419,7 @@ class Server:
             "arena": arena, "arrival": arr, "fp": [device_footprint(arena.ns[i], arena.ms[i]) for i in range(N)],
             "cv": threading.Condition(), "lock": threading.Lock(), "arrived": 0, "taken": 0,
             "free": self.budget, "charge": {}, "error": None, "done": np.zeros(N, float), "batches": [], "m": 0,
+            "builds": 0, "hits": 0,
         }
         st["t0"] = time.perf_counter()
         threads = [threading.Thread(target=self._worker, args=(st, w), daemon=True) for w in range(self.streams)]
@@ -264,7 +431,11 @@ class Server:
             raise st["error"]
         done = st["done"]
         return ServeResult(latency=done - arr, done=done, batches=st["batches"], m_canonical=int(st["m"]),
-                           makespan=float(done.max(initial=0.0)))
+                           makespan=float(done.max(initial=0.0)), builds=st["builds"], resident_hits=st["hits"])
+
+    def close(self):
+        """Releases the resident adjacencies."""
+        self.cache.clear()
 
 
 def serve_alone(arena: Arena, i: int, per_node: bool = True):

@@ -385,6 +385,15 @@ class Graph:
                                     ctypes.c_void_p(col.ctypes.data), ctypes.c_void_p(perm.ctypes.data)))
         return off, col[:m], perm[:n]
 
+    def export_offsets(self):
+        """off[n+1]: the row offsets in degree-order labels (packed graphs
+        occupy consecutive label ranges, graph after graph)."""
+        n = self.info()["n"]
+        off = np.zeros(n + 1, np.int64)
+        o = self._opts()
+        _raise(load().tc_export_csr(self._h, ctypes.byref(o), ctypes.c_void_p(off.ctypes.data), None, None))
+        return off
+
     def export_schedule(self):
         """(bnd[tasks+1], gid[tasks])."""
         lib = load()
@@ -516,6 +525,17 @@ def _device_batch_args(graphs, totals, per_node):
                 raise ValueError("per-node output shorter than its handle's node count")
         pn = (ctypes.c_void_p * ng)(*[(t.data_ptr() if t is not None else None) for t in per_node])
     return hs, pn
+
+
+def count_batch_device(graphs: Sequence[Graph], totals, per_node=None, **over):
+    """tc_count_batch into device tensors (totals: int64[sum of k]; per_node:
+    None or one int64 tensor / None per handle), asynchronous on the stream
+    (default: the current one).  Uses its own scratch, so a handle may be in
+    several such counts on different streams at once."""
+    hs, pn = _device_batch_args(graphs, totals, per_node)
+    o = graphs[0]._opts(outputs_on_device=True, **over)
+    _raise(load().tc_count_batch(hs, len(graphs), ctypes.byref(o), ctypes.c_void_p(totals.data_ptr()), pn))
+    return totals, per_node
 
 
 def count_batch_static(graphs: Sequence[Graph], totals, per_node=None, **over):

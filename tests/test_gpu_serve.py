@@ -93,3 +93,44 @@ def test_packed_device_build_in_place(tcmod):
         assert tot[i] == T_ref
         np.testing.assert_array_equal(tv[b:b + g.n], tv_ref)
         b += g.n
+
+
+def test_resident_adjacency_answers_repeat_requests(tcmod):
+    """Requests cycling over 12 graphs: with the adjacencies kept resident, a
+    second pass over the same requests is answered by count launches only
+    (no build), and every answer equals the oracle; with a budget for about
+    one batch, handles are released and rebuilt, with the same answers."""
+    from paper_1406_5687_amd import serve
+
+    base = [sp.make() for sp in graphgen.serve_specs(12, seed=5, hi=2e5)]
+    keys = [i % 12 for i in range(40)]
+    gs = [base[k] for k in keys]
+    ar = serve.Arena([g.n for g in gs], [g.m for g in gs], keys=keys)
+    for i, g in enumerate(gs):
+        ar.put(i, g.src, g.dst)
+    refs = [oracle.count(g.n, g.src, g.dst) for g in base]
+
+    def check():
+        for i, k in enumerate(keys):
+            assert ar.tot[i] == refs[k][0]
+            np.testing.assert_array_equal(ar.per_node(i), refs[k][1])
+
+    srv = serve.Server(streams=3, hbm_budget_bytes=1 << 30, max_batch_edges=1 << 21, max_batch_graphs=8,
+                       resident_bytes=1 << 34)
+    ar.clear_results()
+    first = srv.run(ar, graphgen.poisson_arrivals(40, 200.0, 3))
+    check()
+    assert first.builds >= 1
+    ar.clear_results()
+    again = srv.run(ar)
+    check()
+    assert again.builds == 0 and again.resident_hits == 40
+    assert again.m_canonical == first.m_canonical
+    srv.close()
+    small = serve.Server(streams=2, hbm_budget_bytes=1 << 30, max_batch_edges=1 << 21, max_batch_graphs=4,
+                         resident_bytes=serve.device_footprint(max(g.n for g in base), max(g.m for g in base)))
+    for _ in range(2):
+        ar.clear_results()
+        small.run(ar)
+        check()
+    small.close()

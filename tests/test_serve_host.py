@@ -106,3 +106,61 @@ def test_fingerprint_is_order_sensitive():
     a = np.array([1, 2, 3], np.int64)
     assert serve.fingerprint(a) != serve.fingerprint(a[::-1].copy())
     assert serve.fingerprint(a) == serve.fingerprint(a.copy())
+
+
+class FakeHandle:
+    """Stand-in for a built handle: device bytes, offsets of its packed graphs."""
+
+    def __init__(self, ns, ms, nbytes):
+        self.ns, self.nbytes = list(ns), nbytes
+        self.off = np.concatenate([[0], np.cumsum(np.repeat(1, sum(ns)))]).astype(np.int64)
+        self.freed = False
+
+    def info(self):
+        return {"device_bytes": self.nbytes}
+
+    def export_offsets(self):
+        return self.off
+
+    def free(self):
+        self.freed = True
+
+
+def test_resident_cache_lookup_pin_and_eviction():
+    c = serve.ResidentCache(250)
+    h1, h2, h3 = FakeHandle([3, 2], [5, 5], 100), FakeHandle([4], [9], 100), FakeHandle([1], [1], 100)
+    assert c.keep(h1, ["a", "b"], [3, 2], [5, 5]) and c.keep(h2, ["c"], [4], [9])
+    assert c.has("a") and c.has("b") and c.has("c") and not c.has("d")
+    ent = c.pin(["b", "a"])
+    assert [(e[1], e[2]) for e in ent] == [(1, 3), (0, 0)]
+    assert ent[0][0].m_of == [3, 2]  # one edge per node in the stand-in offsets
+    assert c.pin(["a", "d"]) is None
+    # a third handle passes the limit: the least recently used idle one goes
+    assert c.keep(h3, ["e"], [1], [1])
+    assert h2.freed and not h1.freed and not c.has("c")
+    c.unpin(ent)
+    c.clear()
+    assert h1.freed and h3.freed and not c.has("a")
+    # nothing is kept without a limit, or when one handle is larger than it
+    assert not serve.ResidentCache(0).keep(FakeHandle([1], [1], 10), ["x"], [1], [1])
+    assert not serve.ResidentCache(50).keep(FakeHandle([1], [1], 100), ["x"], [1], [1])
+
+
+def test_batches_do_not_mix_resident_and_new_requests():
+    ar = make_arena(30)
+    ar.keys = [i % 10 for i in range(30)]
+    srv = FakeServer(streams=2, hbm_budget_bytes=1 << 40, max_batch_graphs=30)
+    srv.resident_bytes = 1
+    srv.cache = serve.ResidentCache(1 << 30)
+    for k in range(0, 10, 2):  # even keys resident
+        srv.cache.where[k] = (object(), 0, 0)
+    got = []
+    orig = srv._run_batch
+
+    def run_batch(st, ws, a, b):
+        got.append([ar.keys[i] % 2 == 0 for i in range(a, b)])
+        return orig(st, ws, a, b)
+
+    srv._run_batch = run_batch
+    srv.run(ar)
+    assert all(len(set(g)) == 1 for g in got)
