@@ -114,10 +114,17 @@ typedef struct {
                              time; a count call with a non-zero intersect or search_ratio uses
                              its own for that call */
     int32_t search_ratio; /* R of TC_INTERSECT_AUTO, 1 .. 2^20; 0 = automatic (32) */
-    int32_t reserved[1];
+    int32_t hash;         /* the table of N_v in on-chip memory that each entry of N_u is looked up
+                             in (Fig. 1: the test w in S):
+                             TC_HASH_AUTO: two-choice (cuckoo) table, every lookup two reads; a
+                             list whose insertion fails falls back to linear probing;
+                             TC_HASH_LINEAR: linear probing for every list.  Same results either
+                             way.  Set at build or reschedule time; a count call with a non-zero
+                             hash uses its own for that call */
 } tc_options;
 
 enum { TC_INTERSECT_AUTO = 0, TC_INTERSECT_WALK = 1, TC_INTERSECT_SEARCH = 2 };
+enum { TC_HASH_AUTO = 0, TC_HASH_LINEAR = 1 };
 
 /* Fills *opt with the defaults (all zero except cost_fn = TC_COST_PRIOR). */
 void tc_options_default(tc_options *opt);
@@ -239,7 +246,8 @@ typedef struct {
                                searched,
                                0 = every row walked, R > 0 = rows longer than R times their
                                candidates searched (see tc_options.intersect) */
-    int32_t reserved[2];
+    int32_t hash;           /* TC_HASH_* of later counts (see tc_options.hash) */
+    int32_t reserved[1];
 } tc_graph_info_t;
 
 tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info);

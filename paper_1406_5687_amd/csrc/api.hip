@@ -20,6 +20,7 @@ struct tc_graph {
     int32_t lds_max = 1920;  // as tc::max_lds_list(); set at build
     int32_t cost_fn = TC_COST_PRIOR;
     int32_t search = 32;  // one-wave lists: search ratio of the descriptors (-1 every row, 0 none)
+    int32_t hash = TC_HASH_AUTO;  // LDS table of the lists: two-choice or linear probing
     // persistent count scratch: queue heads, totals, per-node accumulators
     tc::DevBuf<uint32_t> heads;
     tc::DevBuf<int64_t> totals;
@@ -104,6 +105,8 @@ void check_options(const tc_options *opt) {
         throw tc::Error(TC_ERR_INVALID_ARG, "unknown intersection variant");
     if (opt->search_ratio < 0 || opt->search_ratio > (1 << 20))
         throw tc::Error(TC_ERR_INVALID_ARG, "search_ratio outside 0 .. 2^20");
+    if (opt->hash < TC_HASH_AUTO || opt->hash > TC_HASH_LINEAR)
+        throw tc::Error(TC_ERR_INVALID_ARG, "unknown hash table kind");
 }
 
 constexpr int32_t kDefaultSearchRatio = 32;
@@ -114,6 +117,13 @@ int32_t resolve_search(int32_t intersect, int32_t ratio) {
     if (intersect == TC_INTERSECT_WALK) return 0;
     if (intersect == TC_INTERSECT_SEARCH) return -1;
     return ratio > 0 ? ratio : kDefaultSearchRatio;
+}
+
+// Eviction limit of the two-choice table for a count call (0 = linear
+// probing): the call's table kind when it names one, else the handle's.
+int32_t count_rounds(const tc_graph *g, const tc_options *opt) {
+    const int32_t h = opt && opt->hash != TC_HASH_AUTO ? opt->hash : g->hash;
+    return h == TC_HASH_LINEAR ? 0 : tc::kCuckooRounds;
 }
 
 // The search setting of a count call: its own when it names one, else the handle's.
@@ -239,7 +249,7 @@ void launch_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, const 
     tc::CountDesc *ddesc = (tc::CountDesc *)(base + lay.desc_off);
     std::vector<tc::CountDesc> hd((size_t)ng);
     int64_t task_base = 0, med_base = 0, large_base = 0;
-    int32_t workers = 0, lds_max = tc::max_lds_list();
+    int32_t workers = 0, lds_max = tc::max_lds_list(), rounds = tc::kCuckooRounds;
     for (int32_t i = 0; i < ng; ++i) {
         const tc_graph *g = gs[i];
         tc::CountDesc &d = hd[i];
@@ -267,6 +277,7 @@ void launch_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, const 
         large_base += g->o.nbig - g->o.nmed;
         workers = std::max(workers, g->workers);
         lds_max = std::min(lds_max, g->lds_max);
+        rounds = std::min(rounds, count_rounds(g, opt));
     }
     if (descs_by_kernel) {
         for (int32_t b = 0; b < ng; b += kDescPack) {
@@ -290,6 +301,7 @@ void launch_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, const 
     L.heads = heads;
     L.workers = opt && opt->workers > 0 ? opt->workers : workers;
     L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : lds_max;
+    L.cuckoo_rounds = rounds;
     L.per_node = lay.want_tv;
     tc::count_launch(L, s);
 }
@@ -395,6 +407,7 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
         g->min_chunk = o.min_chunk;
         g->rounds = o.rounds;
         g->search = resolve_search(o.intersect, o.search_ratio);
+        g->hash = o.hash;
         tc::BuildParams bp;
         bp.workers = g->workers;
         bp.cost_fn = o.cost_fn;
@@ -509,6 +522,7 @@ tc_status tc_graph_reschedule(tc_graph *g, const tc_options *opt) {
         g->small_max = bp.small_max;
         g->cost_fn = bp.cost_fn;
         g->search = resolve_search(o.intersect, o.search_ratio);
+        g->hash = o.hash;
         g->lds_max = o.lds_list_max > 0 ? std::max(2, std::min(o.lds_list_max, tc::max_lds_list())) : tc::max_lds_list();
         // the per-handle count descriptor caches the wide list and small_max
         g->desc.release();
@@ -540,7 +554,7 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
             bp.static_chunks = g->static_chunks;
             const int32_t lds = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
             if (timing) TC_HIP(hipEventRecord(g->ev[0], s));
-            tc::count_partitioned(*g->part, bp, lds, search, g->al, s, g->totals.p, want_tv ? g->tv.p : nullptr,
+            tc::count_partitioned(*g->part, bp, lds, search, count_rounds(g, opt), g->al, s, g->totals.p, want_tv ? g->tv.p : nullptr,
                                   g->heads.p);
             if (timing) {
                 TC_HIP(hipEventRecord(g->ev[1], s));
@@ -564,6 +578,7 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
             L.heads = g->heads.p;
             L.workers = opt && opt->workers > 0 ? opt->workers : g->workers;
             L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
+            L.cuckoo_rounds = count_rounds(g, opt);
             L.per_node = want_tv;
             g->times_used = 0;
             if (opt && opt->time_kernels == 2) {
@@ -745,6 +760,7 @@ tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info) {
     info->small_max = g->small_max;
     info->cost_fn = g->cost_fn;
     info->search_ratio = g->search;
+    info->hash = g->hash;
     info->last_count_ms = -1.0;
     if (g->timed) {
         float ms = 0.f;

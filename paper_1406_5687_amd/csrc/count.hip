@@ -16,6 +16,13 @@
 // starts inside the step (one ballot per 64-id window), so short rows never
 // leave lanes idle and long rows need no per-row loop.
 //
+// The table is two-choice (cuckoo): an id sits in one of two slots taken from
+// one multiplicative hash, so every probe is two independent LDS reads and no
+// loop.  With linear probing a wave would walk each 64-id window's collision
+// chains until its slowest lane ends, which on power-law lists costs more
+// than the probe itself.  A list whose insertion gives up (rare below half
+// load) is hashed by linear probing instead.
+//
 //   - lists with 2 <= a <= small_max (at most 128): one wave per list, tasks
 //     of consecutive sources pulled by waves (k_count_small);
 //   - longer lists: one workgroup per list (k_count_wide): 4 waves for lists
@@ -68,9 +75,40 @@ constexpr int kStep = 64 * kWin;  // ids per step
 // finds its four window flags in one 32-bit word; byte kStep is a sink.
 constexpr int kFlagBytes = kStep + 4;
 
-// multiplicative hash on the low 24 bits (full-rate 24-bit multiply)
+// multiplicative hash on the low 24 bits (full-rate 24-bit multiply): the top
+// `bits` bits of the 32-bit product are the slot; the next `bits` bits are
+// the other slot of the two-choice table
 __device__ __forceinline__ uint32_t hash_slot(int32_t x, int bits) {
     return (uint32_t)__umul24((uint32_t)x, 0x9E3779u) >> (32 - bits);
+}
+__device__ __forceinline__ uint32_t hash_slot2(int32_t x, int bits) {
+    return ((uint32_t)__umul24((uint32_t)x, 0x9E3779u) >> (32 - 2 * bits)) & ((1u << bits) - 1);
+}
+
+// Two-choice (cuckoo) insertion of x into an LDS table of 2^bits slots (-1 =
+// empty): x takes its first slot; a key it displaces moves to its other slot,
+// and so on, at most `rounds` moves.  Safe with other lanes inserting at the
+// same time (each move is one atomic exchange).  Returns false when a key is
+// still homeless after the last move: that key is then missing from the
+// table and the caller rebuilds the table with linear probing.
+template <int HBITS>
+__device__ __forceinline__ bool cuckoo_place(int32_t *key, int32_t x, int rounds) {
+    uint32_t sl = hash_slot(x, HBITS);
+    for (int r = 0; r < rounds; ++r) {
+        const int32_t old = atomicExch(&key[sl], x);
+        if (old == -1) return true;
+        x = old;
+        const uint32_t s1 = hash_slot(x, HBITS);
+        sl = s1 == sl ? hash_slot2(x, HBITS) : s1;
+    }
+    return false;
+}
+
+// The slot that holds x in a two-choice table (x must be in it).
+template <int HBITS>
+__device__ __forceinline__ uint32_t cuckoo_slot(const int32_t *key, int32_t x) {
+    const uint32_t s1 = hash_slot(x, HBITS);
+    return key[s1] == x ? s1 : hash_slot2(x, HBITS);
 }
 
 // which = 0: tasks, 1: medium lists, 2: long lists
@@ -150,15 +188,18 @@ using idx_t = typename std::conditional<IDX32, int32_t, int64_t>::type;
 // the row starts that fall inside the step, finds every lane's row with one
 // ballot per 64-id window, loads the 4 ids of each lane together, then probes
 // them together.  `cur` is the row holding e_begin.  Row indices are clamped
-// so every LDS read is valid, lanes past the end are masked, and the
-// collision chains of the hash are entered only when some lane needs one.
-//   IN_LDS: membership in the source list by the LDS hash (key/pos);
+// so every LDS read is valid and lanes past the end are masked.
+//   IN_LDS: membership in the source list by the LDS hash (key/pos): with
+//   CUCKOO a two-choice table (two independent reads per id, no loop),
+//   otherwise linear probing (collision chains entered only when some lane
+//   needs one);
 //   otherwise by binary search in the sorted list col[rs .. rs+a) (huge lists).
+// The return value is the wave's hits spread over its lanes (sum over lanes).
 // Per-node counts go to LDS counters by list position, or (huge lists) to tv.
 // GATHER: the list positions of a step's hits are read for all windows before
 // any counter is updated (one LDS wait per step); otherwise window by window,
 // which is faster where hits are sparse (the one-wave kernel's short lists).
-template <int HBITS, bool PER_NODE, bool IN_LDS, bool IDX32, bool GATHER, class PosT>
+template <int HBITS, bool PER_NODE, bool IN_LDS, bool CUCKOO, bool IDX32, bool GATHER, class PosT>
 __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *pos, const int32_t *P,
                                                const idx_t<IDX32> *base, const PosT *tpos, int32_t *cnt,
                                                uint8_t *flag, const ColReader<IDX32> &rd,
@@ -168,7 +209,8 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
     constexpr uint32_t kMask = (1u << HBITS) - 1;
     const int lane = __lane_id();
     uint32_t *flag_word = reinterpret_cast<uint32_t *>(flag);
-    uint32_t hits = 0;
+    uint32_t hits = 0;   // per lane
+    uint32_t whits = 0;  // per wave
     // wave-uniform by construction; first-lane copies keep them in scalar registers
     cur = uniform32(cur);
     nt = uniform32(nt);
@@ -224,22 +266,51 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
         for (int q = 0; q < kWin; ++q) w[q] = ok[q] ? w[q] : -1;
         if (IN_LDS) {
             uint32_t sl[kWin];
-            int32_t k[kWin];
-#pragma unroll
-            for (int q = 0; q < kWin; ++q) {
-                sl[q] = hash_slot(w[q], HBITS);
-                k[q] = key[sl[q]];
-            }
-            bool need = false;
-#pragma unroll
-            for (int q = 0; q < kWin; ++q) need = need || (k[q] != w[q] && k[q] != -1);
-            if (__ballot(need)) {
+            bool hit[kWin];
+            if (CUCKOO) {
+                // two-choice table: an id is in one of its two slots or absent
+                uint32_t s2[kWin];
+                int32_t k1[kWin], k2[kWin];
 #pragma unroll
                 for (int q = 0; q < kWin; ++q) {
-                    while (k[q] != w[q] && k[q] != -1) {  // collision chain (rare)
-                        sl[q] = (sl[q] + 1) & kMask;
-                        k[q] = key[sl[q]];
+                    const uint32_t p = __umul24((uint32_t)w[q], 0x9E3779u);
+                    sl[q] = p >> (32 - HBITS);
+                    s2[q] = (p >> (32 - 2 * HBITS)) & kMask;
+                    k1[q] = key[sl[q]];
+                    k2[q] = key[s2[q]];
+                }
+#pragma unroll
+                for (int q = 0; q < kWin; ++q) {
+                    // both reads are made; no short-circuit
+                    const bool first = k1[q] == w[q], second = k2[q] == w[q];
+                    hit[q] = ok[q] & (first | second);
+                    sl[q] = first ? sl[q] : s2[q];
+                    // ballots taken from the compares themselves (kept in scalar masks)
+                    whits += (uint32_t)popc64(__ballot(ok[q] & first) | __ballot(ok[q] & second));
+                }
+            } else {
+                int32_t k[kWin];
+#pragma unroll
+                for (int q = 0; q < kWin; ++q) {
+                    sl[q] = hash_slot(w[q], HBITS);
+                    k[q] = key[sl[q]];
+                }
+                bool need = false;
+#pragma unroll
+                for (int q = 0; q < kWin; ++q) need = need || (k[q] != w[q] && k[q] != -1);
+                if (__ballot(need)) {
+#pragma unroll
+                    for (int q = 0; q < kWin; ++q) {
+                        while (k[q] != w[q] && k[q] != -1) {  // collision chain
+                            sl[q] = (sl[q] + 1) & kMask;
+                            k[q] = key[sl[q]];
+                        }
                     }
+                }
+#pragma unroll
+                for (int q = 0; q < kWin; ++q) {
+                    hit[q] = ok[q] && k[q] == w[q];
+                    whits += (uint32_t)popc64(__ballot(hit[q]));
                 }
             }
             if (PER_NODE && GATHER) {
@@ -252,7 +323,7 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
                 }
 #pragma unroll
                 for (int q = 0; q < kWin; ++q) {
-                    if (ok[q] && k[q] == w[q]) {
+                    if (hit[q]) {
                         atomicAdd(&cnt[kw[q]], 1);
                         atomicAdd(&cnt[kt[q]], 1);
                     }
@@ -260,14 +331,12 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
             } else if (PER_NODE) {
 #pragma unroll
                 for (int q = 0; q < kWin; ++q) {
-                    if (ok[q] && k[q] == w[q]) {
+                    if (hit[q]) {
                         atomicAdd(&cnt[pos[sl[q]]], 1);
                         atomicAdd(&cnt[tpos[seg[q]]], 1);
                     }
                 }
             }
-#pragma unroll
-            for (int q = 0; q < kWin; ++q) hits += ok[q] && k[q] == w[q] ? 1u : 0u;
         } else {
 #pragma unroll
             for (int q = 0; q < kWin; ++q) {
@@ -300,7 +369,7 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
         else
             step(e0, std::false_type{});
     }
-    return hits;
+    return hits + (lane == 0 ? whits : 0u);
 }
 
 // --------------------------------------------------------------- one wave
@@ -406,17 +475,36 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
                                                  gptr_t<const int32_t> gcol, gptr_t<const int64_t> off,
                                                  int64_t *__restrict__ tv, int32_t s, int32_t a, int32_t te,
                                                  int32_t row_lo, int64_t ebase, int32_t x0, int32_t x1, int lane,
-                                                 int32_t sr) {
+                                                 int32_t sr, int rounds) {
     const bool h0 = lane < a, h1 = lane + 64 < a;
-    if (h0) {
-        uint32_t sl = hash_slot(x0, kSmallHashBits);
-        while (atomicCAS(&S.key[sl], -1, x0) != -1) sl = (sl + 1) & (kSmallHash - 1);
-        if (PER_NODE) S.pos[sl] = (uint8_t)lane;
+    bool cuckoo = rounds > 0;
+    if (cuckoo) {
+        bool bad = h0 && !cuckoo_place<kSmallHashBits>(S.key, x0, rounds);
+        if (h1 && !bad) bad = !cuckoo_place<kSmallHashBits>(S.key, x1, rounds);
+        cuckoo = __ballot(bad) == 0;
+        wave_lds_sync();
+        if (cuckoo) {
+            if (PER_NODE && h0) S.pos[cuckoo_slot<kSmallHashBits>(S.key, x0)] = (uint8_t)lane;
+            if (PER_NODE && h1) S.pos[cuckoo_slot<kSmallHashBits>(S.key, x1)] = (uint8_t)(64 + lane);
+        } else {
+            // a key found no place: empty the table and probe linearly instead
+            int4 *kv = reinterpret_cast<int4 *>(S.key);
+            kv[lane] = make_int4(-1, -1, -1, -1);
+            kv[64 + lane] = make_int4(-1, -1, -1, -1);
+            wave_lds_sync();
+        }
     }
-    if (h1) {
-        uint32_t sl = hash_slot(x1, kSmallHashBits);
-        while (atomicCAS(&S.key[sl], -1, x1) != -1) sl = (sl + 1) & (kSmallHash - 1);
-        if (PER_NODE) S.pos[sl] = (uint8_t)(64 + lane);
+    if (!cuckoo) {
+        if (h0) {
+            uint32_t sl = hash_slot(x0, kSmallHashBits);
+            while (atomicCAS(&S.key[sl], -1, x0) != -1) sl = (sl + 1) & (kSmallHash - 1);
+            if (PER_NODE) S.pos[sl] = (uint8_t)lane;
+        }
+        if (h1) {
+            uint32_t sl = hash_slot(x1, kSmallHashBits);
+            while (atomicCAS(&S.key[sl], -1, x1) != -1) sl = (sl + 1) & (kSmallHash - 1);
+            if (PER_NODE) S.pos[sl] = (uint8_t)(64 + lane);
+        }
     }
     // rows of t_0 .. t_{te-1}; empty rows are dropped so row starts are distinct.
     // Loads are unconditional (every lane indexes a valid row).
@@ -461,8 +549,12 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
 
     uint32_t hits = npairs ? search_pairs<PER_NODE, IDX32>(S, rd, npairs, ns, a, x0, x1) : 0u;
     const int32_t e_end = ((total + kStep - 1) / kStep) * kStep;
-    hits += walk_steps<kSmallHashBits, PER_NODE, true, IDX32, false, uint8_t>(
-        S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag, rd, gcol, nt, total, 0, 0, e_end, 0, a, 0, tv);
+    if (cuckoo)
+        hits += walk_steps<kSmallHashBits, PER_NODE, true, true, IDX32, false, uint8_t>(
+            S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag, rd, gcol, nt, total, 0, 0, e_end, 0, a, 0, tv);
+    else
+        hits += walk_steps<kSmallHashBits, PER_NODE, true, false, IDX32, false, uint8_t>(
+            S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag, rd, gcol, nt, total, 0, 0, e_end, 0, a, 0, tv);
     if (PER_NODE) {
         const uint64_t hs = wave_sum((uint64_t)hits);
         wave_lds_sync();
@@ -494,7 +586,7 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
 template <bool PER_NODE, bool IDX32, bool SLICE>
 __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_count_small(
     const CountDesc *__restrict__ descs, int ndesc, int64_t total_tasks, uint32_t *__restrict__ head, int nworkers,
-    unsigned long long *__restrict__ times) {
+    unsigned long long *__restrict__ times, int rounds) {
     __shared__ SmallLds<IDX32> lds[kSmallWaves];
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     const int64_t me = (int64_t)blockIdx.x * kSmallWaves + wave;
@@ -560,7 +652,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
                 const int32_t te = readlane32(tl, j);
                 const int32_t sl = SLICE ? readlane32(lab, j) : s0 + j;
                 tri += source_small<PER_NODE, IDX32, SLICE>(S, rd, col, off, tv, sl, a, te, row_lo, ebase, x0, x1,
-                                                            lane, sr);
+                                                            lane, sr, rounds);
                 j = jn;
                 a = an;
                 rs = rn;
@@ -597,6 +689,7 @@ struct WideLds {
     int32_t wcnt[WAVES];
     uint64_t whits[WAVES];
     int64_t item;
+    int32_t homeless;  // some key found no place in the two-choice table
 };
 
 // Lays out the rows of targets i in [i0, i1) (positions in the source list
@@ -653,7 +746,7 @@ __device__ __forceinline__ void wide_rows(L &S, gptr_t<const int32_t> col, gptr_
 template <int WAVES, int HBITS, bool PER_NODE, bool IDX32, class L>
 __device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &rd, gptr_t<const int32_t> gcol,
                                                  int64_t *__restrict__ tv, int64_t rs, int32_t a, int32_t i0,
-                                                 int32_t nt, int32_t total, bool in_lds) {
+                                                 int32_t nt, int32_t total, bool in_lds, bool cuckoo) {
     const int wave = uniform32(threadIdx.x >> 6);  // the same in every lane of the wave
     const int32_t nsteps = (total + kStep - 1) / kStep;
     const int32_t per = (nsteps + WAVES - 1) / WAVES;
@@ -669,20 +762,25 @@ __device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &r
         else
             hi = mid - 1;
     }
+    if (in_lds && cuckoo)
+        return walk_steps<HBITS, PER_NODE, true, true, IDX32, true, int16_t>(
+            S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs,
+            a, i0, tv);
     if (in_lds)
-        return walk_steps<HBITS, PER_NODE, true, IDX32, true, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
-                                                                 S.flag[wave], rd, gcol, nt, total, lo, e_begin,
-                                                                 s1 * kStep, rs, a, i0, tv);
-    return walk_steps<HBITS, PER_NODE, false, IDX32, true, int16_t>(S.key, S.pos, S.P, S.base, S.tpos, S.cnt,
-                                                              S.flag[wave], rd, gcol, nt, total, lo, e_begin,
-                                                              s1 * kStep, rs, a, i0, tv);
+        return walk_steps<HBITS, PER_NODE, true, false, IDX32, true, int16_t>(
+            S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs,
+            a, i0, tv);
+    return walk_steps<HBITS, PER_NODE, false, false, IDX32, true, int16_t>(
+        S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs, a,
+        i0, tv);
 }
 
 // tier 1: lists in big[0, nmed); tier 2: lists in big[nmed, nbig)
 template <bool PER_NODE, bool IDX32, int WAVES, int LMAX, int HBITS, int TIER, bool SLICE>
 __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVES == 8 ? 6 : 1))) void k_count_wide(const CountDesc *__restrict__ descs, int ndesc,
                                                            int64_t total_items, uint32_t *__restrict__ head,
-                                                           int lds_max, unsigned long long *__restrict__ times) {
+                                                           int lds_max, unsigned long long *__restrict__ times,
+                                                           int rounds) {
     constexpr int kThreadsW = WAVES * 64;
     constexpr int kHash = 1 << HBITS;
     __shared__ WideLds<WAVES, LMAX, HBITS, IDX32> S;
@@ -693,6 +791,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
     for (int i = threadIdx.x; i < WAVES * kFlagBytes; i += kThreadsW) (&S.flag[0][0])[i] = 0;
     if (threadIdx.x == 0) {
         S.item = blockIdx.x;
+        S.homeless = 0;
         if (times) times[2 * blockIdx.x] = wall_clock64();
     }
     __syncthreads();
@@ -727,16 +826,36 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
         if (te <= 0) {
             // no resident target (slice launches only)
         } else if (a <= cap) {
-            for (int32_t k = threadIdx.x; k < a; k += kThreadsW) {
-                const int32_t x = col[rs + k];
-                uint32_t sl = hash_slot(x, HBITS);
-                while (atomicCAS(&S.key[sl], -1, x) != -1) sl = (sl + 1) & (kHash - 1);
-                if (PER_NODE) S.pos[sl] = (int16_t)k;
+            if (rounds > 0) {
+                bool bad = false;
+                for (int32_t k = threadIdx.x; k < a && !bad; k += kThreadsW)
+                    bad = !cuckoo_place<HBITS>(S.key, col[rs + k], rounds);
+                if (__ballot(bad) && lane == 0) S.homeless = 1;
+                __syncthreads();
+            }
+            const bool cuckoo = rounds > 0 && !S.homeless;
+            if (cuckoo) {
+                if (PER_NODE) {
+                    for (int32_t k = threadIdx.x; k < a; k += kThreadsW)
+                        S.pos[cuckoo_slot<HBITS>(S.key, col[rs + k])] = (int16_t)k;
+                }
+            } else {
+                if (rounds > 0) {
+                    // a key found no place: empty the table and probe linearly instead
+                    for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = -1;
+                    __syncthreads();
+                }
+                for (int32_t k = threadIdx.x; k < a; k += kThreadsW) {
+                    const int32_t x = col[rs + k];
+                    uint32_t sl = hash_slot(x, HBITS);
+                    while (atomicCAS(&S.key[sl], -1, x) != -1) sl = (sl + 1) & (kHash - 1);
+                    if (PER_NODE) S.pos[sl] = (int16_t)k;
+                }
             }
             __syncthreads();
             int32_t nt, total;
             wide_rows<WAVES, IDX32>(S, col, off, rs, 0, te, row_lo, ebase, &nt, &total);
-            hits = wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, 0, nt, total, true);
+            hits = wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, 0, nt, total, true, cuckoo);
             __syncthreads();
             if (PER_NODE) {
                 for (int32_t k = threadIdx.x; k < a; k += kThreadsW) {
@@ -753,7 +872,8 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                 const int32_t i1 = min(te, i0 + cap);
                 int32_t nt, total;
                 wide_rows<WAVES, IDX32>(S, col, off, rs, i0, i1, row_lo, ebase, &nt, &total);
-                hits += wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, i0, nt, total, false);
+                hits += wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, i0, nt, total, false,
+                                                                    false);
                 __syncthreads();
             }
         }
@@ -767,6 +887,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                 add_u64(&descs[h].totals[g], H);
                 if (PER_NODE) add_u64(&tv[s], H);
             }
+            S.homeless = 0;
             S.item = (int64_t)gridDim.x + (int64_t)atomicAdd(head, 1u);
         }
         __syncthreads();
@@ -840,7 +961,7 @@ void launch_all(CountLaunch &L, int lds_max, hipStream_t s) {
         unsigned long long *tm = times_for((int64_t)blocks * kSmallWaves);
         L.times_tier[0] = tm ? (int64_t)blocks * kSmallWaves : 0;
         k_count_small<PER_NODE, IDX32, SLICE><<<blocks, kSmallWaves * 64, 0, s>>>(
-            L.descs, L.ndesc, L.total_tasks, L.heads, blocks * kSmallWaves, tm);
+            L.descs, L.ndesc, L.total_tasks, L.heads, blocks * kSmallWaves, tm, L.cuckoo_rounds);
         TC_LAUNCH_CHECK();
     }
     if (L.total_med > 0) {
@@ -851,7 +972,8 @@ void launch_all(CountLaunch &L, int lds_max, hipStream_t s) {
         unsigned long long *tm = times_for(blocks);
         L.times_tier[1] = tm ? blocks : 0;
         k_count_wide<PER_NODE, IDX32, kMedWaves, kMedMax, kMedHashBits, 1, SLICE>
-            <<<blocks, kMedWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_med, L.heads + 1, lds_max, tm);
+            <<<blocks, kMedWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_med, L.heads + 1, lds_max, tm,
+                                               L.cuckoo_rounds);
         TC_LAUNCH_CHECK();
     }
     if (L.total_large > 0) {
@@ -862,7 +984,8 @@ void launch_all(CountLaunch &L, int lds_max, hipStream_t s) {
         unsigned long long *tm = times_for(blocks);
         L.times_tier[2] = tm ? blocks : 0;
         k_count_wide<PER_NODE, IDX32, kBigWaves, kLdsMax, kBigHashBits, 2, SLICE>
-            <<<blocks, kBigThreads, 0, s>>>(L.descs, L.ndesc, L.total_large, L.heads + 2, lds_max, tm);
+            <<<blocks, kBigThreads, 0, s>>>(L.descs, L.ndesc, L.total_large, L.heads + 2, lds_max, tm,
+                                            L.cuckoo_rounds);
         TC_LAUNCH_CHECK();
     }
     L.times_used = used;
@@ -916,6 +1039,13 @@ void count_launch(CountLaunch &L, hipStream_t s) {
         return e && e[0] == '1';
     }();
     const bool idx32 = !force64 && L.max_m < ((int64_t)1 << 29);
+    // TC_CUCKOO_ROUNDS=<r> replaces the eviction limit of the two-choice
+    // tables (testing: a small limit sends many lists to the linear fallback)
+    static const int env_rounds = [] {
+        const char *e = std::getenv("TC_CUCKOO_ROUNDS");
+        return e && e[0] ? std::atoi(e) : -1;
+    }();
+    if (L.cuckoo_rounds > 0 && env_rounds >= 0) L.cuckoo_rounds = env_rounds;
     if (L.slice) {
         // slices are sized below 2^29 entries
         if (L.max_m >= ((int64_t)1 << 29)) throw Error(TC_ERR_TOO_LARGE, "slice of 2^29 or more entries");

@@ -176,7 +176,8 @@ void build_partitioned(const int32_t *src, const int32_t *dst, bool on_device, c
 // Counts a partitioned graph slice by slice; totals (1 entry) and tv (N
 // entries, degree-order labels, may be NULL) are device arrays, zeroed here.
 // search: the one-wave intersection choice of the descriptors (CountDesc).
-void count_partitioned(Partitioned &pg, const BuildParams &bp, int32_t lds_max, int32_t search, Allocator &al,
+void count_partitioned(Partitioned &pg, const BuildParams &bp, int32_t lds_max, int32_t search,
+                       int32_t cuckoo_rounds, Allocator &al,
                        hipStream_t s, int64_t *totals, int64_t *tv, uint32_t *heads);
 
 // count.hip --------------------------------------------------------------
@@ -213,6 +214,10 @@ struct CountDesc {
     int32_t search_ratio;
 };
 
+// Moves a two-choice insertion may make before the list falls back to linear
+// probing.
+constexpr int32_t kCuckooRounds = 96;
+
 struct CountLaunch {
     const CountDesc *descs;  // device array
     int32_t ndesc;
@@ -223,6 +228,7 @@ struct CountLaunch {
     int64_t max_m;    // largest adjacency (entries of col) among the descriptors
     int32_t workers;  // persistent waves for the small-list kernel
     int32_t lds_max;     // longest list kept in LDS by the workgroup kernels
+    int32_t cuckoo_rounds;  // two-choice table eviction limit; 0 = linear probing
     bool per_node;
     bool slice;  // descriptors are slice launches (32-bit row addressing)
     // optional per-worker (start, finish) timestamps, wall-clock ticks: small-list

@@ -627,7 +627,8 @@ void build_partitioned(const int32_t *src, const int32_t *dst, bool on_device, c
     out.batch.push_back(R);
 }
 
-void count_partitioned(Partitioned &pg, const BuildParams &bp, int32_t lds_max, int32_t search, Allocator &al,
+void count_partitioned(Partitioned &pg, const BuildParams &bp, int32_t lds_max, int32_t search,
+                       int32_t cuckoo_rounds, Allocator &al,
                        hipStream_t s, int64_t *totals, int64_t *tv, uint32_t *heads) {
     fill_zero(totals, 8, s);
     if (tv) fill_zero(tv, (size_t)std::max<int64_t>(pg.N, 1) * 8, s);
@@ -716,6 +717,7 @@ void count_partitioned(Partitioned &pg, const BuildParams &bp, int32_t lds_max, 
             L.heads = heads;
             L.workers = bp.workers;
             L.lds_max = lds_max;
+            L.cuckoo_rounds = cuckoo_rounds;
             L.per_node = tv != nullptr;
             L.slice = true;
             count_launch(L, s);
