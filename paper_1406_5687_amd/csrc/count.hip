@@ -225,7 +225,8 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
         int32_t w[kWin];
         bool ok[kWin];
         int acc = 0;
-        if (uniform32(P[cur + 1]) >= e0 + kStep) {
+        const bool one_row = uniform32(P[cur + 1]) >= e0 + kStep;
+        if (one_row) {
             // no row starts inside the step: every id lies in row cur
             const idx_t<IDX32> b = base[cur];
 #pragma unroll
@@ -267,6 +268,7 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
         if (IN_LDS) {
             uint32_t sl[kWin];
             bool hit[kWin];
+            uint32_t sh = 0;  // hits of the step (scalar)
             if (CUCKOO) {
                 // two-choice table: an id is in one of its two slots or absent
                 uint32_t s2[kWin];
@@ -286,7 +288,7 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
                     hit[q] = ok[q] & (first | second);
                     sl[q] = first ? sl[q] : s2[q];
                     // ballots taken from the compares themselves (kept in scalar masks)
-                    whits += (uint32_t)popc64(__ballot(ok[q] & first) | __ballot(ok[q] & second));
+                    sh += (uint32_t)popc64(__ballot(ok[q] & first) | __ballot(ok[q] & second));
                 }
             } else {
                 int32_t k[kWin];
@@ -310,10 +312,24 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
 #pragma unroll
                 for (int q = 0; q < kWin; ++q) {
                     hit[q] = ok[q] && k[q] == w[q];
-                    whits += (uint32_t)popc64(__ballot(hit[q]));
+                    sh += (uint32_t)popc64(__ballot(hit[q]));
                 }
             }
-            if (PER_NODE && GATHER) {
+            whits += sh;
+            // Per-node counts: each hit adds one to the position of its id in
+            // the list and one to the position of its row's target.  In the
+            // workgroup kernels (long rows) a step that lies in one row adds
+            // the target's share once; in the one-wave kernel such steps are
+            // rarer and the extra branch did not pay.
+            if (PER_NODE && GATHER && one_row) {
+                int kw[kWin];
+#pragma unroll
+                for (int q = 0; q < kWin; ++q) kw[q] = pos[sl[q]];
+#pragma unroll
+                for (int q = 0; q < kWin; ++q)
+                    if (hit[q]) atomicAdd(&cnt[kw[q]], 1);
+                if (lane == 0 && sh) atomicAdd(&cnt[tpos[cur]], (int)sh);
+            } else if (PER_NODE && GATHER) {
                 // slots and rows are valid in every lane
                 int kw[kWin], kt[kWin];
 #pragma unroll
