@@ -113,7 +113,7 @@ typedef struct {
                              searched.  Same results either way.  Set at build or reschedule
                              time; a count call with a non-zero intersect or search_ratio uses
                              its own for that call */
-    int32_t search_ratio; /* R of TC_INTERSECT_AUTO, 1 .. 2^20; 0 = automatic (32) */
+    int32_t search_ratio; /* R of TC_INTERSECT_AUTO, 1 .. 2^20; 0 = automatic (64) */
     int32_t hash;         /* the table of N_v in on-chip memory that each entry of N_u is looked up
                              in (Fig. 1: the test w in S):
                              TC_HASH_AUTO: two-choice (cuckoo) table, every lookup two reads; a

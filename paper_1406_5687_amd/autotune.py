@@ -64,7 +64,7 @@ def intersections(base: Params) -> list:
     return out
 
 
-SEARCH_RATIOS = (8, 16, 64, 128)
+SEARCH_RATIOS = (16, 32, 128, 256)
 LDS_CAPS = (768, 1024, 1536)
 
 

@@ -19,7 +19,7 @@ struct tc_graph {
     int32_t small_max = 128;
     int32_t lds_max = 1920;  // as tc::max_lds_list(); set at build
     int32_t cost_fn = TC_COST_PRIOR;
-    int32_t search = 32;  // one-wave lists: search ratio of the descriptors (-1 every row, 0 none)
+    int32_t search = 64;  // one-wave lists: search ratio of the descriptors (-1 every row, 0 none)
     int32_t hash = TC_HASH_AUTO;  // LDS table of the lists: two-choice or linear probing
     // persistent count scratch: queue heads, totals, per-node accumulators
     tc::DevBuf<uint32_t> heads;
@@ -109,7 +109,7 @@ void check_options(const tc_options *opt) {
         throw tc::Error(TC_ERR_INVALID_ARG, "unknown hash table kind");
 }
 
-constexpr int32_t kDefaultSearchRatio = 32;
+constexpr int32_t kDefaultSearchRatio = 64;
 
 // Descriptor encoding of the intersection choice: -1 = search every row,
 // 0 = walk every row, R > 0 = search rows longer than R times their candidates.

@@ -69,6 +69,9 @@ constexpr int kBigHashBits = 12;  // load factor <= 1/2
 constexpr int kBigWaves = 8;
 constexpr int kBigThreads = kBigWaves * 64;
 
+// empty LDS table slot (ids are at most 2^31 - 2; padding lanes carry -1)
+constexpr int32_t kEmpty = 0x7FFFFFFF;
+
 constexpr int kWin = 4;           // 64-id windows walked per step
 constexpr int kStep = 64 * kWin;  // ids per step
 // flag bytes: position p of a step is byte (p % 64) * 4 + p / 64, so lane l
@@ -96,7 +99,7 @@ __device__ __forceinline__ bool cuckoo_place(int32_t *key, int32_t x, int rounds
     uint32_t sl = hash_slot(x, HBITS);
     for (int r = 0; r < rounds; ++r) {
         const int32_t old = atomicExch(&key[sl], x);
-        if (old == -1) return true;
+        if (old == kEmpty) return true;
         x = old;
         const uint32_t s1 = hash_slot(x, HBITS);
         sl = s1 == sl ? hash_slot2(x, HBITS) : s1;
@@ -196,10 +199,8 @@ using idx_t = typename std::conditional<IDX32, int32_t, int64_t>::type;
 //   otherwise by binary search in the sorted list col[rs .. rs+a) (huge lists).
 // The return value is the wave's hits spread over its lanes (sum over lanes).
 // Per-node counts go to LDS counters by list position, or (huge lists) to tv.
-// GATHER: the list positions of a step's hits are read for all windows before
-// any counter is updated (one LDS wait per step); otherwise window by window,
-// which is faster where hits are sparse (the one-wave kernel's short lists).
-template <int HBITS, bool PER_NODE, bool IN_LDS, bool CUCKOO, bool IDX32, bool GATHER, class PosT>
+// ROWSUM: a step inside one row adds its target's per-node share at once.
+template <int HBITS, bool PER_NODE, bool IN_LDS, bool CUCKOO, bool IDX32, bool ROWSUM, class PosT>
 __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *pos, const int32_t *P,
                                                const idx_t<IDX32> *base, const PosT *tpos, int32_t *cnt,
                                                uint8_t *flag, const ColReader<IDX32> &rd,
@@ -273,22 +274,36 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
                 // two-choice table: an id is in one of its two slots or absent
                 uint32_t s2[kWin];
                 int32_t k1[kWin], k2[kWin];
+                // An id whose first slot is empty is absent: every key that
+                // ever took a slot keeps it occupied, and a key sits in its
+                // second slot only after its first was taken.  Lanes that need
+                // no second read all read slot 0 (one broadcast), so the second
+                // read touches few banks.
+                bool first[kWin], need[kWin];
 #pragma unroll
                 for (int q = 0; q < kWin; ++q) {
                     const uint32_t p = __umul24((uint32_t)w[q], 0x9E3779u);
                     sl[q] = p >> (32 - HBITS);
                     s2[q] = (p >> (32 - 2 * HBITS)) & kMask;
                     k1[q] = key[sl[q]];
-                    k2[q] = key[s2[q]];
                 }
 #pragma unroll
                 for (int q = 0; q < kWin; ++q) {
-                    // both reads are made; no short-circuit
-                    const bool first = k1[q] == w[q], second = k2[q] == w[q];
-                    hit[q] = ok[q] & (first | second);
-                    sl[q] = first ? sl[q] : s2[q];
-                    // ballots taken from the compares themselves (kept in scalar masks)
-                    sh += (uint32_t)popc64(__ballot(ok[q] & first) | __ballot(ok[q] & second));
+                    first[q] = k1[q] == w[q];
+                    need[q] = !first[q] & (k1[q] != kEmpty);
+                    k2[q] = key[need[q] ? s2[q] : 0u];
+                }
+#pragma unroll
+                for (int q = 0; q < kWin; ++q) {
+                    const bool c2 = k2[q] == w[q];
+                    hit[q] = ok[q] & (first[q] | (need[q] & c2));
+                    sl[q] = first[q] ? sl[q] : s2[q];
+                    // the step's hits from ballots of the compares themselves
+                    // (scalar masks; a ballot of a combined condition is not)
+                    const uint64_t b1 = __ballot(first[q]);
+                    uint64_t bh = b1 | (__ballot(k1[q] != kEmpty) & ~b1 & __ballot(c2));
+                    if (!FULL) bh &= __ballot(ok[q]);
+                    sh += (uint32_t)popc64(bh);
                 }
             } else {
                 int32_t k[kWin];
@@ -299,11 +314,11 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
                 }
                 bool need = false;
 #pragma unroll
-                for (int q = 0; q < kWin; ++q) need = need || (k[q] != w[q] && k[q] != -1);
+                for (int q = 0; q < kWin; ++q) need = need || (k[q] != w[q] && k[q] != kEmpty);
                 if (__ballot(need)) {
 #pragma unroll
                     for (int q = 0; q < kWin; ++q) {
-                        while (k[q] != w[q] && k[q] != -1) {  // collision chain
+                        while (k[q] != w[q] && k[q] != kEmpty) {  // collision chain
                             sl[q] = (sl[q] + 1) & kMask;
                             k[q] = key[sl[q]];
                         }
@@ -317,33 +332,16 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
             }
             whits += sh;
             // Per-node counts: each hit adds one to the position of its id in
-            // the list and one to the position of its row's target.  In the
-            // workgroup kernels (long rows) a step that lies in one row adds
-            // the target's share once; in the one-wave kernel such steps are
-            // rarer and the extra branch did not pay.
-            if (PER_NODE && GATHER && one_row) {
-                int kw[kWin];
-#pragma unroll
-                for (int q = 0; q < kWin; ++q) kw[q] = pos[sl[q]];
+            // the list and one to the position of its row's target; positions
+            // are read by the hit lanes only.  In the workgroup kernels (long
+            // rows) a step that lies in one row adds the target's share once;
+            // in the one-wave kernel such steps are rarer and the extra branch
+            // did not pay.
+            if (PER_NODE && ROWSUM && one_row) {
 #pragma unroll
                 for (int q = 0; q < kWin; ++q)
-                    if (hit[q]) atomicAdd(&cnt[kw[q]], 1);
+                    if (hit[q]) atomicAdd(&cnt[pos[sl[q]]], 1);
                 if (lane == 0 && sh) atomicAdd(&cnt[tpos[cur]], (int)sh);
-            } else if (PER_NODE && GATHER) {
-                // slots and rows are valid in every lane
-                int kw[kWin], kt[kWin];
-#pragma unroll
-                for (int q = 0; q < kWin; ++q) {
-                    kw[q] = pos[sl[q]];
-                    kt[q] = tpos[seg[q]];
-                }
-#pragma unroll
-                for (int q = 0; q < kWin; ++q) {
-                    if (hit[q]) {
-                        atomicAdd(&cnt[kw[q]], 1);
-                        atomicAdd(&cnt[kt[q]], 1);
-                    }
-                }
             } else if (PER_NODE) {
 #pragma unroll
                 for (int q = 0; q < kWin; ++q) {
@@ -505,20 +503,20 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
         } else {
             // a key found no place: empty the table and probe linearly instead
             int4 *kv = reinterpret_cast<int4 *>(S.key);
-            kv[lane] = make_int4(-1, -1, -1, -1);
-            kv[64 + lane] = make_int4(-1, -1, -1, -1);
+            kv[lane] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
+            kv[64 + lane] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
             wave_lds_sync();
         }
     }
     if (!cuckoo) {
         if (h0) {
             uint32_t sl = hash_slot(x0, kSmallHashBits);
-            while (atomicCAS(&S.key[sl], -1, x0) != -1) sl = (sl + 1) & (kSmallHash - 1);
+            while (atomicCAS(&S.key[sl], kEmpty, x0) != kEmpty) sl = (sl + 1) & (kSmallHash - 1);
             if (PER_NODE) S.pos[sl] = (uint8_t)lane;
         }
         if (h1) {
             uint32_t sl = hash_slot(x1, kSmallHashBits);
-            while (atomicCAS(&S.key[sl], -1, x1) != -1) sl = (sl + 1) & (kSmallHash - 1);
+            while (atomicCAS(&S.key[sl], kEmpty, x1) != kEmpty) sl = (sl + 1) & (kSmallHash - 1);
             if (PER_NODE) S.pos[sl] = (uint8_t)(64 + lane);
         }
     }
@@ -593,8 +591,8 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     // empty the whole table (two 16-byte stores per lane)
     static_assert(kSmallHash == 64 * 8, "table clear assumes 8 slots per lane");
     int4 *kv = reinterpret_cast<int4 *>(S.key);
-    kv[lane] = make_int4(-1, -1, -1, -1);
-    kv[64 + lane] = make_int4(-1, -1, -1, -1);
+    kv[lane] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
+    kv[64 + lane] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
     wave_lds_sync();
     return (uint64_t)hits;
 }
@@ -608,7 +606,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
     const int64_t me = (int64_t)blockIdx.x * kSmallWaves + wave;
     if (times && lane == 0) times[2 * me] = wall_clock64();
     SmallLds<IDX32> &S = lds[wave];
-    for (int i = lane; i < kSmallHash; i += 64) S.key[i] = -1;
+    for (int i = lane; i < kSmallHash; i += 64) S.key[i] = kEmpty;
     for (int i = lane; i < kSmallMax; i += 64) S.cnt[i] = 0;
     for (int i = lane; i < kFlagBytes; i += 64) S.flag[i] = 0;
     wave_lds_sync();
@@ -802,7 +800,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
     __shared__ WideLds<WAVES, LMAX, HBITS, IDX32> S;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     const int cap = min(lds_max, LMAX);
-    for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = -1;
+    for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = kEmpty;
     for (int i = threadIdx.x; i < LMAX; i += kThreadsW) S.cnt[i] = 0;
     for (int i = threadIdx.x; i < WAVES * kFlagBytes; i += kThreadsW) (&S.flag[0][0])[i] = 0;
     if (threadIdx.x == 0) {
@@ -858,13 +856,13 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
             } else {
                 if (rounds > 0) {
                     // a key found no place: empty the table and probe linearly instead
-                    for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = -1;
+                    for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = kEmpty;
                     __syncthreads();
                 }
                 for (int32_t k = threadIdx.x; k < a; k += kThreadsW) {
                     const int32_t x = col[rs + k];
                     uint32_t sl = hash_slot(x, HBITS);
-                    while (atomicCAS(&S.key[sl], -1, x) != -1) sl = (sl + 1) & (kHash - 1);
+                    while (atomicCAS(&S.key[sl], kEmpty, x) != kEmpty) sl = (sl + 1) & (kHash - 1);
                     if (PER_NODE) S.pos[sl] = (int16_t)k;
                 }
             }
@@ -882,7 +880,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                     }
                 }
             }
-            for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = -1;
+            for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = kEmpty;
         } else {
             for (int32_t i0 = 0; i0 < te; i0 += cap) {
                 const int32_t i1 = min(te, i0 + cap);

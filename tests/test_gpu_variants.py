@@ -46,7 +46,7 @@ def test_variants_equal_oracle(tc, name, g):
             assert tot[0] == T_ref, kw
             np.testing.assert_array_equal(tv, tv_ref)
             assert h.count_total()[0] == T_ref
-            want = {1: 0, 2: -1}.get(kw["intersect"], kw.get("search_ratio", 0) or 32)
+            want = {1: 0, 2: -1}.get(kw["intersect"], kw.get("search_ratio", 0) or 64)
             assert h.info()["search_ratio"] == want
 
 
