@@ -17,6 +17,7 @@
 //   6. costs and tasks     -- f per node (Sections IV-B, IV-F, V-A), prefix sums,
 //                             Eq. (1)/(2) targets, one binary search per task boundary
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 
@@ -809,6 +810,8 @@ __global__ __launch_bounds__(kOrientTileThreads) void k_orient_pairs_hist(const 
 constexpr int kTinyRow = 8;
 constexpr int kShortRow = 64;
 constexpr int kMidRow = 256;
+constexpr int kLdsRowMid = 2048;    // long rows up to this length: one wave each, in registers
+constexpr int kLdsRowMax = 16384;   // up to this length: 1024-thread workgroups, 64 KB of LDS
 
 __device__ __forceinline__ void cswap(int32_t &a, int32_t &b) {
     const int32_t lo = min(a, b), hi = max(a, b);
@@ -1069,15 +1072,19 @@ __global__ void k_prior_total(const int64_t *__restrict__ off, const int32_t *__
     }
 }
 
+// Entries of each long row left to the radix sort: rows of up to lds_max
+// entries are sorted in LDS (k_long_sort) and count 0 here.
 __global__ void k_long_lengths(const int64_t *__restrict__ off, const int32_t *__restrict__ long_rows, int64_t L,
-                               int64_t *__restrict__ len) {
+                               int64_t lds_max, int64_t *__restrict__ len) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t r = long_rows[i];
-        len[i] = off[r + 1] - off[r];
+        const int64_t a = off[r + 1] - off[r];
+        len[i] = a <= lds_max ? 0 : a;
     }
 }
 
-// keys (i << gb) | t of the entries of long row i, from epos[i] on (one wave per row)
+// keys (i << gb) | t of the entries of long row i, from epos[i] on (one wave
+// per row); rows with no entries left to the radix sort are skipped
 __global__ void k_long_keys(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
                             const int32_t *__restrict__ long_rows, const int64_t *__restrict__ epos, int64_t L, int gb,
                             uint64_t *__restrict__ keys) {
@@ -1085,9 +1092,122 @@ __global__ void k_long_keys(const int64_t *__restrict__ off, const int32_t *__re
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t i = wave; i < L; i += nwaves) {
-        const int32_t r = long_rows[i];
-        const int64_t r0 = off[r], a = off[r + 1] - r0, e = epos[i];
+        const int64_t e = epos[i], a = epos[i + 1] - e;
+        if (a == 0) continue;
+        const int64_t r0 = off[long_rows[i]];
         for (int64_t p = lane; p < a; p += 64) keys[e + p] = ((uint64_t)i << gb) | (uint64_t)(uint32_t)col[r0 + p];
+    }
+}
+
+// Long rows of up to 64 E entries, one wave per row: lane l holds entries
+// l E .. l E + E - 1 in registers (padded with INT32_MAX) and the wave runs a
+// bitonic network over all 64 E of them, exchanging across lanes by shuffles
+// for distances of E or more; equal neighbours after the sort are repeats.
+template <int E>
+__device__ __forceinline__ void wave_sort_long(int32_t *__restrict__ col, int64_t r0, int32_t a, int lane,
+                                               unsigned int *__restrict__ dup) {
+    constexpr int N = 64 * E;
+    int32_t v[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int i = lane * E + j;
+        v[j] = i < a ? col[r0 + i] : INT32_MAX;
+    }
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int d = k >> 1; d > 0; d >>= 1) {
+            if (d >= E) {
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    const int i = lane * E + j;
+                    const int32_t y = __shfl_xor(v[j], d / E, 64);
+                    const bool up = (i & k) == 0, lower = (i & d) == 0;
+                    v[j] = (lower == up) ? min(v[j], y) : max(v[j], y);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < E; ++j) {
+                    if (j & d) continue;
+                    const int p = j | d;
+                    const bool up = ((lane * E + j) & k) == 0;
+                    const int32_t lo = min(v[j], v[p]), hi = max(v[j], v[p]);
+                    v[j] = up ? lo : hi;
+                    v[p] = up ? hi : lo;
+                }
+            }
+        }
+    }
+    bool rep = false;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+        const int i = lane * E + j;
+        if (i < a) col[r0 + i] = v[j];
+        if (j + 1 < E) rep |= i + 1 < a && v[j] == v[j + 1];
+    }
+    const int32_t nx = __shfl_down(v[0], 1, 64);
+    rep |= lane < 63 && lane * E + E < a && v[E - 1] == nx;
+    note_repeat(rep, dup);
+}
+
+// Long rows of (32 E, min(hi, 64 E)] entries, one wave per row (one launch per
+// E, so that each holds only the registers its rows need).
+template <int E>
+__global__ __launch_bounds__(kThreads) void k_long_sort_wave(const int64_t *__restrict__ off, int32_t *__restrict__ col,
+                                                             const int32_t *__restrict__ long_rows, int64_t L,
+                                                             int32_t hi, unsigned int *__restrict__ dup) {
+    const int lane = __lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = wave; i < L; i += nwaves) {
+        const int32_t r = long_rows[i];
+        const int64_t r0 = off[r];
+        const int32_t a = (int32_t)(off[r + 1] - r0);
+        if (a <= 32 * E || a > hi || a > 64 * E) continue;
+        wave_sort_long<E>(col, r0, a, lane, dup);
+    }
+}
+
+// Long rows of (lo, NMAX] entries, one workgroup per row: the row is loaded
+// into LDS, padded to a power of two with INT32_MAX, sorted by a bitonic
+// network (one barrier per stage) and written back; equal neighbours after
+// the sort are repeated entries.
+template <int THREADS, int NMAX>
+__global__ __launch_bounds__(THREADS) void k_long_sort(const int64_t *__restrict__ off, int32_t *__restrict__ col,
+                                                       const int32_t *__restrict__ long_rows, int64_t L, int32_t lo,
+                                                       int32_t hi, unsigned int *__restrict__ dup) {
+    __shared__ int32_t v[NMAX];
+    const int tid = threadIdx.x;
+    for (int64_t i = blockIdx.x; i < L; i += gridDim.x) {
+        const int32_t r = long_rows[i];
+        const int64_t r0 = off[r];
+        const int32_t a = (int32_t)(off[r + 1] - r0);
+        if (a <= lo || a > hi) continue;  // the same in every thread of the block
+        int n = 64;
+        while (n < a) n <<= 1;
+        for (int p = tid; p < n; p += THREADS) v[p] = p < a ? col[r0 + p] : INT32_MAX;
+        __syncthreads();
+        for (int k = 2; k <= n; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = tid; t < (n >> 1); t += THREADS) {
+                    const int x = ((t & ~(j - 1)) << 1) | (t & (j - 1)), y = x + j;
+                    const int32_t vx = v[x], vy = v[y];
+                    if ((vx > vy) == ((x & k) == 0)) {
+                        v[x] = vy;
+                        v[y] = vx;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        bool rep = false;
+        for (int p = tid; p < a; p += THREADS) {
+            const int32_t x = v[p];
+            col[r0 + p] = x;
+            rep |= p > 0 && v[p - 1] == x;
+        }
+        note_repeat(rep, dup);
+        __syncthreads();
     }
 }
 
@@ -1440,13 +1560,45 @@ void sort_rows_finish(const int64_t *off, int32_t *col, int gb, uint64_t *ka, ui
                       unsigned int *dup, const LongRows &lr, unsigned int L, Allocator &tmp, hipStream_t s) {
     if (L == 0) return;
     const int32_t *long_rows = lr.rows.p;
+    // rows of up to kLdsRowMax entries are sorted in LDS, longer ones (at most
+    // sqrt(2m) entries in an oriented adjacency: only above ~1.3e8 edges) by
+    // the radix sort of their (row, entry) keys; TC_LONG_ROW_LDS=<k> lowers
+    // the LDS limit (testing)
+    static const int32_t lds_rows = [] {
+        const char *e = std::getenv("TC_LONG_ROW_LDS");
+        return e && e[0] ? std::max(0, std::min(std::atoi(e), kLdsRowMax)) : kLdsRowMax;
+    }();
+    const int64_t sort_blocks = std::min<int64_t>(L, (int64_t)device_cu_count() * 16);
+    if (lds_rows > kMidRow) {
+        // kMidRow = 256 = 32 * 8: the three launches cover (256, 2048]
+        static_assert(kMidRow == 32 * 8 && kLdsRowMid == 64 * 32, "long-row classes");
+        const int32_t hi = std::min(lds_rows, kLdsRowMid);
+        const int64_t waves = std::min<int64_t>(L, (int64_t)device_cu_count() * 32);
+        const unsigned blocks = (unsigned)ceil_div(waves * 64, kThreads);
+        k_long_sort_wave<8><<<blocks, kThreads, 0, s>>>(off, col, long_rows, L, hi, dup);
+        TC_LAUNCH_CHECK();
+        if (hi > 512) {
+            k_long_sort_wave<16><<<blocks, kThreads, 0, s>>>(off, col, long_rows, L, hi, dup);
+            TC_LAUNCH_CHECK();
+        }
+        if (hi > 1024) {
+            k_long_sort_wave<32><<<blocks, kThreads, 0, s>>>(off, col, long_rows, L, hi, dup);
+            TC_LAUNCH_CHECK();
+        }
+    }
+    if (lds_rows > kLdsRowMid) {
+        k_long_sort<1024, kLdsRowMax><<<(unsigned)sort_blocks, 1024, 0, s>>>(off, col, long_rows, L, kLdsRowMid,
+                                                                             lds_rows, dup);
+        TC_LAUNCH_CHECK();
+    }
     DevBuf<int64_t> len(tmp, L), epos(tmp, (size_t)L + 1);
-    k_long_lengths<<<grid_for(L), kThreads, 0, s>>>(off, long_rows, L, len.p);
+    k_long_lengths<<<grid_for(L), kThreads, 0, s>>>(off, long_rows, L, std::max(lds_rows, kMidRow), len.p);
     TC_LAUNCH_CHECK();
     exclusive_scan(len.p, epos.p, L, true, tmp, s);
     int64_t E = 0;
     d2h(&E, epos.p + L, 1, s);
     TC_HIP(hipStreamSynchronize(s));
+    if (E == 0) return;
     if (E > cap) throw Error(TC_ERR_DEVICE, "long-row scratch smaller than the long rows");
     const int64_t lw = std::min<int64_t>(L, (int64_t)device_cu_count() * 64);
     k_long_keys<<<(unsigned)ceil_div(lw * 64, kThreads), kThreads, 0, s>>>(off, col, long_rows, epos.p, L, gb, ka);
