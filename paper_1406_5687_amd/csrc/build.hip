@@ -1030,10 +1030,43 @@ __global__ __launch_bounds__(kThreads) void k_sort_rows(const int64_t *__restric
 // before any cost is computed per row.  Over all rows the PRIOR costs add up
 // to sum_v dhat_v * d_v (pair (v, t) contributes dhat_v to f(v) and dhat_t
 // to f(v); dhat_t is counted once for each of t's d_t - dhat_t in-pairs);
-// each longer row's own cost is subtracted, one wave per row.
-__global__ void k_prior_total(const int64_t *__restrict__ off, const int32_t *__restrict__ col,
-                              const int32_t *__restrict__ deg, int64_t N, int small,
+// acc[0] gets that sum, acc[1] the entries of the longer rows, whose own
+// costs k_prior_wide then subtracts.
+__global__ void k_prior_total(const int64_t *__restrict__ off, const int32_t *__restrict__ deg, int64_t N, int small,
                               unsigned long long *__restrict__ acc) {
+    int64_t part = 0, wide = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = off[r + 1] - off[r];
+        part += a * (int64_t)deg[r];
+        wide += a > small ? a : 0;
+    }
+    // one add per workgroup: adds to one address are serialised
+    __shared__ int64_t wpart[2][kThreads / 64];
+    part = wave_sum(part);
+    wide = wave_sum(wide);
+    if (__lane_id() == 0) {
+        wpart[0][threadIdx.x >> 6] = part;
+        wpart[1][threadIdx.x >> 6] = wide;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0, w = 0;
+        for (int i = 0; i < kThreads / 64; ++i) {
+            t += wpart[0][i];
+            w += wpart[1][i];
+        }
+        atomicAdd(acc, (unsigned long long)t);
+        atomicAdd(acc + 1, (unsigned long long)w);
+    }
+}
+
+// Subtracts the PRIOR cost of each row longer than small from acc[0], one
+// wave per row, unless those rows hold more than `limit` entries in all
+// (acc[1]): then the early total is not made (the gathers would cost more
+// than they save) and acc[0] is left as it is.
+__global__ void k_prior_wide(const int64_t *__restrict__ off, const int32_t *__restrict__ col, int64_t N, int small,
+                             int64_t limit, unsigned long long *__restrict__ acc) {
+    if ((int64_t)acc[1] > limit) return;
     const int lane = __lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -1044,7 +1077,6 @@ __global__ void k_prior_total(const int64_t *__restrict__ off, const int32_t *__
         if (r < N) {
             r0 = off[r];
             a = off[r + 1] - r0;
-            part += a * (int64_t)deg[r];
         }
         uint64_t wide = __ballot(a > small);
         while (wide) {
@@ -1073,7 +1105,7 @@ __global__ void k_prior_total(const int64_t *__restrict__ off, const int32_t *__
 }
 
 // Entries of each long row left to the radix sort: rows of up to lds_max
-// entries are sorted in LDS (k_long_sort) and count 0 here.
+// entries are sorted by k_long_sort_wave / k_long_sort and count 0 here.
 __global__ void k_long_lengths(const int64_t *__restrict__ off, const int32_t *__restrict__ long_rows, int64_t L,
                                int64_t lds_max, int64_t *__restrict__ len) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L; i += (int64_t)gridDim.x * blockDim.x) {
@@ -1511,7 +1543,10 @@ struct PinnedStage {
     }
 };
 thread_local PinnedStage t_stage;
-thread_local PinnedStage t_total;  // the early cost total
+thread_local PinnedStage t_total;  // the early cost total and the entries of the wide rows
+// Largest number of entries in rows longer than small_max for which the early
+// cost total is made (about 0.1 ms of gathers on MI355X).
+constexpr int64_t kEarlyWide = (int64_t)8 << 20;
 thread_local PinnedStage t_words;  // small results read back at a synchronisation
 thread_local PinnedStage t_bases;  // node and edge offsets of the packed graphs
 
@@ -1817,17 +1852,21 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
         // known before it (k_prior_total), so the host computes the task
         // targets while the device sorts.
         DevBuf<int64_t> f(tmp, (size_t)N);
-        DevBuf<unsigned long long> acc(tmp, 1);
-        fill_zero(acc.p, 8, s);
+        DevBuf<unsigned long long> acc(tmp, 2);
+        fill_zero(acc.p, 16, s);
         const int64_t tw = std::min<int64_t>(ceil_div(N, 64), (int64_t)device_cu_count() * 8);  // waves
-        k_prior_total<<<(unsigned)ceil_div(tw * 64, kThreads), kThreads, 0, s>>>(out.off.p, out.col.p, out.deg.p,
-                                                                                  N, bp.small_max, acc.p);
+        // the early total is made when the rows longer than small_max hold at
+        // most kEarlyWide entries (their costs need a gather per entry)
+        k_prior_total<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, out.deg.p, N, bp.small_max, acc.p);
         TC_LAUNCH_CHECK();
+        k_prior_wide<<<(unsigned)ceil_div(tw * 64, kThreads), kThreads, 0, s>>>(out.off.p, out.col.p, N,
+                                                                                 bp.small_max, kEarlyWide, acc.p);
+        TC_LAUNCH_CHECK();
+        auto *htot = static_cast<unsigned long long *>(t_total.get(2 * sizeof(unsigned long long)));
         PresetTargets pre;
-        auto *htot = static_cast<unsigned long long *>(t_total.get(sizeof(unsigned long long)));
         EventGuard ev;
         if (htot) {
-            TC_HIP(hipMemcpyAsync(htot, acc.p, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+            TC_HIP(hipMemcpyAsync(htot, acc.p, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
             TC_HIP(hipEventCreateWithFlags(&ev.e, hipEventDisableTiming));
             TC_HIP(hipEventRecord(ev.e, s));
         }
@@ -1837,8 +1876,10 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
         sort_rows_begin(out.off.p, N, out.col.p, rowlen.p, f.p, dup, lr, tmp, s);
         if (htot) {  // host work that overlaps the row sort
             TC_HIP(hipEventSynchronize(ev.e));
-            pre.total = (int64_t)*htot;
-            pre.targets = schedule_targets(pre.total, bpr);
+            if ((int64_t)htot[1] <= kEarlyWide) {
+                pre.total = (int64_t)htot[0];
+                pre.targets = schedule_targets(pre.total, bpr);
+            }
         }
         // the task table is enqueued behind the row sort; the long-row count
         // and the repeat flag come back with the schedule's totals
