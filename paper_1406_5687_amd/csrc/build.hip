@@ -1857,7 +1857,9 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
         const int64_t tw = std::min<int64_t>(ceil_div(N, 64), (int64_t)device_cu_count() * 8);  // waves
         // the early total is made when the rows longer than small_max hold at
         // most kEarlyWide entries (their costs need a gather per entry)
-        k_prior_total<<<grid_for(N, 4), kThreads, 0, s>>>(out.off.p, out.deg.p, N, bp.small_max, acc.p);
+        // a few workgroups per CU: each adds its partial sums to the same two words
+        k_prior_total<<<std::min<unsigned>(grid_for(N, 4), (unsigned)device_cu_count() * 4), kThreads, 0, s>>>(
+            out.off.p, out.deg.p, N, bp.small_max, acc.p);
         TC_LAUNCH_CHECK();
         k_prior_wide<<<(unsigned)ceil_div(tw * 64, kThreads), kThreads, 0, s>>>(out.off.p, out.col.p, N,
                                                                                  bp.small_max, kEarlyWide, acc.p);
