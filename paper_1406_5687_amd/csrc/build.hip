@@ -1591,8 +1591,10 @@ void sort_rows_begin(const int64_t *off, int64_t N, int32_t *col, const int32_t 
 }
 
 // ka / kb: scratch of cap keys each.
+// max_row: the longest row (launches for longer classes are skipped).
 void sort_rows_finish(const int64_t *off, int32_t *col, int gb, uint64_t *ka, uint64_t *kb, int64_t cap,
-                      unsigned int *dup, const LongRows &lr, unsigned int L, Allocator &tmp, hipStream_t s) {
+                      unsigned int *dup, const LongRows &lr, unsigned int L, int32_t max_row, Allocator &tmp,
+                      hipStream_t s) {
     if (L == 0) return;
     const int32_t *long_rows = lr.rows.p;
     // rows of up to kLdsRowMax entries are sorted in LDS, longer ones (at most
@@ -1612,16 +1614,16 @@ void sort_rows_finish(const int64_t *off, int32_t *col, int gb, uint64_t *ka, ui
         const unsigned blocks = (unsigned)ceil_div(waves * 64, kThreads);
         k_long_sort_wave<8><<<blocks, kThreads, 0, s>>>(off, col, long_rows, L, hi, dup);
         TC_LAUNCH_CHECK();
-        if (hi > 512) {
+        if (hi > 512 && max_row > 512) {
             k_long_sort_wave<16><<<blocks, kThreads, 0, s>>>(off, col, long_rows, L, hi, dup);
             TC_LAUNCH_CHECK();
         }
-        if (hi > 1024) {
+        if (hi > 1024 && max_row > 1024) {
             k_long_sort_wave<32><<<blocks, kThreads, 0, s>>>(off, col, long_rows, L, hi, dup);
             TC_LAUNCH_CHECK();
         }
     }
-    if (lds_rows > kLdsRowMid) {
+    if (lds_rows > kLdsRowMid && max_row > kLdsRowMid) {
         k_long_sort<1024, kLdsRowMax><<<(unsigned)sort_blocks, 1024, 0, s>>>(off, col, long_rows, L, kLdsRowMid,
                                                                              lds_rows, dup);
         TC_LAUNCH_CHECK();
@@ -1646,13 +1648,13 @@ void sort_rows_finish(const int64_t *off, int32_t *col, int gb, uint64_t *ka, ui
 
 // Both parts with the long-row count read in between.
 void sort_rows(const int64_t *off, int64_t N, int32_t *col, int gb, uint64_t *ka, uint64_t *kb, int64_t cap,
-               unsigned int *dup, Allocator &tmp, hipStream_t s) {
+               unsigned int *dup, int32_t max_row, Allocator &tmp, hipStream_t s) {
     LongRows lr;
     sort_rows_begin(off, N, col, nullptr, nullptr, dup, lr, tmp, s);
     unsigned int L = 0;
     d2h(&L, lr.n.p, 1, s);
     TC_HIP(hipStreamSynchronize(s));
-    sort_rows_finish(off, col, gb, ka, kb, cap, dup, lr, L, tmp, s);
+    sort_rows_finish(off, col, gb, ka, kb, cap, dup, lr, L, max_row, tmp, s);
 }
 
 void build_into(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp, Allocator &al,
@@ -1894,10 +1896,10 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
             TC_HIP(hipStreamSynchronize(s));
             return !(simple && pb.host[1]);  // an edge given twice: take the canonical path
         }
-        sort_rows_finish(out.off.p, out.col.p, gb, ka.p, kb.p, M_in, dup, lr, L, tmp, s);
+        sort_rows_finish(out.off.p, out.col.p, gb, ka.p, kb.p, M_in, dup, lr, L, out.max_dhat, tmp, s);
     } else {
         schedule_into(pk, bp, al, tmp, s, out, okeys, gb);
-        if (M > 0) sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, dup, tmp, s);
+        if (M > 0) sort_rows(out.off.p, N, out.col.p, gb, ka.p, kb.p, M_in, dup, out.max_dhat, tmp, s);
     }
     if (simple && M > 0) {
         uint32_t hdup = 0;
