@@ -114,6 +114,14 @@ __device__ __forceinline__ uint32_t cuckoo_slot(const int32_t *key, int32_t x) {
     return key[s1] == x ? s1 : hash_slot2(x, HBITS);
 }
 
+// The slot that holds x in a linear-probing table (x must be in it).
+template <int HBITS>
+__device__ __forceinline__ uint32_t linear_slot(const int32_t *key, int32_t x) {
+    uint32_t sl = hash_slot(x, HBITS);
+    while (key[sl] != x) sl = (sl + 1) & ((1u << HBITS) - 1);
+    return sl;
+}
+
 // which = 0: tasks, 1: medium lists, 2: long lists
 __device__ __forceinline__ int find_desc(const CountDesc *__restrict__ d, int nd, int64_t c, int which) {
     int lo = 0, hi = nd - 1;  // largest h whose first index is <= c
@@ -199,8 +207,11 @@ using idx_t = typename std::conditional<IDX32, int32_t, int64_t>::type;
 //   otherwise by binary search in the sorted list col[rs .. rs+a) (huge lists).
 // The return value is the wave's hits spread over its lanes (sum over lanes).
 // Per-node counts go to LDS counters by list position, or (huge lists) to tv.
-// ROWSUM: a step inside one row adds its target's per-node share at once.
-template <int HBITS, bool PER_NODE, bool IN_LDS, bool CUCKOO, bool IDX32, bool ROWSUM, class PosT>
+// PN, how per-node counts are kept: 0 by list position (pos[slot]); 1 the
+// same, and a step inside one row adds its target's share at once; 2 by
+// table slot (tpos holds the slot of each row's target), with the one-row
+// share.
+template <int HBITS, bool PER_NODE, bool IN_LDS, bool CUCKOO, bool IDX32, int PN, class PosT>
 __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *pos, const int32_t *P,
                                                const idx_t<IDX32> *base, const PosT *tpos, int32_t *cnt,
                                                uint8_t *flag, const ColReader<IDX32> &rd,
@@ -331,22 +342,23 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
                 }
             }
             whits += sh;
-            // Per-node counts: each hit adds one to the position of its id in
-            // the list and one to the position of its row's target; positions
-            // are read by the hit lanes only.  In the workgroup kernels (long
+            // Per-node counts: each hit adds one to the count of its id and one
+            // to that of its row's target.  By table slot (PN 2) a hit's
+            // counter is at hand; by list position its position is read by
+            // the hit lanes only.  In the workgroup kernels (PN >= 1; long
             // rows) a step that lies in one row adds the target's share once;
             // in the one-wave kernel such steps are rarer and the extra branch
             // did not pay.
-            if (PER_NODE && ROWSUM && one_row) {
+            if (PER_NODE && PN >= 1 && one_row) {
 #pragma unroll
                 for (int q = 0; q < kWin; ++q)
-                    if (hit[q]) atomicAdd(&cnt[pos[sl[q]]], 1);
+                    if (hit[q]) atomicAdd(&cnt[PN == 2 ? (int)sl[q] : (int)pos[sl[q]]], 1);
                 if (lane == 0 && sh) atomicAdd(&cnt[tpos[cur]], (int)sh);
             } else if (PER_NODE) {
 #pragma unroll
                 for (int q = 0; q < kWin; ++q) {
                     if (hit[q]) {
-                        atomicAdd(&cnt[pos[sl[q]]], 1);
+                        atomicAdd(&cnt[PN == 2 ? (int)sl[q] : (int)pos[sl[q]]], 1);
                         atomicAdd(&cnt[tpos[seg[q]]], 1);
                     }
                 }
@@ -564,10 +576,10 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     uint32_t hits = npairs ? search_pairs<PER_NODE, IDX32>(S, rd, npairs, ns, a, x0, x1) : 0u;
     const int32_t e_end = ((total + kStep - 1) / kStep) * kStep;
     if (cuckoo)
-        hits += walk_steps<kSmallHashBits, PER_NODE, true, true, IDX32, false, uint8_t>(
+        hits += walk_steps<kSmallHashBits, PER_NODE, true, true, IDX32, 0, uint8_t>(
             S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag, rd, gcol, nt, total, 0, 0, e_end, 0, a, 0, tv);
     else
-        hits += walk_steps<kSmallHashBits, PER_NODE, true, false, IDX32, false, uint8_t>(
+        hits += walk_steps<kSmallHashBits, PER_NODE, true, false, IDX32, 0, uint8_t>(
             S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag, rd, gcol, nt, total, 0, 0, e_end, 0, a, 0, tv);
     if (PER_NODE) {
         const uint64_t hs = wave_sum((uint64_t)hits);
@@ -690,14 +702,17 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
 // compute unit), longer ones to 8-wave workgroups with a ~52 KB table (three
 // per compute unit; the kernel is held to 80 registers so that 24 waves fit).
 // Lists are handed out longest-rank first (roughly longest first).
-template <int WAVES, int LMAX, int HBITS, bool IDX32>
+// SLOTCNT: per-node counts by table slot (the 4-wave tier); otherwise by list
+// position (the 8-wave tier: by slot its LDS no longer fits three per CU).
+template <int WAVES, int LMAX, int HBITS, bool IDX32, bool SLOTCNT>
 struct WideLds {
+    static constexpr bool kSlotCnt = SLOTCNT;
     idx_t<IDX32> base[LMAX];
     int32_t key[1 << HBITS];
     int32_t P[LMAX + 1];
-    int32_t cnt[LMAX];
-    int16_t pos[1 << HBITS];
-    int16_t tpos[LMAX];
+    int32_t cnt[SLOTCNT ? (1 << HBITS) : LMAX];  // per-node counts
+    int16_t pos[SLOTCNT ? 1 : (1 << HBITS)];     // list position of each slot's id
+    int16_t tpos[LMAX];  // per target row: its target's slot (SLOTCNT, LDS lists) or list position
     alignas(4) uint8_t flag[WAVES][kFlagBytes];
     int32_t wsum[WAVES];
     int32_t wcnt[WAVES];
@@ -707,18 +722,20 @@ struct WideLds {
 };
 
 // Lays out the rows of targets i in [i0, i1) (positions in the source list
-// `col` from rs; target t has row t - row_lo of off) into P / base / tpos
-// (tpos relative to i0).  Returns (rows, total ids).
-template <int WAVES, bool IDX32, class L>
+// `col` from rs; target t has row t - row_lo of off) into P / base / tpos.
+// tpos: the target's slot in the LDS table (TABLE 1: two-choice, 2: linear
+// probing) or, with TABLE 0, its list position relative to i0.  Returns (rows,
+// total ids).
+template <int WAVES, int HBITS, bool IDX32, class L>
 __device__ __forceinline__ void wide_rows(L &S, gptr_t<const int32_t> col, gptr_t<const int64_t> off, int64_t rs,
-                                          int32_t i0, int32_t i1, int32_t row_lo, int64_t ebase, int32_t *nt_out,
-                                          int32_t *total_out) {
+                                          int32_t i0, int32_t i1, int32_t row_lo, int64_t ebase, int table,
+                                          int32_t *nt_out, int32_t *total_out) {
     constexpr int kThreadsW = WAVES * 64;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     int32_t carry_n = 0, carry_sum = 0;
     for (int32_t rb = i0; rb < i1; rb += kThreadsW) {
         const int32_t i = rb + (int32_t)threadIdx.x;
-        const int32_t t = col[rs + min(i, i1 - 1)] - row_lo;
+        const int32_t x = col[rs + min(i, i1 - 1)], t = x - row_lo;
         const int64_t r = off[t], re = off[t + 1];
         const int32_t b = i < i1 ? (int32_t)(re - r) : 0;
         const int32_t inc = wave_inclusive_sum(b);
@@ -744,7 +761,9 @@ __device__ __forceinline__ void wide_rows(L &S, gptr_t<const int32_t> col, gptr_
             const int32_t p = carry_sum + sb + inc - b;
             S.P[j] = p;
             S.base[j] = (idx_t<IDX32>)(r - ebase - (int64_t)p);
-            S.tpos[j] = (int16_t)(i - i0);
+            S.tpos[j] = (int16_t)(table == 1   ? cuckoo_slot<HBITS>(S.key, x)
+                                  : table == 2 ? linear_slot<HBITS>(S.key, x)
+                                               : (uint32_t)(i - i0));
         }
         carry_n += ct;
         carry_sum += st;
@@ -777,14 +796,14 @@ __device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &r
             hi = mid - 1;
     }
     if (in_lds && cuckoo)
-        return walk_steps<HBITS, PER_NODE, true, true, IDX32, true, int16_t>(
+        return walk_steps<HBITS, PER_NODE, true, true, IDX32, L::kSlotCnt ? 2 : 1, int16_t>(
             S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs,
             a, i0, tv);
     if (in_lds)
-        return walk_steps<HBITS, PER_NODE, true, false, IDX32, true, int16_t>(
+        return walk_steps<HBITS, PER_NODE, true, false, IDX32, L::kSlotCnt ? 2 : 1, int16_t>(
             S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs,
             a, i0, tv);
-    return walk_steps<HBITS, PER_NODE, false, false, IDX32, true, int16_t>(
+    return walk_steps<HBITS, PER_NODE, false, false, IDX32, 1, int16_t>(
         S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs, a,
         i0, tv);
 }
@@ -797,11 +816,12 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                                                            int rounds) {
     constexpr int kThreadsW = WAVES * 64;
     constexpr int kHash = 1 << HBITS;
-    __shared__ WideLds<WAVES, LMAX, HBITS, IDX32> S;
+    constexpr bool SLOTCNT = TIER == 1;
+    __shared__ WideLds<WAVES, LMAX, HBITS, IDX32, SLOTCNT> S;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     const int cap = min(lds_max, LMAX);
     for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = kEmpty;
-    for (int i = threadIdx.x; i < LMAX; i += kThreadsW) S.cnt[i] = 0;
+    for (int i = threadIdx.x; i < (int)(sizeof(S.cnt) / 4); i += kThreadsW) S.cnt[i] = 0;
     for (int i = threadIdx.x; i < WAVES * kFlagBytes; i += kThreadsW) (&S.flag[0][0])[i] = 0;
     if (threadIdx.x == 0) {
         S.item = blockIdx.x;
@@ -849,7 +869,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
             }
             const bool cuckoo = rounds > 0 && !S.homeless;
             if (cuckoo) {
-                if (PER_NODE) {
+                if (PER_NODE && !SLOTCNT) {
                     for (int32_t k = threadIdx.x; k < a; k += kThreadsW)
                         S.pos[cuckoo_slot<HBITS>(S.key, col[rs + k])] = (int16_t)k;
                 }
@@ -863,15 +883,17 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                     const int32_t x = col[rs + k];
                     uint32_t sl = hash_slot(x, HBITS);
                     while (atomicCAS(&S.key[sl], kEmpty, x) != kEmpty) sl = (sl + 1) & (kHash - 1);
-                    if (PER_NODE) S.pos[sl] = (int16_t)k;
+                    if (PER_NODE && !SLOTCNT) S.pos[sl] = (int16_t)k;
                 }
             }
             __syncthreads();
             int32_t nt, total;
-            wide_rows<WAVES, IDX32>(S, col, off, rs, 0, te, row_lo, ebase, &nt, &total);
+            wide_rows<WAVES, HBITS, IDX32>(S, col, off, rs, 0, te, row_lo, ebase, !SLOTCNT ? 0 : cuckoo ? 1 : 2, &nt,
+                                           &total);
             hits = wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, 0, nt, total, true, cuckoo);
             __syncthreads();
-            if (PER_NODE) {
+            // counts out (one atomic per non-zero counter), then the table emptied
+            if (PER_NODE && !SLOTCNT) {
                 for (int32_t k = threadIdx.x; k < a; k += kThreadsW) {
                     const int32_t c = S.cnt[k];
                     if (c) {
@@ -880,12 +902,21 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                     }
                 }
             }
-            for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = kEmpty;
+            for (int i = threadIdx.x; i < kHash; i += kThreadsW) {
+                if (PER_NODE && SLOTCNT) {
+                    const int32_t c = S.cnt[i];
+                    if (c) {
+                        add_u64(&tv[S.key[i]], (uint64_t)c);
+                        S.cnt[i] = 0;
+                    }
+                }
+                S.key[i] = kEmpty;
+            }
         } else {
             for (int32_t i0 = 0; i0 < te; i0 += cap) {
                 const int32_t i1 = min(te, i0 + cap);
                 int32_t nt, total;
-                wide_rows<WAVES, IDX32>(S, col, off, rs, i0, i1, row_lo, ebase, &nt, &total);
+                wide_rows<WAVES, HBITS, IDX32>(S, col, off, rs, i0, i1, row_lo, ebase, 0, &nt, &total);
                 hits += wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, i0, nt, total, false,
                                                                     false);
                 __syncthreads();
