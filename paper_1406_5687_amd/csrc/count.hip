@@ -154,6 +154,16 @@ __device__ __forceinline__ void add_u64(int64_t *p, uint64_t v) {
     atomicAdd((unsigned long long *)p, (unsigned long long)v);
 }
 
+// Per-node counter add: PN 3 packs two 16-bit counters per word (slot i in
+// half i & 1 of word i / 2; a slot's count stays below 2^16).
+template <int PN>
+__device__ __forceinline__ void cnt_add(int32_t *cnt, int i, int v) {
+    if (PN == 3)
+        atomicAdd(&cnt[i >> 1], v << ((i & 1) << 4));
+    else
+        atomicAdd(&cnt[i], v);
+}
+
 __device__ __forceinline__ int mbcnt64(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -207,10 +217,11 @@ using idx_t = typename std::conditional<IDX32, int32_t, int64_t>::type;
 //   otherwise by binary search in the sorted list col[rs .. rs+a) (huge lists).
 // The return value is the wave's hits spread over its lanes (sum over lanes).
 // Per-node counts go to LDS counters by list position, or (huge lists) to tv.
-// PN, how per-node counts are kept: 0 by list position (pos[slot]); 1 the
-// same, and a step inside one row adds its target's share at once; 2 by
-// table slot (tpos holds the slot of each row's target), with the one-row
-// share.
+// PN, how per-node counts are kept: 0 by list position (pos[slot]; the
+// one-wave kernel); 1 the same, and a step inside one row adds its target's
+// share at once; 2 by table slot (tpos holds the slot of each row's target),
+// with the one-row share (the 4-wave tier); 3 as 2 in 16-bit halves
+// (cnt_add; the 8-wave tier).
 template <int HBITS, bool PER_NODE, bool IN_LDS, bool CUCKOO, bool IDX32, int PN, class PosT>
 __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *pos, const int32_t *P,
                                                const idx_t<IDX32> *base, const PosT *tpos, int32_t *cnt,
@@ -352,14 +363,14 @@ __device__ __forceinline__ uint32_t walk_steps(const int32_t *key, const PosT *p
             if (PER_NODE && PN >= 1 && one_row) {
 #pragma unroll
                 for (int q = 0; q < kWin; ++q)
-                    if (hit[q]) atomicAdd(&cnt[PN == 2 ? (int)sl[q] : (int)pos[sl[q]]], 1);
-                if (lane == 0 && sh) atomicAdd(&cnt[tpos[cur]], (int)sh);
+                    if (hit[q]) cnt_add<PN>(cnt, PN >= 2 ? (int)sl[q] : (int)pos[sl[q]], 1);
+                if (lane == 0 && sh) cnt_add<PN>(cnt, tpos[cur], (int)sh);
             } else if (PER_NODE) {
 #pragma unroll
                 for (int q = 0; q < kWin; ++q) {
                     if (hit[q]) {
-                        atomicAdd(&cnt[PN == 2 ? (int)sl[q] : (int)pos[sl[q]]], 1);
-                        atomicAdd(&cnt[tpos[seg[q]]], 1);
+                        cnt_add<PN>(cnt, PN >= 2 ? (int)sl[q] : (int)pos[sl[q]], 1);
+                        cnt_add<PN>(cnt, tpos[seg[q]], 1);
                     }
                 }
             }
@@ -702,17 +713,16 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
 // compute unit), longer ones to 8-wave workgroups with a ~52 KB table (three
 // per compute unit; the kernel is held to 80 registers so that 24 waves fit).
 // Lists are handed out longest-rank first (roughly longest first).
-// SLOTCNT: per-node counts by table slot (the 4-wave tier); otherwise by list
-// position (the 8-wave tier: by slot its LDS no longer fits three per CU).
-template <int WAVES, int LMAX, int HBITS, bool IDX32, bool SLOTCNT>
+// Per-node counts are kept by table slot: CNT 1 one 32-bit counter per slot,
+// 2 two 16-bit counters per word.
+template <int WAVES, int LMAX, int HBITS, bool IDX32, int CNT>
 struct WideLds {
-    static constexpr bool kSlotCnt = SLOTCNT;
+    static constexpr int kCnt = CNT;
     idx_t<IDX32> base[LMAX];
     int32_t key[1 << HBITS];
     int32_t P[LMAX + 1];
-    int32_t cnt[SLOTCNT ? (1 << HBITS) : LMAX];  // per-node counts
-    int16_t pos[SLOTCNT ? 1 : (1 << HBITS)];     // list position of each slot's id
-    int16_t tpos[LMAX];  // per target row: its target's slot (SLOTCNT, LDS lists) or list position
+    int32_t cnt[CNT == 1 ? (1 << HBITS) : (1 << HBITS) / 2];  // per-node counts by slot
+    int16_t tpos[LMAX];  // per target row: its target's slot (lists in LDS) or list position
     alignas(4) uint8_t flag[WAVES][kFlagBytes];
     int32_t wsum[WAVES];
     int32_t wcnt[WAVES];
@@ -796,15 +806,15 @@ __device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &r
             hi = mid - 1;
     }
     if (in_lds && cuckoo)
-        return walk_steps<HBITS, PER_NODE, true, true, IDX32, L::kSlotCnt ? 2 : 1, int16_t>(
-            S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs,
+        return walk_steps<HBITS, PER_NODE, true, true, IDX32, L::kCnt + 1, int16_t>(
+            S.key, S.tpos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs,
             a, i0, tv);
     if (in_lds)
-        return walk_steps<HBITS, PER_NODE, true, false, IDX32, L::kSlotCnt ? 2 : 1, int16_t>(
-            S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs,
+        return walk_steps<HBITS, PER_NODE, true, false, IDX32, L::kCnt + 1, int16_t>(
+            S.key, S.tpos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs,
             a, i0, tv);
-    return walk_steps<HBITS, PER_NODE, false, false, IDX32, 1, int16_t>(
-        S.key, S.pos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs, a,
+    return walk_steps<HBITS, PER_NODE, false, false, IDX32, L::kCnt + 1, int16_t>(
+        S.key, S.tpos, S.P, S.base, S.tpos, S.cnt, S.flag[wave], rd, gcol, nt, total, lo, e_begin, s1 * kStep, rs, a,
         i0, tv);
 }
 
@@ -816,8 +826,11 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                                                            int rounds) {
     constexpr int kThreadsW = WAVES * 64;
     constexpr int kHash = 1 << HBITS;
-    constexpr bool SLOTCNT = TIER == 1;
-    __shared__ WideLds<WAVES, LMAX, HBITS, IDX32, SLOTCNT> S;
+    // the 4-wave tier counts by slot; the 8-wave tier by slot in 16-bit
+    // halves (32-bit counters by slot would take its LDS past what lets three
+    // of its workgroups share a CU)
+    constexpr int CNT = TIER == 1 ? 1 : 2;
+    __shared__ WideLds<WAVES, LMAX, HBITS, IDX32, CNT> S;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     const int cap = min(lds_max, LMAX);
     for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = kEmpty;
@@ -868,12 +881,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                 __syncthreads();
             }
             const bool cuckoo = rounds > 0 && !S.homeless;
-            if (cuckoo) {
-                if (PER_NODE && !SLOTCNT) {
-                    for (int32_t k = threadIdx.x; k < a; k += kThreadsW)
-                        S.pos[cuckoo_slot<HBITS>(S.key, col[rs + k])] = (int16_t)k;
-                }
-            } else {
+            if (!cuckoo) {
                 if (rounds > 0) {
                     // a key found no place: empty the table and probe linearly instead
                     for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = kEmpty;
@@ -883,27 +891,28 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                     const int32_t x = col[rs + k];
                     uint32_t sl = hash_slot(x, HBITS);
                     while (atomicCAS(&S.key[sl], kEmpty, x) != kEmpty) sl = (sl + 1) & (kHash - 1);
-                    if (PER_NODE && !SLOTCNT) S.pos[sl] = (int16_t)k;
                 }
             }
             __syncthreads();
             int32_t nt, total;
-            wide_rows<WAVES, HBITS, IDX32>(S, col, off, rs, 0, te, row_lo, ebase, !SLOTCNT ? 0 : cuckoo ? 1 : 2, &nt,
+            wide_rows<WAVES, HBITS, IDX32>(S, col, off, rs, 0, te, row_lo, ebase, cuckoo ? 1 : 2, &nt,
                                            &total);
             hits = wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, 0, nt, total, true, cuckoo);
             __syncthreads();
             // counts out (one atomic per non-zero counter), then the table emptied
-            if (PER_NODE && !SLOTCNT) {
-                for (int32_t k = threadIdx.x; k < a; k += kThreadsW) {
-                    const int32_t c = S.cnt[k];
+            if (PER_NODE && CNT == 2) {
+                for (int w = threadIdx.x; w < kHash / 2; w += kThreadsW) {
+                    const uint32_t c = (uint32_t)S.cnt[w];
                     if (c) {
-                        add_u64(&tv[col[rs + k]], (uint64_t)c);
-                        S.cnt[k] = 0;
+                        if (c & 0xffffu) add_u64(&tv[S.key[2 * w]], (uint64_t)(c & 0xffffu));
+                        if (c >> 16) add_u64(&tv[S.key[2 * w + 1]], (uint64_t)(c >> 16));
+                        S.cnt[w] = 0;
                     }
                 }
+                __syncthreads();
             }
             for (int i = threadIdx.x; i < kHash; i += kThreadsW) {
-                if (PER_NODE && SLOTCNT) {
+                if (PER_NODE && CNT == 1) {
                     const int32_t c = S.cnt[i];
                     if (c) {
                         add_u64(&tv[S.key[i]], (uint64_t)c);
