@@ -175,6 +175,7 @@ void ensure_scratch(tc_graph *g, bool per_node, int32_t search, hipStream_t s) {
         d.k = g->pk.k;
         d.small_max = g->small_max;
         d.search_ratio = search;
+        d.samp = g->o.samp.p;
         if (!g->desc.p) g->desc = tc::DevBuf<tc::CountDesc>(g->al, 1);
         k_store_desc<<<1, 64, 0, s>>>(d, g->desc.p);
         TC_LAUNCH_CHECK();
@@ -231,7 +232,7 @@ struct DescPack {
     tc::CountDesc d[kDescPack];
 };
 static_assert(sizeof(DescPack) <= 3072, "descriptor pack must fit the kernel argument space");
-static_assert(sizeof(tc::CountDesc) == 168, "tc.h states the scratch of tc_count_batch_static with 168-byte descriptors");
+static_assert(sizeof(tc::CountDesc) == 176, "tc.h states the scratch of tc_count_batch_static with 176-byte descriptors");
 
 __global__ void k_store_descs(DescPack p, int n, tc::CountDesc *out) {
     const int i = (int)threadIdx.x;
@@ -272,6 +273,7 @@ void launch_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, const 
         d.k = g->pk.k;
         d.small_max = g->small_max;
         d.search_ratio = count_search(g, opt);
+        d.samp = g->o.samp.p;
         task_base += g->o.tasks;
         med_base += g->o.nmed;
         large_base += g->o.nbig - g->o.nmed;

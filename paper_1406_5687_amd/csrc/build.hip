@@ -1663,6 +1663,14 @@ void schedule_into(const Packing &pk, const BuildParams &bp, Allocator &al, Allo
                    Oriented &out, const uint64_t *okeys, int gb, int64_t *f_prior = nullptr,
                    PresetTargets *pre = nullptr, Piggyback *pb = nullptr);
 
+// samp[j] = col[j * kSampleStride]: the first level of the one-wave kernel's
+// binary searches in long rows (a few MB that stay cached, so a search reads
+// one line of col instead of several)
+__global__ void k_sample_col(const int32_t *__restrict__ col, int64_t ns, int32_t *__restrict__ samp) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ns; j += (int64_t)gridDim.x * blockDim.x)
+        samp[j] = col[j << kSampleShift];
+}
+
 void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
                            Allocator &al, hipStream_t s, Oriented &out) {
     const int64_t N = pk.N, M_in = pk.M_in;
@@ -1682,6 +1690,12 @@ void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing
         throw;
     }
     al.put(arena, arena_bytes);
+    const int64_t ns = ceil_div(out.M, kSampleStride);
+    out.samp = DevBuf<int32_t>(al, (size_t)std::max<int64_t>(ns, 1));
+    if (ns > 0) {
+        k_sample_col<<<grid_for(ns, 4), kThreads, 0, s>>>(out.col.p, ns, out.samp.p);
+        TC_LAUNCH_CHECK();
+    }
 }
 
 namespace {

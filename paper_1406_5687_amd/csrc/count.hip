@@ -464,7 +464,8 @@ __device__ __forceinline__ int32_t search_setup(SmallLds<IDX32> &S, bool q0, boo
 // {s, t_i, L[j]}.
 template <bool PER_NODE, bool IDX32>
 __device__ __forceinline__ uint32_t search_pairs(SmallLds<IDX32> &S, const ColReader<IDX32> &rd, int32_t npairs,
-                                                 int ns, int32_t a, int32_t x0, int32_t x1) {
+                                                 int ns, int32_t a, int32_t x0, int32_t x1,
+                                                 gptr_t<const int32_t> samp, int64_t ebase) {
     const int lane = __lane_id();
     uint32_t hits = 0;
     for (int32_t p0 = 0; p0 < npairs; p0 += 64) {
@@ -483,8 +484,27 @@ __device__ __forceinline__ uint32_t search_pairs(SmallLds<IDX32> &S, const ColRe
         const int j = min(i + 1 + (p - S.P[kSmallMax - lo]), a - 1);
         const int32_t xa = __shfl(x0, j & 63, 64), xb = __shfl(x1, j & 63, 64);
         const int32_t x = j < 64 ? xa : xb;
-        const idx_t<IDX32> rb = S.base[sl];
+        idx_t<IDX32> rb = S.base[sl];
         int32_t n = okp ? S.slen[sl] : 1;
+        if (samp && n > 1) {
+            // first level: the samples inside the row (entries j * stride of
+            // col, j in [js, je)) narrow the search to one stride of the row
+            const int64_t g0 = ebase + (int64_t)rb, g1 = g0 + n;
+            const int64_t js = (g0 + kSampleStride - 1) >> kSampleShift, je = (g1 + kSampleStride - 1) >> kSampleShift;
+            int64_t b0 = g0, b1 = min(g1, js << kSampleShift);
+            if (je > js && samp[js] <= x) {
+                int64_t at = js, m = je - js;  // at: the last sample <= x so far
+                while (m > 1) {
+                    const int64_t half = m >> 1;
+                    if (samp[at + half] <= x) at += half;
+                    m -= half;
+                }
+                b0 = at << kSampleShift;
+                b1 = min(g1, b0 + kSampleStride);
+            }
+            rb = (idx_t<IDX32>)(b0 - ebase);
+            n = (int32_t)(b1 - b0);
+        }
         int32_t at = 0;
         while (n > 1) {  // at: the last entry <= x so far (or 0), N_t[at .. at + n) still open
             const int32_t half = n >> 1;
@@ -512,7 +532,7 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
                                                  gptr_t<const int32_t> gcol, gptr_t<const int64_t> off,
                                                  int64_t *__restrict__ tv, int32_t s, int32_t a, int32_t te,
                                                  int32_t row_lo, int64_t ebase, int32_t x0, int32_t x1, int lane,
-                                                 int32_t sr, int rounds) {
+                                                 int32_t sr, int rounds, gptr_t<const int32_t> samp) {
     const bool h0 = lane < a, h1 = lane + 64 < a;
     bool cuckoo = rounds > 0;
     if (cuckoo) {
@@ -584,7 +604,7 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
                                      : 0;
     wave_lds_sync();
 
-    uint32_t hits = npairs ? search_pairs<PER_NODE, IDX32>(S, rd, npairs, ns, a, x0, x1) : 0u;
+    uint32_t hits = npairs ? search_pairs<PER_NODE, IDX32>(S, rd, npairs, ns, a, x0, x1, samp, ebase) : 0u;
     const int32_t e_end = ((total + kStep - 1) / kStep) * kStep;
     if (cuckoo)
         hits += walk_steps<kSmallHashBits, PER_NODE, true, true, IDX32, 0, uint8_t>(
@@ -658,6 +678,8 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
         const ColReader<IDX32> rd(descs[h].col + ebase, mg);
         const int small_max = descs[h].small_max;
         const int32_t sr = uniform32(descs[h].search_ratio);
+        // slices hold no samples of their rows
+        const gptr_t<const int32_t> samp = gview(SLICE ? (const int32_t *)nullptr : descs[h].samp);
         uint64_t tri = 0;
         for (int32_t s0 = v0; s0 < v1; s0 += 64) {
             const int32_t sv = min(s0 + lane, v1 - 1);
@@ -689,7 +711,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
                 const int32_t te = readlane32(tl, j);
                 const int32_t sl = SLICE ? readlane32(lab, j) : s0 + j;
                 tri += source_small<PER_NODE, IDX32, SLICE>(S, rd, col, off, tv, sl, a, te, row_lo, ebase, x0, x1,
-                                                            lane, sr, rounds);
+                                                            lane, sr, rounds, samp);
                 j = jn;
                 a = an;
                 rs = rn;

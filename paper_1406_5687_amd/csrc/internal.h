@@ -74,6 +74,7 @@ struct Oriented {
     int64_t nmed = 0;  // lists in big[0, nmed) have at most max_medium_list() entries
     int32_t max_dhat = 0;
     int32_t rounds = 1;  // rounds of the task table
+    DevBuf<int32_t> samp;  // ceil(M / kSampleStride): col[j * kSampleStride]
 };
 
 // src/dst: packed input edges on the device (edge e of graph g at edge_base[g] + i).
@@ -212,7 +213,12 @@ struct CountDesc {
     // entries after the target is binary-searched instead of walked; -1 =
     // every row, 0 = none
     int32_t search_ratio;
+    // every kSampleStride-th entry of col (samp[j] = col[j * kSampleStride]),
+    // the first level of those searches; NULL: search col directly
+    const int32_t *samp;
 };
+constexpr int kSampleShift = 5;
+constexpr int64_t kSampleStride = (int64_t)1 << kSampleShift;  // entries per sample (one 128-byte line)
 
 // Moves a two-choice insertion may make before the list falls back to linear
 // probing.
