@@ -121,6 +121,17 @@ typedef struct {
                              TC_HASH_LINEAR: linear probing for every list.  Same results either
                              way.  Set at build or reschedule time; a count call with a non-zero
                              hash uses its own for that call */
+    int32_t bitmap_ratio; /* dense core (Fig. 1: the test w in N_u, turned around): a one-graph
+                             handle built without a budget keeps the rows of its last nodes in
+                             the degree order (those of highest degree, whose rows fill a good
+                             share of the few labels above them) as bitmaps too.  With
+                             TC_INTERSECT_AUTO, a target row of the core holding 64 entries or
+                             more that is longer than bitmap_ratio times the entries of N_v
+                             after u (the only candidates) is not read: each candidate is tested
+                             against one word of its bitmap instead.  Same results either way.
+                             0 = automatic (2); -1 = never (at build time: no core is kept);
+                             at most 2^20.  Set at build or reschedule time; a count call with a
+                             non-zero bitmap_ratio uses its own for that call */
 } tc_options;
 
 enum { TC_INTERSECT_AUTO = 0, TC_INTERSECT_WALK = 1, TC_INTERSECT_SEARCH = 2 };
@@ -184,7 +195,7 @@ tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt,
  * allocator.  Outputs must be device pointers (opt->outputs_on_device = 1,
  * else TC_ERR_INVALID_ARG).  The scratch needed is 256 + 8 * (sum of k) +
  * 8 * (sum of n over the handles, when any per-node output is asked for),
- * rounded up to 256, + 176 * ng bytes; a batch that needs more returns
+ * rounded up to 256, + 208 * ng bytes; a batch that needs more returns
  * TC_ERR_TOO_LARGE before any launch.  Every call on one GPU uses the same
  * array and clears what it reads before the count: calls that overlap on one
  * GPU (two streams, two threads) race and must be serialised by the caller. */
@@ -247,7 +258,11 @@ typedef struct {
                                0 = every row walked, R > 0 = rows longer than R times their
                                candidates searched (see tc_options.intersect) */
     int32_t hash;           /* TC_HASH_* of later counts (see tc_options.hash) */
-    int32_t reserved[1];
+    int32_t bitmap_ratio;   /* core tests of later counts: 0 = none (no core, or switched off),
+                               B > 0 = core rows longer than B times their candidates tested
+                               (see tc_options.bitmap_ratio) */
+    int64_t core_rows;      /* rows kept as bitmaps (the last core_rows labels); 0 = no core */
+    uint64_t core_bytes;    /* device bytes of those bitmaps */
 } tc_graph_info_t;
 
 tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info);

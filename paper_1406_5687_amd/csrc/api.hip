@@ -21,6 +21,7 @@ struct tc_graph {
     int32_t cost_fn = TC_COST_PRIOR;
     int32_t search = 64;  // one-wave lists: search ratio of the descriptors (-1 every row, 0 none)
     int32_t hash = TC_HASH_AUTO;  // LDS table of the lists: two-choice or linear probing
+    int32_t bitmap = 2;  // core rows: bitmap ratio of the descriptors (0 none)
     // persistent count scratch: queue heads, totals, per-node accumulators
     tc::DevBuf<uint32_t> heads;
     tc::DevBuf<int64_t> totals;
@@ -28,6 +29,7 @@ struct tc_graph {
     tc::DevBuf<tc::CountDesc> desc;  // one descriptor pointing at the buffers above
     bool desc_has_tv = false;
     int32_t desc_search = 0;  // search ratio written into desc
+    int32_t desc_bitmap = 0;  // bitmap ratio written into desc
     // optional device timing of the counting kernels
     hipEvent_t ev[2] = {nullptr, nullptr};
     bool timed = false;
@@ -107,6 +109,8 @@ void check_options(const tc_options *opt) {
         throw tc::Error(TC_ERR_INVALID_ARG, "search_ratio outside 0 .. 2^20");
     if (opt->hash < TC_HASH_AUTO || opt->hash > TC_HASH_LINEAR)
         throw tc::Error(TC_ERR_INVALID_ARG, "unknown hash table kind");
+    if (opt->bitmap_ratio < -1 || opt->bitmap_ratio > (1 << 20))
+        throw tc::Error(TC_ERR_INVALID_ARG, "bitmap_ratio outside -1 .. 2^20");
 }
 
 constexpr int32_t kDefaultSearchRatio = 64;
@@ -117,6 +121,23 @@ int32_t resolve_search(int32_t intersect, int32_t ratio) {
     if (intersect == TC_INTERSECT_WALK) return 0;
     if (intersect == TC_INTERSECT_SEARCH) return -1;
     return ratio > 0 ? ratio : kDefaultSearchRatio;
+}
+
+constexpr int32_t kDefaultBitmapRatio = 2;
+
+// Descriptor encoding of the core tests: 0 = none, B > 0 = core rows longer
+// than B times their candidates are tested against their bitmaps.  Only the
+// automatic intersection uses them.
+int32_t resolve_bitmap(int32_t intersect, int32_t ratio) {
+    if (intersect != TC_INTERSECT_AUTO || ratio < 0) return 0;
+    return ratio > 0 ? ratio : kDefaultBitmapRatio;
+}
+
+// The core-test setting of a count call: its own when it names one, else the handle's.
+int32_t count_bitmap(const tc_graph *g, const tc_options *opt) {
+    if (opt && (opt->intersect != TC_INTERSECT_AUTO || opt->bitmap_ratio != 0))
+        return resolve_bitmap(opt->intersect, opt->bitmap_ratio);
+    return g->bitmap;
 }
 
 // Eviction limit of the two-choice table for a count call (0 = linear
@@ -149,13 +170,23 @@ __global__ void k_count_reset(uint32_t *heads, int64_t *totals, int64_t k, int64
         for (int64_t i = i0; i < n; i += st) tv[i] = 0;
 }
 
+// The core fields of a descriptor (none when the handle has no core).
+void set_core(tc::CountDesc &d, const tc_graph *g, int32_t bitmap) {
+    d.bm = g->o.bm.p;
+    d.core_lo = g->o.core.lo;
+    d.core_wl = g->o.core.wl;
+    d.core_fc = g->o.core.fc;
+    d.bitmap_ratio = g->o.bm.p ? bitmap : 0;
+}
+
 // Per-handle descriptor used by single-handle counts (kept on the device).
-void ensure_scratch(tc_graph *g, bool per_node, int32_t search, hipStream_t s) {
+void ensure_scratch(tc_graph *g, bool per_node, int32_t search, int32_t bitmap, hipStream_t s) {
     g->al.stream = s;
     if (!g->heads.p) g->heads = tc::DevBuf<uint32_t>(g->al, 4);  // 3 queue heads
     if (!g->totals.p) g->totals = tc::DevBuf<int64_t>(g->al, (size_t)std::max(g->pk.k, 1));
     if (per_node && !g->tv.p) g->tv = tc::DevBuf<int64_t>(g->al, (size_t)std::max<int64_t>(g->pk.N, 1));
-    if (!g->part && (!g->desc.p || (per_node && !g->desc_has_tv) || g->desc_search != search)) {
+    if (!g->part && (!g->desc.p || (per_node && !g->desc_has_tv) || g->desc_search != search ||
+                     g->desc_bitmap != bitmap)) {
         tc::CountDesc d{};
         d.off = g->o.off.p;
         d.col = g->o.col.p;
@@ -176,11 +207,13 @@ void ensure_scratch(tc_graph *g, bool per_node, int32_t search, hipStream_t s) {
         d.small_max = g->small_max;
         d.search_ratio = search;
         d.samp = g->o.samp.p;
+        set_core(d, g, bitmap);
         if (!g->desc.p) g->desc = tc::DevBuf<tc::CountDesc>(g->al, 1);
         k_store_desc<<<1, 64, 0, s>>>(d, g->desc.p);
         TC_LAUNCH_CHECK();
         g->desc_has_tv = g->tv.p != nullptr;
         g->desc_search = search;
+        g->desc_bitmap = bitmap;
     }
 }
 
@@ -227,12 +260,12 @@ BatchLayout batch_layout(tc_graph *const *gs, int32_t ng, int64_t *const *per_no
 
 // Descriptors stored by kernels whose arguments carry them: no host buffer
 // has to outlive the call, so the upload can be captured in a graph.
-constexpr int kDescPack = 16;
+constexpr int kDescPack = 14;
 struct DescPack {
     tc::CountDesc d[kDescPack];
 };
 static_assert(sizeof(DescPack) <= 3072, "descriptor pack must fit the kernel argument space");
-static_assert(sizeof(tc::CountDesc) == 176, "tc.h states the scratch of tc_count_batch_static with 176-byte descriptors");
+static_assert(sizeof(tc::CountDesc) == 208, "tc.h states the scratch of tc_count_batch_static with 208-byte descriptors");
 
 __global__ void k_store_descs(DescPack p, int n, tc::CountDesc *out) {
     const int i = (int)threadIdx.x;
@@ -274,6 +307,7 @@ void launch_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, const 
         d.small_max = g->small_max;
         d.search_ratio = count_search(g, opt);
         d.samp = g->o.samp.p;
+        set_core(d, g, count_bitmap(g, opt));
         task_base += g->o.tasks;
         med_base += g->o.nmed;
         large_base += g->o.nbig - g->o.nmed;
@@ -410,6 +444,7 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
         g->rounds = o.rounds;
         g->search = resolve_search(o.intersect, o.search_ratio);
         g->hash = o.hash;
+        g->bitmap = resolve_bitmap(o.intersect, o.bitmap_ratio);
         tc::BuildParams bp;
         bp.workers = g->workers;
         bp.cost_fn = o.cost_fn;
@@ -418,6 +453,7 @@ tc_status tc_build_oriented(const tc_edges *graphs, int32_t k, const tc_options 
         bp.rounds = o.rounds;
         bp.direct = o.direct;
         bp.static_chunks = o.static_chunks;
+        bp.core = o.bitmap_ratio >= 0;  // -1 at build time: no core at all
         g->static_chunks = o.static_chunks;
 
         // Resident unless forced or over the budget: the resident build holds
@@ -525,6 +561,7 @@ tc_status tc_graph_reschedule(tc_graph *g, const tc_options *opt) {
         g->cost_fn = bp.cost_fn;
         g->search = resolve_search(o.intersect, o.search_ratio);
         g->hash = o.hash;
+        g->bitmap = resolve_bitmap(o.intersect, o.bitmap_ratio);
         g->lds_max = o.lds_list_max > 0 ? std::max(2, std::min(o.lds_list_max, tc::max_lds_list())) : tc::max_lds_list();
         // the per-handle count descriptor caches the wide list and small_max
         g->desc.release();
@@ -539,7 +576,7 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
         hipStream_t s = opt ? (hipStream_t)opt->stream : nullptr;
         const bool want_tv = per_node != nullptr;
         const int32_t search = count_search(g, opt);
-        ensure_scratch(g, want_tv, search, s);
+        ensure_scratch(g, want_tv, search, count_bitmap(g, opt), s);
         const size_t k = (size_t)g->pk.k;
         const bool timing = opt && opt->time_kernels;
         if (timing) {
@@ -763,6 +800,9 @@ tc_status tc_graph_info(const tc_graph *g, tc_graph_info_t *info) {
     info->cost_fn = g->cost_fn;
     info->search_ratio = g->search;
     info->hash = g->hash;
+    info->bitmap_ratio = g->o.bm.p ? g->bitmap : 0;
+    info->core_rows = g->o.bm.p ? g->pk.N - g->o.core.lo : 0;
+    info->core_bytes = (uint64_t)g->o.core.words * 4;
     info->last_count_ms = -1.0;
     if (g->timed) {
         float ms = 0.f;

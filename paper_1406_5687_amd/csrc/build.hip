@@ -1671,6 +1671,99 @@ __global__ void k_sample_col(const int32_t *__restrict__ col, int64_t ns, int32_
         samp[j] = col[j << kSampleShift];
 }
 
+// Dense core.  The rows at the end of the degree order belong to the nodes of
+// highest degree; every member of such a row u lies in (u, N), a range so
+// short that the row fills a good share of it.  From the first row among the
+// last kCoreScan that holds kCoreMinRow entries or more and fills at least
+// 1/32 of (u, N), every row is kept as a bitmap over (u, N) as well (the
+// layout of core_origin), at most min(M, 512 MiB) bytes in all: a bitmap is
+// then no larger than the row, and a test of one id reads one word of it.
+constexpr int64_t kCoreScan = (int64_t)1 << 17;
+constexpr int kCoreMinRow = 32;
+constexpr int64_t kCoreMaxWords = (int64_t)1 << 27;
+
+// far[0] = max of N - u over the qualifying rows u >= u0 (0: none)
+__global__ void k_core_start(const int64_t *__restrict__ off, int64_t N, int64_t u0, int32_t *__restrict__ far) {
+    const int64_t u = u0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool q = false;
+    if (u < N) {
+        const int64_t L = off[u + 1] - off[u];
+        q = L >= kCoreMinRow && 32 * L >= N - 1 - u;
+    }
+    const uint64_t b = __ballot(q);
+    // the first qualifying lane of the wave holds its smallest row
+    if (q && (int)__lane_id() == __builtin_ctzll(b)) atomicMax(far, (int32_t)(N - u));
+}
+
+// One wave per core row: each entry x sets bit x & 31 of word
+// core_origin(u) + (x >> 5).  A row is sorted, so the entries of one word sit
+// in adjacent lanes; their bits are OR-ed across the lanes first and each
+// word takes one atomic OR per wave.
+__global__ __launch_bounds__(kThreads) void k_core_bits(const int64_t *__restrict__ off,
+                                                        const int32_t *__restrict__ col, int64_t lo, int64_t N,
+                                                        int64_t wl, int64_t fc, uint32_t *__restrict__ bm) {
+    const int lane = (int)__lane_id();
+    const int64_t u = lo + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 64;
+    if (u >= N) return;  // the whole wave
+    const int64_t org = core_origin(u, lo, wl, fc);
+    const int64_t r1 = off[u + 1];
+    for (int64_t e0 = off[u]; e0 < r1; e0 += 64) {
+        const int64_t e = e0 + lane;
+        const bool ok = e < r1;
+        const int32_t x = ok ? col[e] : 0;
+        const int32_t w = ok ? (int32_t)(org + (x >> 5)) : -1 - lane;  // distinct keys past the row
+        uint32_t bits = ok ? 1u << (x & 31) : 0u;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t ob = __shfl_up(bits, d, 64);
+            const int32_t ow = __shfl_up(w, d, 64);
+            if (lane >= d && ow == w) bits |= ob;
+        }
+        const int32_t nw = __shfl_down(w, 1, 64);
+        if (ok && (lane == 63 || nw != w)) atomicOr(&bm[w], bits);
+    }
+}
+
+// Builds the core of a one-graph handle without a device budget (else none).
+void build_core(const Packing &pk, const BuildParams &bp, Allocator &al, hipStream_t s, Oriented &out) {
+    const int64_t N = pk.N;
+    out.core = Oriented::CoreLayout{};
+    out.core.lo = (int32_t)N;
+    if (!bp.core || pk.k != 1 || al.budget || out.M == 0 || N < 2) return;
+    const int64_t u0 = std::max<int64_t>(0, N - kCoreScan);
+    DevBuf<int32_t> far(al, 1);
+    fill_zero(far.p, 4, s);
+    k_core_start<<<grid_for(N - u0), kThreads, 0, s>>>(out.off.p, N, u0, far.p);
+    TC_LAUNCH_CHECK();
+    int32_t hfar = 0;
+    read_words(&hfar, far.p, 1, s);
+    if (hfar <= 0) return;
+    int64_t lo = N - hfar;
+    const int64_t cap = std::min<int64_t>(kCoreMaxWords, out.M / 4);
+    if (core_words(N, lo) > cap) {
+        int64_t a = lo, b = N;  // smallest row start whose core fits the cap
+        while (a < b) {
+            const int64_t mid = a + (b - a) / 2;
+            if (core_words(N, mid) <= cap)
+                b = mid;
+            else
+                a = mid + 1;
+        }
+        lo = a;
+    }
+    const int64_t words = core_words(N, lo);
+    if (lo >= N || words <= 0) return;
+    out.bm = DevBuf<uint32_t>(al, (size_t)words);
+    fill_zero(out.bm.p, (size_t)words * 4, s);
+    out.core.lo = (int32_t)lo;
+    out.core.wl = (int32_t)((N - 1) >> 5);
+    out.core.fc = core_prefix(lo + 1);
+    out.core.words = words;
+    k_core_bits<<<(unsigned)ceil_div((N - lo) * 64, (int64_t)kThreads), kThreads, 0, s>>>(
+        out.off.p, out.col.p, lo, N, out.core.wl, out.core.fc, out.bm.p);
+    TC_LAUNCH_CHECK();
+}
+
 void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
                            Allocator &al, hipStream_t s, Oriented &out) {
     const int64_t N = pk.N, M_in = pk.M_in;
@@ -1696,6 +1789,7 @@ void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing
         k_sample_col<<<grid_for(ns, 4), kThreads, 0, s>>>(out.col.p, ns, out.samp.p);
         TC_LAUNCH_CHECK();
     }
+    build_core(pk, bp, al, s, out);
 }
 
 namespace {

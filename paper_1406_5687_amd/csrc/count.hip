@@ -523,6 +523,69 @@ __device__ __forceinline__ uint32_t search_pairs(SmallLds<IDX32> &S, const ColRe
     return hits;
 }
 
+// The one-wave kernel's core rows (flags z0 / z1 of targets lane and 64 +
+// lane, bitmap origins o0 / o1): for each such target t_i the entries L[j],
+// j > i, of the list are tested against the bitmap of N_{t_i}, lane j reading
+// the word of L[j].  Per-node counts are summed in registers: c0 / c1 for the
+// entries lane and 64 + lane (both the hits of L[j] and, for the entry t_i,
+// those of its row).  Returns this lane's hits.
+template <bool PER_NODE>
+__device__ __forceinline__ uint32_t core_rows_small(gptr_t<const uint32_t> bm, uint64_t Z0, uint64_t Z1, int32_t o0,
+                                                    int32_t o1, int32_t a, int32_t x0, int32_t x1, int32_t &c0,
+                                                    int32_t &c1) {
+    const int lane = __lane_id();
+    uint32_t hits = 0;
+    const int32_t s0 = x0 >> 5, s1 = x1 >> 5;
+    const uint32_t m0 = 1u << (x0 & 31), m1 = 1u << (x1 & 31);
+    // two rows per round, their four words loaded together
+    while (Z0 | Z1) {
+        int i[2];
+        int32_t og[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (Z0) {
+                const int l = __builtin_ctzll(Z0);
+                Z0 &= Z0 - 1;
+                i[q] = l;
+                og[q] = readlane32(o0, l);
+            } else if (Z1) {
+                const int l = __builtin_ctzll(Z1);
+                Z1 &= Z1 - 1;
+                i[q] = 64 + l;
+                og[q] = readlane32(o1, l);
+            } else {
+                i[q] = 1 << 30;  // no row: every lane is masked
+                og[q] = 0;
+            }
+        }
+        uint32_t w0[2], w1[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const bool v0 = lane > i[q] && lane < a;
+            const bool v1 = 64 + lane > i[q] && 64 + lane < a;
+            w0[q] = v0 ? bm[og[q] + s0] : 0u;
+            w1[q] = v1 ? bm[og[q] + s1] : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const bool h0 = (w0[q] & m0) != 0u, h1 = (w1[q] & m1) != 0u;
+            hits += (uint32_t)h0 + (uint32_t)h1;
+            if (PER_NODE) {
+                c0 += (int32_t)h0;
+                c1 += (int32_t)h1;
+                const int32_t rh = popc64(__ballot(h0)) + popc64(__ballot(h1));
+                if (lane == (i[q] & 63)) {
+                    if (i[q] < 64)
+                        c0 += rh;
+                    else if (i[q] < 128)
+                        c1 += rh;
+                }
+            }
+        }
+    }
+    return hits;
+}
+
 // One source s whose list (a entries, 2 <= a <= 128) is already in registers:
 // x0 = L[lane], x1 = L[64 + lane] (clamped copies beyond a).  The first te
 // entries are the targets (te = a - 1 for a resident adjacency); their rows
@@ -532,7 +595,9 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
                                                  gptr_t<const int32_t> gcol, gptr_t<const int64_t> off,
                                                  int64_t *__restrict__ tv, int32_t s, int32_t a, int32_t te,
                                                  int32_t row_lo, int64_t ebase, int32_t x0, int32_t x1, int lane,
-                                                 int32_t sr, int rounds, gptr_t<const int32_t> samp) {
+                                                 int32_t sr, int rounds, gptr_t<const int32_t> samp,
+                                                 gptr_t<const uint32_t> bm, int32_t br, int32_t clo, int32_t cwl,
+                                                 int64_t cfc) {
     const bool h0 = lane < a, h1 = lane + 64 < a;
     bool cuckoo = rounds > 0;
     if (cuckoo) {
@@ -574,9 +639,14 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     // rows searched instead of walked: at least a whole step long and longer
     // than sr times the candidates after the target (a - 1 - i >= 1 for
     // every target i < te); a shorter row shares its walk steps with others
-    const bool q0 = sr != 0 && l0 > 0 && (sr < 0 || (l0 >= kStep && l0 > sr * (a - 1 - lane)));
-    const bool q1 = sr != 0 && l1 > 0 && (sr < 0 || (l1 >= kStep && l1 > sr * (a - 65 - lane)));
-    const int32_t b0 = q0 ? 0 : l0, b1 = q1 ? 0 : l1;
+    // rows of the dense core tested against their bitmaps instead: at least
+    // kCoreMinProbe entries and longer than br times the candidates (chosen
+    // first: a test reads one word where a search reads several)
+    const bool z0 = br > 0 && l0 >= kCoreMinProbe && x0 >= clo && l0 > br * (a - 1 - lane);
+    const bool z1 = br > 0 && l1 >= kCoreMinProbe && x1 >= clo && l1 > br * (a - 65 - lane);
+    const bool q0 = !z0 && sr != 0 && l0 > 0 && (sr < 0 || (l0 >= kStep && l0 > sr * (a - 1 - lane)));
+    const bool q1 = !z1 && sr != 0 && l1 > 0 && (sr < 0 || (l1 >= kStep && l1 > sr * (a - 65 - lane)));
+    const int32_t b0 = (q0 || z0) ? 0 : l0, b1 = (q1 || z1) ? 0 : l1;
     const uint64_t m0 = __ballot(b0 > 0), m1 = __ballot(b1 > 0);
     const int n0 = popc64(m0);
     const int32_t inc0 = wave_inclusive_sum(b0);
@@ -605,6 +675,15 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     wave_lds_sync();
 
     uint32_t hits = npairs ? search_pairs<PER_NODE, IDX32>(S, rd, npairs, ns, a, x0, x1, samp, ebase) : 0u;
+    int32_t zc0 = 0, zc1 = 0;  // per-node counts of the core tests
+    {
+        const uint64_t Z0 = __ballot(z0), Z1 = __ballot(z1);
+        if (Z0 | Z1) {
+            const int32_t o0 = z0 ? (int32_t)core_origin(x0, clo, cwl, cfc) : 0;
+            const int32_t o1 = z1 ? (int32_t)core_origin(x1, clo, cwl, cfc) : 0;
+            hits += core_rows_small<PER_NODE>(bm, Z0, Z1, o0, o1, a, x0, x1, zc0, zc1);
+        }
+    }
     const int32_t e_end = ((total + kStep - 1) / kStep) * kStep;
     if (cuckoo)
         hits += walk_steps<kSmallHashBits, PER_NODE, true, true, IDX32, 0, uint8_t>(
@@ -616,14 +695,14 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
         const uint64_t hs = wave_sum((uint64_t)hits);
         wave_lds_sync();
         if (h0) {
-            const int32_t c = S.cnt[lane];
+            const int32_t c = S.cnt[lane] + zc0;
             if (c) {
                 add_u64(&tv[x0], (uint64_t)c);
                 S.cnt[lane] = 0;
             }
         }
         if (h1) {
-            const int32_t c = S.cnt[64 + lane];
+            const int32_t c = S.cnt[64 + lane] + zc1;
             if (c) {
                 add_u64(&tv[x1], (uint64_t)c);
                 S.cnt[64 + lane] = 0;
@@ -680,6 +759,11 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
         const int32_t sr = uniform32(descs[h].search_ratio);
         // slices hold no samples of their rows
         const gptr_t<const int32_t> samp = gview(SLICE ? (const int32_t *)nullptr : descs[h].samp);
+        // nor a core
+        const gptr_t<const uint32_t> bm = gview(SLICE ? (const uint32_t *)nullptr : descs[h].bm);
+        const int32_t br = bm ? uniform32(descs[h].bitmap_ratio) : 0;
+        const int32_t clo = uniform32(descs[h].core_lo), cwl = uniform32(descs[h].core_wl);
+        const int64_t cfc = uniform64(descs[h].core_fc);
         uint64_t tri = 0;
         for (int32_t s0 = v0; s0 < v1; s0 += 64) {
             const int32_t sv = min(s0 + lane, v1 - 1);
@@ -711,7 +795,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
                 const int32_t te = readlane32(tl, j);
                 const int32_t sl = SLICE ? readlane32(lab, j) : s0 + j;
                 tri += source_small<PER_NODE, IDX32, SLICE>(S, rd, col, off, tv, sl, a, te, row_lo, ebase, x0, x1,
-                                                            lane, sr, rounds, samp);
+                                                            lane, sr, rounds, samp, bm, br, clo, cwl, cfc);
                 j = jn;
                 a = an;
                 rs = rn;
@@ -740,6 +824,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
 template <int WAVES, int LMAX, int HBITS, bool IDX32, int CNT>
 struct WideLds {
     static constexpr int kCnt = CNT;
+    static constexpr int kLmax = LMAX;
     idx_t<IDX32> base[LMAX];
     int32_t key[1 << HBITS];
     int32_t P[LMAX + 1];
@@ -748,6 +833,7 @@ struct WideLds {
     alignas(4) uint8_t flag[WAVES][kFlagBytes];
     int32_t wsum[WAVES];
     int32_t wcnt[WAVES];
+    int32_t wcore[WAVES];
     uint64_t whits[WAVES];
     int64_t item;
     int32_t homeless;  // some key found no place in the two-choice table
@@ -757,54 +843,129 @@ struct WideLds {
 // `col` from rs; target t has row t - row_lo of off) into P / base / tpos.
 // tpos: the target's slot in the LDS table (TABLE 1: two-choice, 2: linear
 // probing) or, with TABLE 0, its list position relative to i0.  Returns (rows,
-// total ids).
+// total ids).  With br > 0 (a list in LDS, a - 1 - i candidates after target
+// i), a target row of the dense core with kCoreMinProbe entries or more that
+// is longer than br times its candidates is left out of the walk and listed
+// for core_rows_wide instead: core row k (in list order) keeps its target in
+// P[LMAX - k], its bitmap origin in base[LMAX - 1 - k] and its slot in
+// tpos[LMAX - 1 - k].  The walk's rows and the core rows together are at most
+// the targets, fewer than LMAX, so the two ends never meet.
 template <int WAVES, int HBITS, bool IDX32, class L>
 __device__ __forceinline__ void wide_rows(L &S, gptr_t<const int32_t> col, gptr_t<const int64_t> off, int64_t rs,
                                           int32_t i0, int32_t i1, int32_t row_lo, int64_t ebase, int table,
-                                          int32_t *nt_out, int32_t *total_out) {
+                                          int32_t a, int32_t br, int32_t clo, int32_t cwl, int64_t cfc,
+                                          int32_t *nt_out, int32_t *total_out, int32_t *nc_out) {
     constexpr int kThreadsW = WAVES * 64;
+    constexpr int LMAX = L::kLmax;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
-    int32_t carry_n = 0, carry_sum = 0;
+    int32_t carry_n = 0, carry_sum = 0, carry_c = 0;
     for (int32_t rb = i0; rb < i1; rb += kThreadsW) {
         const int32_t i = rb + (int32_t)threadIdx.x;
         const int32_t x = col[rs + min(i, i1 - 1)], t = x - row_lo;
         const int64_t r = off[t], re = off[t + 1];
-        const int32_t b = i < i1 ? (int32_t)(re - r) : 0;
+        const int32_t len = i < i1 ? (int32_t)(re - r) : 0;
+        const bool z = br > 0 && len >= kCoreMinProbe && x >= clo && len > br * (a - 1 - i);
+        const int32_t b = z ? 0 : len;
         const int32_t inc = wave_inclusive_sum(b);
         const uint64_t m = __ballot(b > 0);
+        const uint64_t mz = __ballot(z);
         if (lane == 63) {
             S.wsum[wave] = inc;
             S.wcnt[wave] = popc64(m);
+            S.wcore[wave] = popc64(mz);
         }
         __syncthreads();
-        int32_t sb = 0, cb = 0, st = 0, ct = 0;
+        int32_t sb = 0, cb = 0, st = 0, ct = 0, zb = 0, zt = 0;
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) {
-            const int32_t ws = S.wsum[w], wc = S.wcnt[w];
+            const int32_t ws = S.wsum[w], wc = S.wcnt[w], wz = S.wcore[w];
             if (w < wave) {
                 sb += ws;
                 cb += wc;
+                zb += wz;
             }
             st += ws;
             ct += wc;
+            zt += wz;
         }
-        if (b > 0) {
-            const int j = carry_n + cb + mbcnt64(m);
-            const int32_t p = carry_sum + sb + inc - b;
-            S.P[j] = p;
-            S.base[j] = (idx_t<IDX32>)(r - ebase - (int64_t)p);
-            S.tpos[j] = (int16_t)(table == 1   ? cuckoo_slot<HBITS>(S.key, x)
-                                  : table == 2 ? linear_slot<HBITS>(S.key, x)
-                                               : (uint32_t)(i - i0));
+        if (b > 0 || z) {
+            const int16_t slot = (int16_t)(table == 1   ? cuckoo_slot<HBITS>(S.key, x)
+                                           : table == 2 ? linear_slot<HBITS>(S.key, x)
+                                                        : (uint32_t)(i - i0));
+            if (z) {
+                const int k = carry_c + zb + mbcnt64(mz);
+                S.P[LMAX - k] = x;
+                S.base[LMAX - 1 - k] = (idx_t<IDX32>)core_origin(x, clo, cwl, cfc);
+                S.tpos[LMAX - 1 - k] = slot;
+            } else {
+                const int j = carry_n + cb + mbcnt64(m);
+                const int32_t p = carry_sum + sb + inc - b;
+                S.P[j] = p;
+                S.base[j] = (idx_t<IDX32>)(r - ebase - (int64_t)p);
+                S.tpos[j] = slot;
+            }
         }
         carry_n += ct;
         carry_sum += st;
+        carry_c += zt;
         __syncthreads();
     }
     if (threadIdx.x == 0) S.P[carry_n] = carry_sum;
     __syncthreads();
     *nt_out = uniform32(carry_n);
     *total_out = uniform32(carry_sum);
+    *nc_out = uniform32(carry_c);
+}
+
+// The core rows listed by wide_rows (nc of them): for each, the list entries
+// after its target are tested against the target's bitmap.  The list goes in
+// chunks of 64 entries, chunk c to wave c mod WAVES; a chunk meets the core
+// rows whose target is below its largest entry (a prefix: targets ascend),
+// lane j reading the word of L[j] for every row whose target precedes L[j].
+// Per-node counts: a row's hits go to its target's slot counter, an entry's
+// hits over all rows to its own.  Returns this lane's hits.
+template <int WAVES, int HBITS, bool PER_NODE, int PN, class L>
+__device__ __forceinline__ uint32_t core_rows_wide(L &S, gptr_t<const int32_t> col, int64_t rs, int32_t a,
+                                                   int32_t nc, gptr_t<const uint32_t> bm, bool cuckoo) {
+    constexpr int LMAX = L::kLmax;
+    const int lane = __lane_id();
+    const int wave = uniform32(threadIdx.x >> 6);
+    uint32_t hits = 0;
+    const int32_t nch = (a + 63) >> 6;
+    for (int32_t c = wave; c < nch; c += WAVES) {
+        const int32_t j = c * 64 + lane;
+        const bool in = j < a;
+        const int32_t x = col[rs + min(j, a - 1)];
+        const int32_t xmax = readlane32(x, 63);  // the chunk's largest entry (clamped lanes repeat the last)
+        int lo = 0, hi = nc;  // rows whose target is below xmax: [0, lo)
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (uniform32(S.P[LMAX - mid]) < xmax)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        const int32_t sw = x >> 5;
+        const uint32_t mb = 1u << (x & 31);
+        int32_t acc = 0;
+#pragma unroll 4
+        for (int k = 0; k < lo; ++k) {
+            const int32_t u = S.P[LMAX - k];
+            const int32_t org = (int32_t)S.base[LMAX - 1 - k];
+            const bool v = in && x > u;
+            const uint32_t w = v ? bm[org + sw] : 0u;
+            const bool h = (w & mb) != 0u;
+            acc += (int32_t)h;
+            if (PER_NODE) {
+                const int rh = popc64(__ballot(h));
+                if (rh && lane == 0) cnt_add<PN>(S.cnt, S.tpos[LMAX - 1 - k], rh);
+            }
+        }
+        hits += (uint32_t)acc;
+        if (PER_NODE && acc)
+            cnt_add<PN>(S.cnt, cuckoo ? cuckoo_slot<HBITS>(S.key, x) : linear_slot<HBITS>(S.key, x), acc);
+    }
+    return hits;
 }
 
 // This wave's contiguous share of the virtual sequence, in whole steps.
@@ -891,6 +1052,11 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
             mg = off[descs[h].node_base[g + 1]] - ebase;
         }
         const ColReader<IDX32> rd(descs[h].col + ebase, mg);
+        // slices hold no core
+        const gptr_t<const uint32_t> bm = gview(SLICE ? (const uint32_t *)nullptr : descs[h].bm);
+        const int32_t br = bm ? uniform32(descs[h].bitmap_ratio) : 0;
+        const int32_t clo = uniform32(descs[h].core_lo), cwl = uniform32(descs[h].core_wl);
+        const int64_t cfc = uniform64(descs[h].core_fc);
         uint64_t hits = 0;
         if (te <= 0) {
             // no resident target (slice launches only)
@@ -916,10 +1082,12 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                 }
             }
             __syncthreads();
-            int32_t nt, total;
-            wide_rows<WAVES, HBITS, IDX32>(S, col, off, rs, 0, te, row_lo, ebase, cuckoo ? 1 : 2, &nt,
-                                           &total);
-            hits = wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, 0, nt, total, true, cuckoo);
+            int32_t nt, total, nc;
+            wide_rows<WAVES, HBITS, IDX32>(S, col, off, rs, 0, te, row_lo, ebase, cuckoo ? 1 : 2, a, br, clo, cwl,
+                                           cfc, &nt, &total, &nc);
+            if (nc > 0)
+                hits = core_rows_wide<WAVES, HBITS, PER_NODE, CNT + 1>(S, col, rs, a, nc, bm, cuckoo);
+            hits += wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, 0, nt, total, true, cuckoo);
             __syncthreads();
             // counts out (one atomic per non-zero counter), then the table emptied
             if (PER_NODE && CNT == 2) {
@@ -946,8 +1114,9 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
         } else {
             for (int32_t i0 = 0; i0 < te; i0 += cap) {
                 const int32_t i1 = min(te, i0 + cap);
-                int32_t nt, total;
-                wide_rows<WAVES, HBITS, IDX32>(S, col, off, rs, i0, i1, row_lo, ebase, 0, &nt, &total);
+                int32_t nt, total, nc;
+                wide_rows<WAVES, HBITS, IDX32>(S, col, off, rs, i0, i1, row_lo, ebase, 0, a, 0, 0, 0, 0, &nt,
+                                               &total, &nc);
                 hits += wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, i0, nt, total, false,
                                                                     false);
                 __syncthreads();

@@ -50,6 +50,7 @@ struct BuildParams {
     int32_t rounds = 0;  // Eq. (1) with W = workers * rounds; 0 = automatic
     int32_t direct = 0;  // partitioned form: one streamed range per stored edge
     int32_t static_chunks = 0;  // W equal-cost tasks instead of Eq. (1)/(2)
+    int32_t core = 1;           // keep the dense core's rows as bitmaps too (Oriented::bm)
 };
 
 // Automatic rounds: one for a single graph; for k packed graphs, enough that
@@ -75,7 +76,36 @@ struct Oriented {
     int32_t max_dhat = 0;
     int32_t rounds = 1;  // rounds of the task table
     DevBuf<int32_t> samp;  // ceil(M / kSampleStride): col[j * kSampleStride]
+    // Dense core (one graph only): rows core.lo .. N-1 as bitmaps, see CoreLayout
+    DevBuf<uint32_t> bm;
+    struct CoreLayout {
+        int32_t lo = 0;   // first core row; N = no core
+        int32_t wl = 0;   // (N - 1) >> 5: last word of every core row
+        int64_t fc = 0;   // core_prefix(lo + 1)
+        int64_t words = 0;
+    } core;
 };
+
+// Layout of the core bitmaps.  Every member of N_u lies in (u, N) by the
+// degree order, so core row u keeps the bits of the words (u + 1) >> 5 .. wl
+// (bit x & 31 of word x >> 5 is set when x is in N_u), the rows one after the
+// other from core.lo.  core_prefix(t) = sum of i >> 5 over 0 <= i < t.
+__host__ __device__ __forceinline__ int64_t core_prefix(int64_t t) {
+    const int64_t q = t >> 5, r = t & 31;
+    return 16 * q * (q - 1) + r * q;
+}
+// Word of id x in the bitmap of core row u is core_origin(u, ...) + (x >> 5),
+// for u < x < N.
+__host__ __device__ __forceinline__ int64_t core_origin(int64_t u, int64_t lo, int64_t wl, int64_t fc) {
+    const int64_t q = (u + 1) >> 5;
+    return (u - lo) * (wl + 1) - (core_prefix(u + 1) - fc) - q;
+}
+// Words of the core from row lo on (rows lo .. N-1).
+inline int64_t core_words(int64_t N, int64_t lo) {
+    if (lo >= N) return 0;
+    const int64_t wl = (N - 1) >> 5;
+    return (N - lo) * (wl + 1) - (core_prefix(N + 1) - core_prefix(lo + 1));
+}
 
 // src/dst: packed input edges on the device (edge e of graph g at edge_base[g] + i).
 void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,
@@ -216,7 +246,18 @@ struct CountDesc {
     // every kSampleStride-th entry of col (samp[j] = col[j * kSampleStride]),
     // the first level of those searches; NULL: search col directly
     const int32_t *samp;
+    // Dense core (Oriented::bm): a target row u >= core_lo of at least
+    // kCoreMinProbe entries that is longer than bitmap_ratio times the list
+    // entries after u is not walked; those entries are tested against its
+    // bitmap instead.  bm NULL or bitmap_ratio 0: none.
+    const uint32_t *bm;
+    int64_t core_fc;
+    int32_t core_lo;
+    int32_t core_wl;
+    int32_t bitmap_ratio;
+    int32_t pad_;
 };
+constexpr int kCoreMinProbe = 64;
 constexpr int kSampleShift = 5;
 constexpr int64_t kSampleStride = (int64_t)1 << kSampleShift;  // entries per sample (one 128-byte line)
 

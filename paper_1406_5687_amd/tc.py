@@ -76,6 +76,7 @@ class Options(ctypes.Structure):
         ("intersect", ctypes.c_int32),
         ("search_ratio", ctypes.c_int32),
         ("hash", ctypes.c_int32),
+        ("bitmap_ratio", ctypes.c_int32),
     ]
 
 
@@ -104,7 +105,9 @@ class GraphInfo(ctypes.Structure):
         ("rounds", ctypes.c_int32),
         ("search_ratio", ctypes.c_int32),
         ("hash", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("bitmap_ratio", ctypes.c_int32),
+        ("core_rows", ctypes.c_int64),
+        ("core_bytes", ctypes.c_uint64),
     ]
 
 
@@ -219,7 +222,7 @@ def _is_tensor(x) -> bool:
 def make_options(*, stream=None, inputs_on_device=False, outputs_on_device=False, hbm_budget_bytes=0, workers=0,
                  cost_fn=COST_PRIOR, min_chunk=0, small_max=0, lds_list_max=0, time_kernels=False,
                  partitions=0, rounds=0, direct=False, static_chunks=False, intersect=INTERSECT_AUTO,
-                 search_ratio=0, hash=HASH_AUTO, torch_allocator=True) -> Options:
+                 search_ratio=0, hash=HASH_AUTO, bitmap_ratio=0, torch_allocator=True) -> Options:
     global _torch_alloc
     o = Options()
     load().tc_options_default(ctypes.byref(o))
@@ -239,6 +242,7 @@ def make_options(*, stream=None, inputs_on_device=False, outputs_on_device=False
     o.intersect = int(intersect)
     o.search_ratio = int(search_ratio)
     o.hash = int(hash)
+    o.bitmap_ratio = int(bitmap_ratio)
     if stream is None:
         try:
             torch = _torch()
@@ -329,12 +333,13 @@ class Graph:
         return tv[: self.n_total], tot[: self.k]
 
     def reschedule(self, workers=0, cost_fn=COST_PRIOR, min_chunk=0, small_max=0, rounds=0, static_chunks=False,
-                   intersect=INTERSECT_AUTO, search_ratio=0, lds_list_max=0, hash=HASH_AUTO):
-        """New task table, intersection choice, LDS cap and table kind for the
-        same adjacency (tc_graph_reschedule); later counts use them."""
+                   intersect=INTERSECT_AUTO, search_ratio=0, lds_list_max=0, hash=HASH_AUTO, bitmap_ratio=0):
+        """New task table, intersection choice, LDS cap, table kind and core
+        tests for the same adjacency (tc_graph_reschedule); later counts use
+        them."""
         self._kw.update(workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max, rounds=rounds,
                         static_chunks=static_chunks, intersect=intersect, search_ratio=search_ratio,
-                        lds_list_max=lds_list_max, hash=hash)
+                        lds_list_max=lds_list_max, hash=hash, bitmap_ratio=bitmap_ratio)
         o = self._opts()
         _raise(load().tc_graph_reschedule(self._h, ctypes.byref(o)))
 
@@ -429,7 +434,8 @@ class Graph:
 
 def build_oriented(graphs: Sequence, *, stream=None, hbm_budget_bytes=0, workers=0, cost_fn=COST_PRIOR, min_chunk=0,
                    small_max=0, lds_list_max=0, partitions=0, rounds=0, direct=False, static_chunks=False,
-                   intersect=INTERSECT_AUTO, search_ratio=0, hash=HASH_AUTO, torch_allocator=True) -> Graph:
+                   intersect=INTERSECT_AUTO, search_ratio=0, hash=HASH_AUTO, bitmap_ratio=0,
+                   torch_allocator=True) -> Graph:
     """Builds one handle from graphs given as (n, src, dst) triples.  src/dst are
     numpy arrays (host) or torch tensors (all on the device, or all host)."""
     if not len(graphs):
@@ -449,7 +455,7 @@ def build_oriented(graphs: Sequence, *, stream=None, hbm_budget_bytes=0, workers
     kw = dict(stream=stream, hbm_budget_bytes=hbm_budget_bytes, workers=workers, cost_fn=cost_fn,
               min_chunk=min_chunk, small_max=small_max, lds_list_max=lds_list_max, partitions=partitions,
               rounds=rounds, direct=direct, static_chunks=static_chunks, intersect=intersect,
-              search_ratio=search_ratio, hash=hash, torch_allocator=torch_allocator)
+              search_ratio=search_ratio, hash=hash, bitmap_ratio=bitmap_ratio, torch_allocator=torch_allocator)
     o = make_options(inputs_on_device=on_dev, **kw)
     h = ctypes.c_void_p(0)
     _raise(load().tc_build_oriented(arr, len(graphs), ctypes.byref(o), ctypes.byref(h)))
@@ -463,7 +469,7 @@ _EDGES_DTYPE = np.dtype({"names": ["n", "m", "src", "dst"], "formats": ["<i4", "
 
 def build_packed_device(ns, ms, src_ptr: int, dst_ptr: int, *, stream=None, workers=0, cost_fn=COST_PRIOR,
                         min_chunk=0, small_max=0, lds_list_max=0, rounds=0, intersect=INTERSECT_AUTO,
-                        search_ratio=0, hash=HASH_AUTO, torch_allocator=True) -> Graph:
+                        search_ratio=0, hash=HASH_AUTO, bitmap_ratio=0, torch_allocator=True) -> Graph:
     """Builds one handle from k graphs whose edges already lie back to back in
     two device arrays (graph i's edges start at the sum of the earlier m), read
     in place.  ns / ms: node and edge counts per graph; src_ptr / dst_ptr:
@@ -482,7 +488,7 @@ def build_packed_device(ns, ms, src_ptr: int, dst_ptr: int, *, stream=None, work
     arr["dst"] = np.uint64(dst_ptr) + (eb * 4).astype(np.uint64)
     kw = dict(stream=stream, workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max,
               lds_list_max=lds_list_max, rounds=rounds, intersect=intersect, search_ratio=search_ratio,
-              hash=hash, torch_allocator=torch_allocator)
+              hash=hash, bitmap_ratio=bitmap_ratio, torch_allocator=torch_allocator)
     o = make_options(inputs_on_device=True, **kw)
     h = ctypes.c_void_p(0)
     _raise(load().tc_build_oriented(ctypes.cast(arr.ctypes.data, ctypes.POINTER(Edges)), k, ctypes.byref(o),

@@ -38,16 +38,18 @@ def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "tc.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tc_options),'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tc_options),'
         ' sizeof(tc_graph_info_t), sizeof(tc_edges), offsetof(tc_options, hbm_budget_bytes),'
         ' offsetof(tc_options, min_chunk), offsetof(tc_options, lds_list_max), offsetof(tc_graph_info_t, device_bytes),'
-        ' offsetof(tc_options, hash), offsetof(tc_graph_info_t, hash)); return 0;}\n')
+        ' offsetof(tc_options, hash), offsetof(tc_graph_info_t, hash), offsetof(tc_options, bitmap_ratio),'
+        ' offsetof(tc_graph_info_t, core_rows), offsetof(tc_graph_info_t, core_bytes)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert vals == [ctypes.sizeof(tc.Options), ctypes.sizeof(tc.GraphInfo), ctypes.sizeof(tc.Edges),
                     tc.Options.hbm_budget_bytes.offset, tc.Options.min_chunk.offset, tc.Options.lds_list_max.offset,
-                    tc.GraphInfo.device_bytes.offset, tc.Options.hash.offset, tc.GraphInfo.hash.offset]
+                    tc.GraphInfo.device_bytes.offset, tc.Options.hash.offset, tc.GraphInfo.hash.offset,
+                    tc.Options.bitmap_ratio.offset, tc.GraphInfo.core_rows.offset, tc.GraphInfo.core_bytes.offset]
 
 
 def test_status_strings_and_defaults():
@@ -59,7 +61,7 @@ def test_status_strings_and_defaults():
     o = tc.Options()
     lib.tc_options_default(ctypes.byref(o))
     assert o.cost_fn == tc.COST_PRIOR and o.workers == 0 and o.hbm_budget_bytes == 0
-    assert o.hash == tc.HASH_AUTO
+    assert o.hash == tc.HASH_AUTO and o.bitmap_ratio == 0
 
 
 def test_argument_errors_without_device():
