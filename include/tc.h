@@ -195,7 +195,7 @@ tc_status tc_count_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt,
  * allocator.  Outputs must be device pointers (opt->outputs_on_device = 1,
  * else TC_ERR_INVALID_ARG).  The scratch needed is 256 + 8 * (sum of k) +
  * 8 * (sum of n over the handles, when any per-node output is asked for),
- * rounded up to 256, + 208 * ng bytes; a batch that needs more returns
+ * rounded up to 256, + 200 * ng bytes; a batch that needs more returns
  * TC_ERR_TOO_LARGE before any launch.  Every call on one GPU uses the same
  * array and clears what it reads before the count: calls that overlap on one
  * GPU (two streams, two threads) race and must be serialised by the caller. */

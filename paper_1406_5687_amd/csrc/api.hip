@@ -175,7 +175,7 @@ void set_core(tc::CountDesc &d, const tc_graph *g, int32_t bitmap) {
     d.bm = g->o.bm.p;
     d.core_lo = g->o.core.lo;
     d.core_wl = g->o.core.wl;
-    d.core_fc = g->o.core.fc;
+    d.core_kw = g->o.core.kw;
     d.bitmap_ratio = g->o.bm.p ? bitmap : 0;
 }
 
@@ -260,12 +260,12 @@ BatchLayout batch_layout(tc_graph *const *gs, int32_t ng, int64_t *const *per_no
 
 // Descriptors stored by kernels whose arguments carry them: no host buffer
 // has to outlive the call, so the upload can be captured in a graph.
-constexpr int kDescPack = 14;
+constexpr int kDescPack = 15;
 struct DescPack {
     tc::CountDesc d[kDescPack];
 };
 static_assert(sizeof(DescPack) <= 3072, "descriptor pack must fit the kernel argument space");
-static_assert(sizeof(tc::CountDesc) == 208, "tc.h states the scratch of tc_count_batch_static with 208-byte descriptors");
+static_assert(sizeof(tc::CountDesc) == 200, "tc.h states the scratch of tc_count_batch_static with 200-byte descriptors");
 
 __global__ void k_store_descs(DescPack p, int n, tc::CountDesc *out) {
     const int i = (int)threadIdx.x;

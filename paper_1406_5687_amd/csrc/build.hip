@@ -1675,9 +1675,9 @@ __global__ void k_sample_col(const int32_t *__restrict__ col, int64_t ns, int32_
 // highest degree; every member of such a row u lies in (u, N), a range so
 // short that the row fills a good share of it.  From the first row among the
 // last kCoreScan that holds kCoreMinRow entries or more and fills at least
-// 1/32 of (u, N), every row is kept as a bitmap over (u, N) as well (the
-// layout of core_origin), at most min(M, 512 MiB) bytes in all: a bitmap is
-// then no larger than the row, and a test of one id reads one word of it.
+// 1/32 of (u, N), the adjacency among those last labels is kept as bitmaps
+// too (the layout of core_origin), at most min(M, 512 MiB) bytes in all: a
+// test of one id then reads one word, and two rows meet by AND-ing words.
 constexpr int64_t kCoreScan = (int64_t)1 << 17;
 constexpr int kCoreMinRow = 32;
 constexpr int64_t kCoreMaxWords = (int64_t)1 << 27;
@@ -1695,22 +1695,24 @@ __global__ void k_core_start(const int64_t *__restrict__ off, int64_t N, int64_t
     if (q && (int)__lane_id() == __builtin_ctzll(b)) atomicMax(far, (int32_t)(N - u));
 }
 
-// One wave per core row: each entry x sets bit x & 31 of word
-// core_origin(u) + (x >> 5).  A row is sorted, so the entries of one word sit
-// in adjacent lanes; their bits are OR-ed across the lanes first and each
-// word takes one atomic OR per wave.
+// One wave per core row u: each entry x sets bit x in row u and bit u in row
+// x.  A row is sorted, so the entries of one word of row u sit in adjacent
+// lanes; their bits are OR-ed across the lanes first and each such word takes
+// one atomic OR per wave.
 __global__ __launch_bounds__(kThreads) void k_core_bits(const int64_t *__restrict__ off,
                                                         const int32_t *__restrict__ col, int64_t lo, int64_t N,
-                                                        int64_t wl, int64_t fc, uint32_t *__restrict__ bm) {
+                                                        int64_t kw, uint32_t *__restrict__ bm) {
     const int lane = (int)__lane_id();
     const int64_t u = lo + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 64;
     if (u >= N) return;  // the whole wave
-    const int64_t org = core_origin(u, lo, wl, fc);
+    const int64_t org = core_origin(u, lo, kw);
     const int64_t r1 = off[u + 1];
+    const uint32_t ubit = 1u << (u & 31);
     for (int64_t e0 = off[u]; e0 < r1; e0 += 64) {
         const int64_t e = e0 + lane;
         const bool ok = e < r1;
         const int32_t x = ok ? col[e] : 0;
+        if (ok) atomicOr(&bm[core_origin(x, lo, kw) + (u >> 5)], ubit);
         const int32_t w = ok ? (int32_t)(org + (x >> 5)) : -1 - lane;  // distinct keys past the row
         uint32_t bits = ok ? 1u << (x & 31) : 0u;
 #pragma unroll
@@ -1722,6 +1724,11 @@ __global__ __launch_bounds__(kThreads) void k_core_bits(const int64_t *__restric
         const int32_t nw = __shfl_down(w, 1, 64);
         if (ok && (lane == 63 || nw != w)) atomicOr(&bm[w], bits);
     }
+}
+
+// Words of the core from label lo on.
+inline int64_t core_words(int64_t N, int64_t lo) {
+    return lo >= N ? 0 : (N - lo) * (((N - 1) >> 5) - (lo >> 5) + 1);
 }
 
 // Builds the core of a one-graph handle without a device budget (else none).
@@ -1741,7 +1748,7 @@ void build_core(const Packing &pk, const BuildParams &bp, Allocator &al, hipStre
     int64_t lo = N - hfar;
     const int64_t cap = std::min<int64_t>(kCoreMaxWords, out.M / 4);
     if (core_words(N, lo) > cap) {
-        int64_t a = lo, b = N;  // smallest row start whose core fits the cap
+        int64_t a = lo, b = N;  // smallest first label whose core fits the cap
         while (a < b) {
             const int64_t mid = a + (b - a) / 2;
             if (core_words(N, mid) <= cap)
@@ -1757,10 +1764,10 @@ void build_core(const Packing &pk, const BuildParams &bp, Allocator &al, hipStre
     fill_zero(out.bm.p, (size_t)words * 4, s);
     out.core.lo = (int32_t)lo;
     out.core.wl = (int32_t)((N - 1) >> 5);
-    out.core.fc = core_prefix(lo + 1);
+    out.core.kw = (int32_t)(out.core.wl - (lo >> 5) + 1);
     out.core.words = words;
-    k_core_bits<<<(unsigned)ceil_div((N - lo) * 64, (int64_t)kThreads), kThreads, 0, s>>>(
-        out.off.p, out.col.p, lo, N, out.core.wl, out.core.fc, out.bm.p);
+    k_core_bits<<<(unsigned)ceil_div((N - lo) * 64, (int64_t)kThreads), kThreads, 0, s>>>(out.off.p, out.col.p, lo,
+                                                                                         N, out.core.kw, out.bm.p);
     TC_LAUNCH_CHECK();
 }
 

@@ -597,7 +597,7 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
                                                  int32_t row_lo, int64_t ebase, int32_t x0, int32_t x1, int lane,
                                                  int32_t sr, int rounds, gptr_t<const int32_t> samp,
                                                  gptr_t<const uint32_t> bm, int32_t br, int32_t clo, int32_t cwl,
-                                                 int64_t cfc) {
+                                                 int32_t ckw) {
     const bool h0 = lane < a, h1 = lane + 64 < a;
     bool cuckoo = rounds > 0;
     if (cuckoo) {
@@ -679,8 +679,8 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     {
         const uint64_t Z0 = __ballot(z0), Z1 = __ballot(z1);
         if (Z0 | Z1) {
-            const int32_t o0 = z0 ? (int32_t)core_origin(x0, clo, cwl, cfc) : 0;
-            const int32_t o1 = z1 ? (int32_t)core_origin(x1, clo, cwl, cfc) : 0;
+            const int32_t o0 = z0 ? (int32_t)core_origin(x0, clo, ckw) : 0;
+            const int32_t o1 = z1 ? (int32_t)core_origin(x1, clo, ckw) : 0;
             hits += core_rows_small<PER_NODE>(bm, Z0, Z1, o0, o1, a, x0, x1, zc0, zc1);
         }
     }
@@ -763,7 +763,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
         const gptr_t<const uint32_t> bm = gview(SLICE ? (const uint32_t *)nullptr : descs[h].bm);
         const int32_t br = bm ? uniform32(descs[h].bitmap_ratio) : 0;
         const int32_t clo = uniform32(descs[h].core_lo), cwl = uniform32(descs[h].core_wl);
-        const int64_t cfc = uniform64(descs[h].core_fc);
+        const int32_t ckw = uniform32(descs[h].core_kw);
         uint64_t tri = 0;
         for (int32_t s0 = v0; s0 < v1; s0 += 64) {
             const int32_t sv = min(s0 + lane, v1 - 1);
@@ -795,7 +795,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
                 const int32_t te = readlane32(tl, j);
                 const int32_t sl = SLICE ? readlane32(lab, j) : s0 + j;
                 tri += source_small<PER_NODE, IDX32, SLICE>(S, rd, col, off, tv, sl, a, te, row_lo, ebase, x0, x1,
-                                                            lane, sr, rounds, samp, bm, br, clo, cwl, cfc);
+                                                            lane, sr, rounds, samp, bm, br, clo, cwl, ckw);
                 j = jn;
                 a = an;
                 rs = rn;
@@ -825,9 +825,16 @@ template <int WAVES, int LMAX, int HBITS, bool IDX32, int CNT>
 struct WideLds {
     static constexpr int kCnt = CNT;
     static constexpr int kLmax = LMAX;
-    idx_t<IDX32> base[LMAX];
+    static constexpr int kAndWords = (int)((sizeof(idx_t<IDX32>) * LMAX + 4 * (LMAX + 1)) / 4);
+    // the walk's row table, or (a source of the core) the bitmap of its list
+    union {
+        struct {
+            idx_t<IDX32> base[LMAX];
+            int32_t P[LMAX + 1];
+        };
+        uint32_t vbits[kAndWords];
+    };
     int32_t key[1 << HBITS];
-    int32_t P[LMAX + 1];
     int32_t cnt[CNT == 1 ? (1 << HBITS) : (1 << HBITS) / 2];  // per-node counts by slot
     int16_t tpos[LMAX];  // per target row: its target's slot (lists in LDS) or list position
     alignas(4) uint8_t flag[WAVES][kFlagBytes];
@@ -853,7 +860,7 @@ struct WideLds {
 template <int WAVES, int HBITS, bool IDX32, class L>
 __device__ __forceinline__ void wide_rows(L &S, gptr_t<const int32_t> col, gptr_t<const int64_t> off, int64_t rs,
                                           int32_t i0, int32_t i1, int32_t row_lo, int64_t ebase, int table,
-                                          int32_t a, int32_t br, int32_t clo, int32_t cwl, int64_t cfc,
+                                          int32_t a, int32_t br, int32_t clo, int32_t cwl, int32_t ckw,
                                           int32_t *nt_out, int32_t *total_out, int32_t *nc_out) {
     constexpr int kThreadsW = WAVES * 64;
     constexpr int LMAX = L::kLmax;
@@ -895,7 +902,7 @@ __device__ __forceinline__ void wide_rows(L &S, gptr_t<const int32_t> col, gptr_
             if (z) {
                 const int k = carry_c + zb + mbcnt64(mz);
                 S.P[LMAX - k] = x;
-                S.base[LMAX - 1 - k] = (idx_t<IDX32>)core_origin(x, clo, cwl, cfc);
+                S.base[LMAX - 1 - k] = (idx_t<IDX32>)core_origin(x, clo, ckw);
                 S.tpos[LMAX - 1 - k] = slot;
             } else {
                 const int j = carry_n + cb + mbcnt64(m);
@@ -1001,6 +1008,60 @@ __device__ __forceinline__ uint64_t wide_windows(L &S, const ColReader<IDX32> &r
         i0, tv);
 }
 
+// A source v of the core: every entry of N_v lies in the core too.  N_v is
+// a bitmap in LDS (vbits, words from clo >> 5), and two lists meet by AND-ing
+// it with core rows word by word: (n - v) / 32 words instead of |N_u| ids,
+// fewer by the rows' density.  List entries go to the waves in turn, each
+// wave's lanes over consecutive words.
+//
+// Total only: for each target u, N_v intersect N_u is the AND with row u over
+// the labels above u.  Returns this lane's hits.
+template <int WAVES, class L>
+__device__ __forceinline__ uint32_t core_and_total(L &S, gptr_t<const int32_t> col, int64_t rs, int32_t te,
+                                                   gptr_t<const uint32_t> bm, int32_t clo, int32_t cwl, int32_t ckw) {
+    const int lane = __lane_id();
+    const int wave = uniform32(threadIdx.x >> 6);
+    const int32_t wv0 = clo >> 5;
+    uint32_t hits = 0;
+    for (int32_t i = wave; i < te; i += WAVES) {
+        const int32_t u = uniform32(col[rs + i]);
+        const int64_t org = core_origin(u, clo, ckw);
+        const int32_t w0 = (u + 1) >> 5;
+        const uint32_t m0 = ~0u << ((u + 1) & 31);  // labels above u in the first word
+        for (int32_t w = w0 + lane; w <= cwl; w += 64) {
+            const uint32_t x = bm[org + w] & S.vbits[w - wv0] & (w == w0 ? m0 : ~0u);
+            hits += (uint32_t)__popc(x);
+        }
+    }
+    return hits;
+}
+
+// Per node: for each entry x of N_v, the AND with the whole row x counts the
+// entries of N_v adjacent to x, that is the triangles {v, x, w} found from v,
+// which is x's share; every such triangle is found from both of its other
+// entries, so v's share is half the sum (the caller halves it).  Adds the
+// shares of the entries to tv and returns this lane's part of the sum.
+template <int WAVES, class L>
+__device__ __forceinline__ uint32_t core_and_per_node(L &S, gptr_t<const int32_t> col, int64_t rs, int32_t a,
+                                                      int32_t v, gptr_t<const uint32_t> bm, int32_t clo,
+                                                      int32_t cwl, int32_t ckw, int64_t *__restrict__ tv) {
+    const int lane = __lane_id();
+    const int wave = uniform32(threadIdx.x >> 6);
+    const int32_t wv0 = clo >> 5;
+    const int32_t w0 = (v + 1) >> 5;  // N_v lies above v
+    uint32_t hits = 0;
+    for (int32_t i = wave; i < a; i += WAVES) {
+        const int32_t x = uniform32(col[rs + i]);
+        const int64_t org = core_origin(x, clo, ckw);
+        uint32_t t = 0;
+        for (int32_t w = w0 + lane; w <= cwl; w += 64) t += (uint32_t)__popc(bm[org + w] & S.vbits[w - wv0]);
+        hits += t;
+        const uint64_t tx = wave_sum((uint64_t)t);
+        if (tx && lane == 0) add_u64(&tv[x], tx);
+    }
+    return hits;
+}
+
 // tier 1: lists in big[0, nmed); tier 2: lists in big[nmed, nbig)
 template <bool PER_NODE, bool IDX32, int WAVES, int LMAX, int HBITS, int TIER, bool SLICE>
 __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVES == 8 ? 6 : 1))) void k_count_wide(const CountDesc *__restrict__ descs, int ndesc,
@@ -1013,7 +1074,8 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
     // halves (32-bit counters by slot would take its LDS past what lets three
     // of its workgroups share a CU)
     constexpr int CNT = TIER == 1 ? 1 : 2;
-    __shared__ WideLds<WAVES, LMAX, HBITS, IDX32, CNT> S;
+    using L_t = WideLds<WAVES, LMAX, HBITS, IDX32, CNT>;
+    __shared__ L_t S;
     const int lane = __lane_id(), wave = threadIdx.x >> 6;
     const int cap = min(lds_max, LMAX);
     for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = kEmpty;
@@ -1056,12 +1118,17 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
         const gptr_t<const uint32_t> bm = gview(SLICE ? (const uint32_t *)nullptr : descs[h].bm);
         const int32_t br = bm ? uniform32(descs[h].bitmap_ratio) : 0;
         const int32_t clo = uniform32(descs[h].core_lo), cwl = uniform32(descs[h].core_wl);
-        const int64_t cfc = uniform64(descs[h].core_fc);
+        const int32_t ckw = uniform32(descs[h].core_kw);
         uint64_t hits = 0;
+        bool halve = false;  // hits counted twice (core AND, per node)
         if (te <= 0) {
             // no resident target (slice launches only)
         } else if (a <= cap) {
-            if (rounds > 0) {
+            // a source of the core whose list's bitmap fits the LDS: AND of bitmaps
+            const bool use_and = br > 0 && s >= clo && ckw <= L_t::kAndWords;
+            halve = use_and && PER_NODE;
+            const bool table = !use_and;  // the walk's table
+            if (rounds > 0 && table) {
                 bool bad = false;
                 for (int32_t k = threadIdx.x; k < a && !bad; k += kThreadsW)
                     bad = !cuckoo_place<HBITS>(S.key, col[rs + k], rounds);
@@ -1069,7 +1136,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                 __syncthreads();
             }
             const bool cuckoo = rounds > 0 && !S.homeless;
-            if (!cuckoo) {
+            if (!cuckoo && table) {
                 if (rounds > 0) {
                     // a key found no place: empty the table and probe linearly instead
                     for (int i = threadIdx.x; i < kHash; i += kThreadsW) S.key[i] = kEmpty;
@@ -1082,12 +1149,27 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
                 }
             }
             __syncthreads();
-            int32_t nt, total, nc;
-            wide_rows<WAVES, HBITS, IDX32>(S, col, off, rs, 0, te, row_lo, ebase, cuckoo ? 1 : 2, a, br, clo, cwl,
-                                           cfc, &nt, &total, &nc);
-            if (nc > 0)
-                hits = core_rows_wide<WAVES, HBITS, PER_NODE, CNT + 1>(S, col, rs, a, nc, bm, cuckoo);
-            hits += wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, 0, nt, total, true, cuckoo);
+            if (use_and) {
+                for (int i = threadIdx.x; i < ckw; i += kThreadsW) S.vbits[i] = 0u;
+                __syncthreads();
+                for (int32_t k = threadIdx.x; k < a; k += kThreadsW) {
+                    const int32_t x = col[rs + k];
+                    atomicOr(&S.vbits[(x >> 5) - (clo >> 5)], 1u << (x & 31));
+                }
+                __syncthreads();
+                if (PER_NODE)
+                    hits = core_and_per_node<WAVES>(S, col, rs, a, s, bm, clo, cwl, ckw, tv);
+                else
+                    hits = core_and_total<WAVES>(S, col, rs, te, bm, clo, cwl, ckw);
+            } else {
+                int32_t nt, total, nc;
+                wide_rows<WAVES, HBITS, IDX32>(S, col, off, rs, 0, te, row_lo, ebase, cuckoo ? 1 : 2, a, br, clo,
+                                               cwl, ckw, &nt, &total, &nc);
+                if (nc > 0)
+                    hits = core_rows_wide<WAVES, HBITS, PER_NODE, CNT + 1>(S, col, rs, a, nc, bm, cuckoo);
+                hits += wide_windows<WAVES, HBITS, PER_NODE, IDX32>(S, rd, col, tv, rs, a, 0, nt, total, true,
+                                                                    cuckoo);
+            }
             __syncthreads();
             // counts out (one atomic per non-zero counter), then the table emptied
             if (PER_NODE && CNT == 2) {
@@ -1128,6 +1210,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
         if (threadIdx.x == 0) {
             uint64_t H = 0;
             for (int w = 0; w < WAVES; ++w) H += S.whits[w];
+            if (halve) H >>= 1;
             if (H) {
                 add_u64(&descs[h].totals[g], H);
                 if (PER_NODE) add_u64(&tv[s], H);

@@ -76,35 +76,25 @@ struct Oriented {
     int32_t max_dhat = 0;
     int32_t rounds = 1;  // rounds of the task table
     DevBuf<int32_t> samp;  // ceil(M / kSampleStride): col[j * kSampleStride]
-    // Dense core (one graph only): rows core.lo .. N-1 as bitmaps, see CoreLayout
+    // Dense core (one graph only): the core's adjacency as bitmaps, see CoreLayout
     DevBuf<uint32_t> bm;
     struct CoreLayout {
-        int32_t lo = 0;   // first core row; N = no core
-        int32_t wl = 0;   // (N - 1) >> 5: last word of every core row
-        int64_t fc = 0;   // core_prefix(lo + 1)
+        int32_t lo = 0;   // first core label; N = no core
+        int32_t wl = 0;   // (N - 1) >> 5: the last word of a row
+        int32_t kw = 0;   // words per row: wl - (lo >> 5) + 1
         int64_t words = 0;
     } core;
 };
 
-// Layout of the core bitmaps.  Every member of N_u lies in (u, N) by the
-// degree order, so core row u keeps the bits of the words (u + 1) >> 5 .. wl
-// (bit x & 31 of word x >> 5 is set when x is in N_u), the rows one after the
-// other from core.lo.  core_prefix(t) = sum of i >> 5 over 0 <= i < t.
-__host__ __device__ __forceinline__ int64_t core_prefix(int64_t t) {
-    const int64_t q = t >> 5, r = t & 31;
-    return 16 * q * (q - 1) + r * q;
-}
-// Word of id x in the bitmap of core row u is core_origin(u, ...) + (x >> 5),
-// for u < x < N.
-__host__ __device__ __forceinline__ int64_t core_origin(int64_t u, int64_t lo, int64_t wl, int64_t fc) {
-    const int64_t q = (u + 1) >> 5;
-    return (u - lo) * (wl + 1) - (core_prefix(u + 1) - fc) - q;
-}
-// Words of the core from row lo on (rows lo .. N-1).
-inline int64_t core_words(int64_t N, int64_t lo) {
-    if (lo >= N) return 0;
-    const int64_t wl = (N - 1) >> 5;
-    return (N - lo) * (wl + 1) - (core_prefix(N + 1) - core_prefix(lo + 1));
+// Layout of the core bitmaps: one row of kw words per core label u, rows in
+// label order from core.lo, word j of a row covering the labels
+// 32 * ((lo >> 5) + j) .. + 31; bit x & 31 of the word of x is set in row u
+// when u and x are adjacent (both in the core).  Over labels above u a row is
+// N_u (every member of N_u lies above u by the degree order); below u it holds
+// the core nodes whose lists contain u.  core_origin(u) + (x >> 5) is the word
+// of x in row u.
+__host__ __device__ __forceinline__ int64_t core_origin(int64_t u, int64_t lo, int64_t kw) {
+    return (u - lo) * kw - (lo >> 5);
 }
 
 // src/dst: packed input edges on the device (edge e of graph g at edge_base[g] + i).
@@ -251,11 +241,10 @@ struct CountDesc {
     // entries after u is not walked; those entries are tested against its
     // bitmap instead.  bm NULL or bitmap_ratio 0: none.
     const uint32_t *bm;
-    int64_t core_fc;
     int32_t core_lo;
     int32_t core_wl;
+    int32_t core_kw;
     int32_t bitmap_ratio;
-    int32_t pad_;
 };
 constexpr int kCoreMinProbe = 64;
 constexpr int kSampleShift = 5;

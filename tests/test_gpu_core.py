@@ -5,8 +5,8 @@ against its bitmap instead of being read (Fig. 1: the test w in N_u, turned
 around).  Counts must equal the oracle's whatever the ratio, in all three
 kernel tiers, per count call or set at build / reschedule time, in batches
 beside handles without a core, and with the core left out (-1).  The core's
-size is checked against the layout the library states: row u keeps the words
-(u + 1) >> 5 .. (n - 1) >> 5."""
+size is checked against the layout the library states: one row per core label,
+each of the words (lo >> 5) .. (n - 1) >> 5 for the first core label lo."""
 import numpy as np
 import pytest
 
@@ -28,9 +28,9 @@ def tc():
 
 
 def core_words(n: int, rows: int) -> int:
-    """Words of the bitmaps of the last `rows` labels, summed row by row."""
-    wl = (n - 1) >> 5
-    return sum(wl - ((u + 1) >> 5) + 1 for u in range(n - rows, n))
+    """Words of the bitmaps of the last `rows` labels."""
+    lo = n - rows
+    return rows * (((n - 1) >> 5) - (lo >> 5) + 1)
 
 
 def _workloads():
