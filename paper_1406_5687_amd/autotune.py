@@ -2,12 +2,13 @@
 Eq. (1) (how many tasks the first half of the cost is cut into per worker), the
 wave/workgroup list threshold, the task floor of Eq. (2), the cost function,
 the intersection variant of one-wave lists (hash walk, binary search, or the
-ratio rule between them) and the longest list a workgroup keeps in LDS, for a
+ratio rule between them), the longest list a workgroup keeps in LDS and the
+ratio past which rows of the dense core are tested by bitmap, for a
 built handle, by timing the counting kernels on the data itself, and caches
 the choice per device and graph shape in a JSON file.  The search has three
 stages: rounds with the other parameters at their defaults, then threshold,
-floor and cost function with the best rounds, then the intersection and the
-LDS cap with the best of those.
+floor and cost function with the best rounds, then the intersection, the LDS
+cap and the bitmap ratio with the best of those.
 
 Counts do not depend on any of these choices (Section V-D: any task split
 counts every triangle once); only the time does.  The search reschedules the
@@ -36,6 +37,7 @@ class Params:
     intersect: int = tc.INTERSECT_AUTO  # one-wave lists: ratio rule, hash walk only, or search only
     search_ratio: int = 0     # R of the ratio rule; 0 = the library's choice
     lds_list_max: int = 0     # longest list a workgroup hashes in LDS; 0 = the library's choice
+    bitmap_ratio: int = 0     # core rows tested by bitmap past this ratio; 0 = the library's, -1 = never
 
     def min_chunk(self, total_cost: int, workers: int) -> int:
         return max(256, total_cost // (workers * self.floor_div + 1))
@@ -61,11 +63,13 @@ def intersections(base: Params) -> list:
     out = [replace(base, intersect=tc.INTERSECT_WALK), replace(base, intersect=tc.INTERSECT_SEARCH)]
     out += [replace(base, intersect=tc.INTERSECT_AUTO, search_ratio=r) for r in SEARCH_RATIOS]
     out += [replace(base, lds_list_max=c) for c in LDS_CAPS]
+    out += [replace(base, bitmap_ratio=b) for b in BITMAP_RATIOS]
     return out
 
 
 SEARCH_RATIOS = (16, 32, 128, 256)
 LDS_CAPS = (768, 1024, 1536)
+BITMAP_RATIOS = (1, 4, 8, -1)
 
 
 def features(info: dict) -> str:
@@ -132,7 +136,7 @@ class Autotuner:
         graph.reschedule(workers=info["workers"], cost_fn=p.cost_fn,
                          min_chunk=p.min_chunk(info["total_cost"], info["workers"]), small_max=p.small_max,
                          rounds=p.rounds, intersect=p.intersect, search_ratio=p.search_ratio,
-                         lds_list_max=p.lds_list_max)
+                         lds_list_max=p.lds_list_max, bitmap_ratio=p.bitmap_ratio)
 
     def tune(self, graph, per_node: bool = False, force: bool = False) -> Params:
         """Returns the chosen parameters and leaves the handle scheduled with them."""

@@ -1675,7 +1675,7 @@ __global__ void k_sample_col(const int32_t *__restrict__ col, int64_t ns, int32_
 // highest degree; every member of such a row u lies in (u, N), a range so
 // short that the row fills a good share of it.  From the first row among the
 // last kCoreScan that holds kCoreMinRow entries or more and fills at least
-// 1/32 of (u, N), the adjacency among those last labels is kept as bitmaps
+// 1/kCoreDensity of (u, N), the adjacency among those last labels is kept as bitmaps
 // too (the layout of core_origin), at most min(M, 512 MiB) bytes in all: a
 // test of one id then reads one word, and two rows meet by AND-ing words.
 constexpr int64_t kCoreScan = (int64_t)1 << 17;
@@ -1688,7 +1688,7 @@ __global__ void k_core_start(const int64_t *__restrict__ off, int64_t N, int64_t
     bool q = false;
     if (u < N) {
         const int64_t L = off[u + 1] - off[u];
-        q = L >= kCoreMinRow && 32 * L >= N - 1 - u;
+        q = L >= kCoreMinRow && kCoreDensity * L >= N - 1 - u;
     }
     const uint64_t b = __ballot(q);
     // the first qualifying lane of the wave holds its smallest row

@@ -1124,8 +1124,10 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
         if (te <= 0) {
             // no resident target (slice launches only)
         } else if (a <= cap) {
-            // a source of the core whose list's bitmap fits the LDS: AND of bitmaps
-            const bool use_and = br > 0 && s >= clo && ckw <= L_t::kAndWords;
+            // a source of the core whose list fills 1 / kCoreDensity of the labels
+            // above it and whose bitmap fits the LDS: AND of bitmaps
+            const bool use_and = br > 0 && s >= clo && ckw <= L_t::kAndWords &&
+                                 (int64_t)kCoreDensity * a >= (((int64_t)cwl << 5) | 31) - s;
             halve = use_and && PER_NODE;
             const bool table = !use_and;  // the walk's table
             if (rounds > 0 && table) {

@@ -247,6 +247,10 @@ struct CountDesc {
     int32_t bitmap_ratio;
 };
 constexpr int kCoreMinProbe = 64;
+// The core starts at a row that fills at least 1 / kCoreDensity of the labels
+// above it; a source of the core meets its list by bitmap AND when its own
+// list is as dense.
+constexpr int kCoreDensity = 32;
 constexpr int kSampleShift = 5;
 constexpr int64_t kSampleStride = (int64_t)1 << kSampleShift;  // entries per sample (one 128-byte line)
 

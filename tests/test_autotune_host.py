@@ -15,9 +15,10 @@ class FakeGraph:
                 "workers": 1024, "wide_nodes": 0, "tasks": 9000}
 
     def reschedule(self, workers, cost_fn, min_chunk, small_max, rounds=0, intersect=0, search_ratio=0,
-                   lds_list_max=0):
+                   lds_list_max=0, bitmap_ratio=0):
         self.sched = dict(workers=workers, cost_fn=cost_fn, min_chunk=min_chunk, small_max=small_max,
-                          rounds=rounds, intersect=intersect, search_ratio=search_ratio, lds_list_max=lds_list_max)
+                          rounds=rounds, intersect=intersect, search_ratio=search_ratio, lds_list_max=lds_list_max,
+                          bitmap_ratio=bitmap_ratio)
         self.calls.append(dict(self.sched))
 
 
