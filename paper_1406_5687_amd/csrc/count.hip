@@ -955,17 +955,38 @@ __device__ __forceinline__ uint32_t core_rows_wide(L &S, gptr_t<const int32_t> c
         const int32_t sw = x >> 5;
         const uint32_t mb = 1u << (x & 31);
         int32_t acc = 0;
+        if (!PER_NODE) {
 #pragma unroll 4
-        for (int k = 0; k < lo; ++k) {
-            const int32_t u = S.P[LMAX - k];
-            const int32_t org = (int32_t)S.base[LMAX - 1 - k];
-            const bool v = in && x > u;
-            const uint32_t w = v ? bm[org + sw] : 0u;
-            const bool h = (w & mb) != 0u;
-            acc += (int32_t)h;
-            if (PER_NODE) {
-                const int rh = popc64(__ballot(h));
-                if (rh && lane == 0) cnt_add<PN>(S.cnt, S.tpos[LMAX - 1 - k], rh);
+            for (int k = 0; k < lo; ++k) {
+                const int32_t u = S.P[LMAX - k];
+                const int32_t org = (int32_t)S.base[LMAX - 1 - k];
+                const uint32_t w = in && x > u ? bm[org + sw] : 0u;
+                acc += (w & mb) != 0u ? 1 : 0;
+            }
+        } else {
+            // four rows at a time: their words loaded together, their row
+            // counts added by one lane after the four ballots
+            for (int k0 = 0; k0 < lo; k0 += 4) {
+                uint32_t w[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int k = min(k0 + q, lo - 1);
+                    const int32_t u = S.P[LMAX - k];
+                    const int32_t org = (int32_t)S.base[LMAX - 1 - k];
+                    w[q] = in && x > u && k0 + q < lo ? bm[org + sw] : 0u;
+                }
+                int rh[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool h = (w[q] & mb) != 0u;
+                    acc += (int32_t)h;
+                    rh[q] = popc64(__ballot(h));
+                }
+                if (lane == 0) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (rh[q]) cnt_add<PN>(S.cnt, S.tpos[LMAX - 1 - (k0 + q)], rh[q]);
+                }
             }
         }
         hits += (uint32_t)acc;
