@@ -537,12 +537,13 @@ __device__ __forceinline__ uint32_t core_rows_small(gptr_t<const uint32_t> bm, u
     uint32_t hits = 0;
     const int32_t s0 = x0 >> 5, s1 = x1 >> 5;
     const uint32_t m0 = 1u << (x0 & 31), m1 = 1u << (x1 & 31);
-    // two rows per round, their four words loaded together
+    // kRows rows per round, their words loaded together
+    constexpr int kRows = 4;
     while (Z0 | Z1) {
-        int i[2];
-        int32_t og[2];
+        int i[kRows];
+        int32_t og[kRows];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < kRows; ++q) {
             if (Z0) {
                 const int l = __builtin_ctzll(Z0);
                 Z0 &= Z0 - 1;
@@ -558,16 +559,16 @@ __device__ __forceinline__ uint32_t core_rows_small(gptr_t<const uint32_t> bm, u
                 og[q] = 0;
             }
         }
-        uint32_t w0[2], w1[2];
+        uint32_t w0[kRows], w1[kRows];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < kRows; ++q) {
             const bool v0 = lane > i[q] && lane < a;
             const bool v1 = 64 + lane > i[q] && 64 + lane < a;
             w0[q] = v0 ? bm[og[q] + s0] : 0u;
             w1[q] = v1 ? bm[og[q] + s1] : 0u;
         }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < kRows; ++q) {
             const bool h0 = (w0[q] & m0) != 0u, h1 = (w1[q] & m1) != 0u;
             hits += (uint32_t)h0 + (uint32_t)h1;
             if (PER_NODE) {
@@ -956,35 +957,42 @@ __device__ __forceinline__ uint32_t core_rows_wide(L &S, gptr_t<const int32_t> c
         const uint32_t mb = 1u << (x & 31);
         int32_t acc = 0;
         if (!PER_NODE) {
-#pragma unroll 4
-            for (int k = 0; k < lo; ++k) {
-                const int32_t u = S.P[LMAX - k];
-                const int32_t org = (int32_t)S.base[LMAX - 1 - k];
-                const uint32_t w = in && x > u ? bm[org + sw] : 0u;
-                acc += (w & mb) != 0u ? 1 : 0;
-            }
-        } else {
-            // four rows at a time: their words loaded together, their row
-            // counts added by one lane after the four ballots
-            for (int k0 = 0; k0 < lo; k0 += 4) {
-                uint32_t w[4];
+            constexpr int kRowBatch = 8;
+            for (int k0 = 0; k0 < lo; k0 += kRowBatch) {
+                uint32_t w[kRowBatch];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < kRowBatch; ++q) {
                     const int k = min(k0 + q, lo - 1);
                     const int32_t u = S.P[LMAX - k];
                     const int32_t org = (int32_t)S.base[LMAX - 1 - k];
                     w[q] = in && x > u && k0 + q < lo ? bm[org + sw] : 0u;
                 }
-                int rh[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < kRowBatch; ++q) acc += (w[q] & mb) != 0u ? 1 : 0;
+            }
+        } else {
+            // kRowBatch rows at a time: their words loaded together, their row
+            // counts added by one lane after the ballots
+            constexpr int kRowBatch = 8;
+            for (int k0 = 0; k0 < lo; k0 += kRowBatch) {
+                uint32_t w[kRowBatch];
+#pragma unroll
+                for (int q = 0; q < kRowBatch; ++q) {
+                    const int k = min(k0 + q, lo - 1);
+                    const int32_t u = S.P[LMAX - k];
+                    const int32_t org = (int32_t)S.base[LMAX - 1 - k];
+                    w[q] = in && x > u && k0 + q < lo ? bm[org + sw] : 0u;
+                }
+                int rh[kRowBatch];
+#pragma unroll
+                for (int q = 0; q < kRowBatch; ++q) {
                     const bool h = (w[q] & mb) != 0u;
                     acc += (int32_t)h;
                     rh[q] = popc64(__ballot(h));
                 }
                 if (lane == 0) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < kRowBatch; ++q)
                         if (rh[q]) cnt_add<PN>(S.cnt, S.tpos[LMAX - 1 - (k0 + q)], rh[q]);
                 }
             }
