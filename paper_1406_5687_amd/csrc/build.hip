@@ -1675,12 +1675,13 @@ __global__ void k_sample_col(const int32_t *__restrict__ col, int64_t ns, int32_
 // highest degree; every member of such a row u lies in (u, N), a range so
 // short that the row fills a good share of it.  From the first row among the
 // last kCoreScan that holds kCoreMinRow entries or more and fills at least
-// 1/kCoreDensity of (u, N), the adjacency among those last labels is kept as bitmaps
-// too (the layout of core_origin), at most min(M, 512 MiB) bytes in all: a
-// test of one id then reads one word, and two rows meet by AND-ing words.
+// 1/kCoreDensity of (u, N), the adjacency among those last labels is kept as
+// bitmaps too (the layout of core_origin), at most min(2 M, 1 GiB) bytes in
+// all: a test of one id then reads one word, and two rows meet by AND-ing
+// words.
 constexpr int64_t kCoreScan = (int64_t)1 << 17;
 constexpr int kCoreMinRow = 32;
-constexpr int64_t kCoreMaxWords = (int64_t)1 << 27;
+constexpr int64_t kCoreMaxWords = (int64_t)1 << 28;
 
 // far[0] = max of N - u over the qualifying rows u >= u0 (0: none)
 __global__ void k_core_start(const int64_t *__restrict__ off, int64_t N, int64_t u0, int32_t *__restrict__ far) {
@@ -1746,7 +1747,7 @@ void build_core(const Packing &pk, const BuildParams &bp, Allocator &al, hipStre
     read_words(&hfar, far.p, 1, s);
     if (hfar <= 0) return;
     int64_t lo = N - hfar;
-    const int64_t cap = std::min<int64_t>(kCoreMaxWords, out.M / 4);
+    const int64_t cap = std::min<int64_t>(kCoreMaxWords, out.M / 2);
     if (core_words(N, lo) > cap) {
         int64_t a = lo, b = N;  // smallest first label whose core fits the cap
         while (a < b) {

@@ -826,16 +826,17 @@ template <int WAVES, int LMAX, int HBITS, bool IDX32, int CNT>
 struct WideLds {
     static constexpr int kCnt = CNT;
     static constexpr int kLmax = LMAX;
-    static constexpr int kAndWords = (int)((sizeof(idx_t<IDX32>) * LMAX + 4 * (LMAX + 1)) / 4);
-    // the walk's row table, or (a source of the core) the bitmap of its list
+    static constexpr int kAndWords = (int)((sizeof(idx_t<IDX32>) * LMAX + 4 * (LMAX + 1) + 4 * (1 << HBITS)) / 4);
+    // the walk's row table and hashed list, or (a source of the core met by
+    // bitmap AND) the bitmap of its list
     union {
         struct {
             idx_t<IDX32> base[LMAX];
             int32_t P[LMAX + 1];
+            int32_t key[1 << HBITS];
         };
         uint32_t vbits[kAndWords];
     };
-    int32_t key[1 << HBITS];
     int32_t cnt[CNT == 1 ? (1 << HBITS) : (1 << HBITS) / 2];  // per-node counts by slot
     int16_t tpos[LMAX];  // per target row: its target's slot (lists in LDS) or list position
     alignas(4) uint8_t flag[WAVES][kFlagBytes];
@@ -1153,10 +1154,12 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WAVE
         if (te <= 0) {
             // no resident target (slice launches only)
         } else if (a <= cap) {
-            // a source of the core whose list fills 1 / kCoreDensity of the labels
-            // above it and whose bitmap fits the LDS: AND of bitmaps
+            // a source of the core whose list fills 1 / kAndDensity of the labels
+            // above it (2 / kAndDensity per node) and whose bitmap fits the LDS:
+            // AND of bitmaps
             const bool use_and = br > 0 && s >= clo && ckw <= L_t::kAndWords &&
-                                 (int64_t)kCoreDensity * a >= (((int64_t)cwl << 5) | 31) - s;
+                                 (int64_t)(PER_NODE ? kAndDensity / 2 : kAndDensity) * a >=
+                                     (((int64_t)cwl << 5) | 31) - s;
             halve = use_and && PER_NODE;
             const bool table = !use_and;  // the walk's table
             if (rounds > 0 && table) {

@@ -248,9 +248,13 @@ struct CountDesc {
 };
 constexpr int kCoreMinProbe = 64;
 // The core starts at a row that fills at least 1 / kCoreDensity of the labels
-// above it; a source of the core meets its list by bitmap AND when its own
-// list is as dense.
-constexpr int kCoreDensity = 32;
+// above it.  A source of the core meets its list by bitmap AND when its own
+// list fills at least 1 / kAndDensity of them (total only; per node, where
+// every entry's whole row is AND-ed, 2 / kAndDensity): a list of a entries
+// among the d labels above the source otherwise costs about a * a / 2 tests
+// of single words, against a * d / 64 words AND-ed (a * d / 32 per node).
+constexpr int kCoreDensity = 128;
+constexpr int kAndDensity = 32;
 constexpr int kSampleShift = 5;
 constexpr int64_t kSampleStride = (int64_t)1 << kSampleShift;  // entries per sample (one 128-byte line)
 
