@@ -284,6 +284,7 @@ void launch_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, const 
     std::vector<tc::CountDesc> hd((size_t)ng);
     int64_t task_base = 0, med_base = 0, large_base = 0;
     int32_t workers = 0, lds_max = tc::max_lds_list(), rounds = tc::kCuckooRounds;
+    bool core = false;
     for (int32_t i = 0; i < ng; ++i) {
         const tc_graph *g = gs[i];
         tc::CountDesc &d = hd[i];
@@ -313,6 +314,7 @@ void launch_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, const 
         large_base += g->o.nbig - g->o.nmed;
         workers = std::max(workers, g->workers);
         lds_max = std::min(lds_max, g->lds_max);
+        core = core || (g->o.core.long_rows > 0 && d.bitmap_ratio > 0);
         rounds = std::min(rounds, count_rounds(g, opt));
     }
     if (descs_by_kernel) {
@@ -339,6 +341,7 @@ void launch_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, const 
     L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : lds_max;
     L.cuckoo_rounds = rounds;
     L.per_node = lay.want_tv;
+    L.core = core;
     tc::count_launch(L, s);
 }
 
@@ -619,6 +622,7 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
             L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
             L.cuckoo_rounds = count_rounds(g, opt);
             L.per_node = want_tv;
+            L.core = g->o.core.long_rows > 0 && count_bitmap(g, opt) > 0;
             g->times_used = 0;
             if (opt && opt->time_kernels == 2) {
                 const int64_t cap = tc::max_timed_workers();

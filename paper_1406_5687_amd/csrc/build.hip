@@ -1696,24 +1696,24 @@ __global__ void k_core_start(const int64_t *__restrict__ off, int64_t N, int64_t
     if (q && (int)__lane_id() == __builtin_ctzll(b)) atomicMax(far, (int32_t)(N - u));
 }
 
-// One wave per core row u: each entry x sets bit x in row u and bit u in row
-// x.  A row is sorted, so the entries of one word of row u sit in adjacent
-// lanes; their bits are OR-ed across the lanes first and each such word takes
-// one atomic OR per wave.
+// One wave per core row u: each entry x sets bit x in row u (the upper
+// triangle; k_core_mirror fills the lower one).  A row is sorted, so the
+// entries of one word sit in adjacent lanes; their bits are OR-ed across the
+// lanes first and each word takes one atomic OR per wave.
 __global__ __launch_bounds__(kThreads) void k_core_bits(const int64_t *__restrict__ off,
                                                         const int32_t *__restrict__ col, int64_t lo, int64_t N,
-                                                        int64_t kw, uint32_t *__restrict__ bm) {
+                                                        int64_t kw, uint32_t *__restrict__ bm,
+                                                        unsigned int *__restrict__ nlong) {
     const int lane = (int)__lane_id();
     const int64_t u = lo + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 64;
     if (u >= N) return;  // the whole wave
     const int64_t org = core_origin(u, lo, kw);
     const int64_t r1 = off[u + 1];
-    const uint32_t ubit = 1u << (u & 31);
+    if (lane == 0 && r1 - off[u] >= 2 * kCoreMinProbe) atomicAdd(nlong, 1u);
     for (int64_t e0 = off[u]; e0 < r1; e0 += 64) {
         const int64_t e = e0 + lane;
         const bool ok = e < r1;
         const int32_t x = ok ? col[e] : 0;
-        if (ok) atomicOr(&bm[core_origin(x, lo, kw) + (u >> 5)], ubit);
         const int32_t w = ok ? (int32_t)(org + (x >> 5)) : -1 - lane;  // distinct keys past the row
         uint32_t bits = ok ? 1u << (x & 31) : 0u;
 #pragma unroll
@@ -1725,6 +1725,47 @@ __global__ __launch_bounds__(kThreads) void k_core_bits(const int64_t *__restric
         const int32_t nw = __shfl_down(w, 1, 64);
         if (ok && (lane == 63 || nw != w)) atomicOr(&bm[w], bits);
     }
+}
+
+// The lower triangle as the mirror of the upper one, 32 x 32 bit blocks at a
+// time: block (b, c) holds rows 32 b .. 32 b + 31 (labels) and the word of
+// labels 32 c .. 32 c + 31.  Each half-wave takes one block b <= c: lane r
+// loads row 32 b + r's word c, the 32 words are transposed across the lanes in
+// five exchange rounds, and lane r writes word b of row 32 c + r (OR-ed into
+// the block itself when b == c).  Rows below lo do not exist and hold nothing.
+__global__ __launch_bounds__(kThreads) void k_core_mirror(int64_t lo, int64_t N, int64_t kw, int64_t nb,
+                                                          int64_t pairs, uint32_t *__restrict__ bm) {
+    const int r = (int)(__lane_id() & 31);
+    const int64_t t = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 5;  // block pair, b <= c
+    const bool live = t < pairs;
+    // pair t -> (b, c), row-major over the upper triangle of nb x nb blocks:
+    // counted from the end, index q lies in the row of k = nb - b pairs with
+    // k (k - 1) / 2 <= q < k (k + 1) / 2
+    const int64_t q = live ? pairs - 1 - t : 0;
+    int64_t k = (int64_t)((sqrt(8.0 * (double)q + 1.0) + 1.0) * 0.5);
+    while (k > 1 && k * (k - 1) / 2 > q) --k;
+    while (k * (k + 1) / 2 <= q) ++k;
+    const int64_t b = nb - k;
+    const int64_t c = nb - 1 - (q - k * (k - 1) / 2);
+    const int64_t b0 = lo >> 5;  // label block of word 0
+    const int64_t ru = (b0 + b) * 32 + r, rv = (b0 + c) * 32 + r;
+    const bool has_u = live && ru >= lo && ru < N, has_v = live && rv >= lo && rv < N;
+    uint32_t w = has_u ? bm[core_origin(ru, lo, kw) + b0 + c] : 0u;
+    const uint32_t orig = w;
+    // transpose: after the rounds lane r holds bit k of lane k's word at bit r
+    constexpr uint32_t kHi[5] = {0xFFFF0000u, 0xFF00FF00u, 0xF0F0F0F0u, 0xCCCCCCCCu, 0xAAAAAAAAu};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const int j = 16 >> q;
+        const uint32_t o = __shfl_xor(w, j, 32);
+        w = (r & j) ? (w & kHi[q]) | ((o & kHi[q]) >> j) : (w & ~kHi[q]) | ((o & ~kHi[q]) << j);
+    }
+    if (!has_v) return;
+    const int64_t at = core_origin(rv, lo, kw) + b0 + b;
+    if (b == c)
+        bm[at] = w | orig;  // the diagonal block: rows and bits of one label block
+    else
+        bm[at] = w;
 }
 
 // Words of the core from label lo on.
@@ -1767,9 +1808,18 @@ void build_core(const Packing &pk, const BuildParams &bp, Allocator &al, hipStre
     out.core.wl = (int32_t)((N - 1) >> 5);
     out.core.kw = (int32_t)(out.core.wl - (lo >> 5) + 1);
     out.core.words = words;
-    k_core_bits<<<(unsigned)ceil_div((N - lo) * 64, (int64_t)kThreads), kThreads, 0, s>>>(out.off.p, out.col.p, lo,
-                                                                                         N, out.core.kw, out.bm.p);
+    DevBuf<unsigned int> nlong(al, 1);
+    fill_zero(nlong.p, 4, s);
+    k_core_bits<<<(unsigned)ceil_div((N - lo) * 64, (int64_t)kThreads), kThreads, 0, s>>>(
+        out.off.p, out.col.p, lo, N, out.core.kw, out.bm.p, nlong.p);
     TC_LAUNCH_CHECK();
+    const int64_t nb = out.core.kw, pairs = nb * (nb + 1) / 2;
+    k_core_mirror<<<(unsigned)ceil_div(pairs * 32, (int64_t)kThreads), kThreads, 0, s>>>(lo, N, out.core.kw, nb,
+                                                                                       pairs, out.bm.p);
+    TC_LAUNCH_CHECK();
+    unsigned int hl = 0;
+    read_words(&hl, nlong.p, 1, s);
+    out.core.long_rows = hl;
 }
 
 void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,

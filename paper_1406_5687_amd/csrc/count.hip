@@ -591,7 +591,7 @@ __device__ __forceinline__ uint32_t core_rows_small(gptr_t<const uint32_t> bm, u
 // x0 = L[lane], x1 = L[64 + lane] (clamped copies beyond a).  The first te
 // entries are the targets (te = a - 1 for a resident adjacency); their rows
 // are off[t - row_lo] .. off[t - row_lo + 1].
-template <bool PER_NODE, bool IDX32, bool SLICE>
+template <bool PER_NODE, bool IDX32, bool SLICE, bool CORE>
 __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColReader<IDX32> &rd,
                                                  gptr_t<const int32_t> gcol, gptr_t<const int64_t> off,
                                                  int64_t *__restrict__ tv, int32_t s, int32_t a, int32_t te,
@@ -643,8 +643,8 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     // rows of the dense core tested against their bitmaps instead: at least
     // kCoreMinProbe entries and longer than br times the candidates (chosen
     // first: a test reads one word where a search reads several)
-    const bool z0 = br > 0 && l0 >= kCoreMinProbe && x0 >= clo && l0 > br * (a - 1 - lane);
-    const bool z1 = br > 0 && l1 >= kCoreMinProbe && x1 >= clo && l1 > br * (a - 65 - lane);
+    const bool z0 = CORE && br > 0 && l0 >= kCoreMinProbe && x0 >= clo && l0 > br * (a - 1 - lane);
+    const bool z1 = CORE && br > 0 && l1 >= kCoreMinProbe && x1 >= clo && l1 > br * (a - 65 - lane);
     const bool q0 = !z0 && sr != 0 && l0 > 0 && (sr < 0 || (l0 >= kStep && l0 > sr * (a - 1 - lane)));
     const bool q1 = !z1 && sr != 0 && l1 > 0 && (sr < 0 || (l1 >= kStep && l1 > sr * (a - 65 - lane)));
     const int32_t b0 = (q0 || z0) ? 0 : l0, b1 = (q1 || z1) ? 0 : l1;
@@ -676,13 +676,16 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     wave_lds_sync();
 
     uint32_t hits = npairs ? search_pairs<PER_NODE, IDX32>(S, rd, npairs, ns, a, x0, x1, samp, ebase) : 0u;
-    int32_t zc0 = 0, zc1 = 0;  // per-node counts of the core tests
     {
         const uint64_t Z0 = __ballot(z0), Z1 = __ballot(z1);
         if (Z0 | Z1) {
+            int32_t zc0 = 0, zc1 = 0;  // per-node counts of the core tests
             const int32_t o0 = z0 ? (int32_t)core_origin(x0, clo, ckw) : 0;
             const int32_t o1 = z1 ? (int32_t)core_origin(x1, clo, ckw) : 0;
             hits += core_rows_small<PER_NODE>(bm, Z0, Z1, o0, o1, a, x0, x1, zc0, zc1);
+            // into the position counters before the walk adds to them
+            if (PER_NODE && h0) S.cnt[lane] += zc0;
+            if (PER_NODE && h1) S.cnt[64 + lane] += zc1;
         }
     }
     const int32_t e_end = ((total + kStep - 1) / kStep) * kStep;
@@ -696,14 +699,14 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
         const uint64_t hs = wave_sum((uint64_t)hits);
         wave_lds_sync();
         if (h0) {
-            const int32_t c = S.cnt[lane] + zc0;
+            const int32_t c = S.cnt[lane];
             if (c) {
                 add_u64(&tv[x0], (uint64_t)c);
                 S.cnt[lane] = 0;
             }
         }
         if (h1) {
-            const int32_t c = S.cnt[64 + lane] + zc1;
+            const int32_t c = S.cnt[64 + lane];
             if (c) {
                 add_u64(&tv[x1], (uint64_t)c);
                 S.cnt[64 + lane] = 0;
@@ -720,7 +723,10 @@ __device__ __forceinline__ uint64_t source_small(SmallLds<IDX32> &S, const ColRe
     return (uint64_t)hits;
 }
 
-template <bool PER_NODE, bool IDX32, bool SLICE>
+// CORE: the core's bit tests compiled in (launched only for handles whose
+// core has rows long enough to take them; the code costs the other lists'
+// walk a few registers).
+template <bool PER_NODE, bool IDX32, bool SLICE, bool CORE>
 __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_count_small(
     const CountDesc *__restrict__ descs, int ndesc, int64_t total_tasks, uint32_t *__restrict__ head, int nworkers,
     unsigned long long *__restrict__ times, int rounds) {
@@ -761,7 +767,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
         // slices hold no samples of their rows
         const gptr_t<const int32_t> samp = gview(SLICE ? (const int32_t *)nullptr : descs[h].samp);
         // nor a core
-        const gptr_t<const uint32_t> bm = gview(SLICE ? (const uint32_t *)nullptr : descs[h].bm);
+        const gptr_t<const uint32_t> bm = gview(SLICE || !CORE ? (const uint32_t *)nullptr : descs[h].bm);
         const int32_t br = bm ? uniform32(descs[h].bitmap_ratio) : 0;
         const int32_t clo = uniform32(descs[h].core_lo), cwl = uniform32(descs[h].core_wl);
         const int32_t ckw = uniform32(descs[h].core_kw);
@@ -795,7 +801,7 @@ __global__ __launch_bounds__(kSmallWaves * 64) __attribute__((amdgpu_waves_per_e
                 const int32_t nx1 = col[rn + min(lane + 64, an - 1)];
                 const int32_t te = readlane32(tl, j);
                 const int32_t sl = SLICE ? readlane32(lab, j) : s0 + j;
-                tri += source_small<PER_NODE, IDX32, SLICE>(S, rd, col, off, tv, sl, a, te, row_lo, ebase, x0, x1,
+                tri += source_small<PER_NODE, IDX32, SLICE, CORE>(S, rd, col, off, tv, sl, a, te, row_lo, ebase, x0, x1,
                                                             lane, sr, rounds, samp, bm, br, clo, cwl, ckw);
                 j = jn;
                 a = an;
@@ -1316,14 +1322,15 @@ void launch_all(CountLaunch &L, int lds_max, hipStream_t s) {
         // never launch more workers than can be resident at once: a worker that
         // starts late would hold its first task until the end
         int per_cu = 0;
-        TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_count_small<PER_NODE, IDX32, SLICE>,
-                                                            kSmallWaves * 64, 0));
+        auto kern = L.core && !SLICE ? k_count_small<PER_NODE, IDX32, SLICE, true>
+                                     : k_count_small<PER_NODE, IDX32, SLICE, false>;
+        TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kSmallWaves * 64, 0));
         const int64_t resident = (int64_t)std::max(1, per_cu) * cus;
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(L.workers, kSmallWaves), resident));
         unsigned long long *tm = times_for((int64_t)blocks * kSmallWaves);
         L.times_tier[0] = tm ? (int64_t)blocks * kSmallWaves : 0;
-        k_count_small<PER_NODE, IDX32, SLICE><<<blocks, kSmallWaves * 64, 0, s>>>(
-            L.descs, L.ndesc, L.total_tasks, L.heads, blocks * kSmallWaves, tm, L.cuckoo_rounds);
+        kern<<<blocks, kSmallWaves * 64, 0, s>>>(L.descs, L.ndesc, L.total_tasks, L.heads, blocks * kSmallWaves, tm,
+                                                 L.cuckoo_rounds);
         TC_LAUNCH_CHECK();
     }
     if (L.total_med > 0) {
@@ -1365,10 +1372,10 @@ int small_kernel_waves_per_cu(bool per_node) {
     if (!c) {
         int blocks = 0;
         if (per_node)
-            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<true, false, false>,
+            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<true, false, false, false>,
                                                                 kSmallWaves * 64, 0));
         else
-            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<false, false, false>,
+            TC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_count_small<false, false, false, false>,
                                                                 kSmallWaves * 64, 0));
         c = std::max(1, blocks) * kSmallWaves;
     }
