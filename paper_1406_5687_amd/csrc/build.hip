@@ -733,11 +733,59 @@ __global__ void k_orient_pairs(const int32_t *__restrict__ src, const int32_t *_
 // threads make kRadixTile / kOrientTileThreads keys each.
 constexpr int kOrientTileThreads = 512;
 constexpr int kOrientTileWaves = kOrientTileThreads / 64;
-__global__ __launch_bounds__(kOrientTileThreads) void k_orient_pairs_hist(const int32_t *__restrict__ src,
-                                                           const int32_t *__restrict__ dst, int64_t m, int gb,
-                                                           const int32_t *__restrict__ rank,
-                                                           uint64_t *__restrict__ okeys, int shift, int bits,
-                                                           int64_t tiles, uint32_t *__restrict__ hist) {
+// Adds one round of a tile's digits to the wave's LDS table: lanes holding
+// the same digit (all of them when the first lane's digit is everyone's,
+// else found with one ballot per digit bit) are counted by the first of
+// them, so no counter gets two writes in a round.  d = 256: no key.
+__device__ __forceinline__ void tile_digit_round(uint32_t *hw, uint32_t d, int bits, bool full) {
+    const int lane = __lane_id();
+    const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
+    uint64_t peers = ~0ull;
+    if (__ballot(d == d0) != ~0ull) {
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            if (b < bits) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bal = __ballot(bit);
+                peers &= bit ? bal : ~bal;
+            }
+        }
+        if (!full) {
+            const bool past = d >> 8;
+            const uint64_t bal = __ballot(past);
+            peers &= past ? bal : ~bal;
+        }
+    }
+    if (d < 256u && lane == __ffsll((unsigned long long)peers) - 1) hw[d] += (uint32_t)popc64(peers);
+    wave_lds_sync();
+}
+
+// The tile's digit counts, summed over the waves' tables, into the
+// digit-major table of the first radix pass.
+template <int WAVES>
+__device__ __forceinline__ void tile_digit_flush(uint32_t (*hw)[256], int64_t t, int64_t tiles,
+                                                 uint32_t *__restrict__ hist) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 256; i += WAVES * 64) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) c += hw[w][i];
+        hist[(int64_t)i * tiles + t] = c;
+    }
+}
+
+// Oriented keys (min label << gb) | max label under rank, of the pairs
+// (src[i], dst[i]) (KEYS false) or of the pair keys (lo << gb) | hi (KEYS
+// true), written in the first radix pass's tiles together with that pass's
+// digit table (bits [shift, shift + bits) of the keys), so the pass does not
+// read the keys to count them.
+template <bool KEYS>
+__global__ __launch_bounds__(kOrientTileThreads) void k_orient_hist(const int32_t *__restrict__ src,
+                                                                    const int32_t *__restrict__ dst,
+                                                                    const uint64_t *__restrict__ ukeys, int64_t m,
+                                                                    int gb, const int32_t *__restrict__ rank,
+                                                                    uint64_t *__restrict__ okeys, int shift, int bits,
+                                                                    int64_t tiles, uint32_t *__restrict__ hist) {
     constexpr int kRounds = kRadixTile / kOrientTileThreads;
     __shared__ uint32_t hw[kOrientTileWaves][256];  // one table per wave
     for (int i = threadIdx.x; i < kOrientTileWaves * 256; i += kOrientTileThreads) (&hw[0][0])[i] = 0u;
@@ -747,13 +795,20 @@ __global__ __launch_bounds__(kOrientTileThreads) void k_orient_pairs_hist(const 
     const int64_t base = t * kRadixTile + (int64_t)wave * (64 * kRounds) + lane;
     const bool full = m - t * kRadixTile >= kRadixTile;  // every lane holds a key
     const uint32_t dmask = (1u << bits) - 1u;
+    const uint64_t lmask = (1ull << gb) - 1;
     // all endpoints are loaded, then all ranks gathered, before any key is made
     int32_t u[kRounds], v[kRounds];
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int64_t i = base + r * 64;
-        u[r] = i < m ? __builtin_nontemporal_load(&src[i]) : 0;
-        v[r] = i < m ? __builtin_nontemporal_load(&dst[i]) : 0;
+        if (KEYS) {
+            const uint64_t k = i < m ? __builtin_nontemporal_load(&ukeys[i]) : 0;
+            u[r] = (int32_t)(k >> gb);
+            v[r] = (int32_t)(k & lmask);
+        } else {
+            u[r] = i < m ? __builtin_nontemporal_load(&src[i]) : 0;
+            v[r] = i < m ? __builtin_nontemporal_load(&dst[i]) : 0;
+        }
     }
 #pragma unroll
     for (int r = 0; r < kRounds; ++r) {
@@ -767,37 +822,61 @@ __global__ __launch_bounds__(kOrientTileThreads) void k_orient_pairs_hist(const 
         const uint32_t ra = (uint32_t)u[r], rb = (uint32_t)v[r];
         const uint64_t key = ((uint64_t)(ra < rb ? ra : rb) << gb) | (ra < rb ? rb : ra);
         if (i < m) __builtin_nontemporal_store(key, &okeys[i]);
-        const uint32_t d = i < m ? (uint32_t)(key >> shift) & dmask : 256u;  // 256: past the end
-        // lanes holding the same digit (all of them when the first lane's
-        // digit is everyone's, else one ballot per digit bit); the first of
-        // them adds their number, so no counter gets two writes in a round
-        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)d);
-        uint64_t peers = ~0ull;
-        if (__ballot(d == d0) != ~0ull) {
-#pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                if (b < bits) {
-                    const bool bit = (d >> b) & 1u;
-                    const uint64_t bal = __ballot(bit);
-                    peers &= bit ? bal : ~bal;
-                }
-            }
-            if (!full) {
-                const bool past = d >> 8;
-                const uint64_t bal = __ballot(past);
-                peers &= past ? bal : ~bal;
-            }
-        }
-        if (d < 256u && lane == __ffsll((unsigned long long)peers) - 1) hw[wave][d] += (uint32_t)popc64(peers);
-        wave_lds_sync();
+        tile_digit_round(hw[wave], i < m ? (uint32_t)(key >> shift) & dmask : 256u, bits, full);
     }
+    tile_digit_flush<kOrientTileWaves>(hw, t, tiles, hist);
+}
+
+// Step 1a as k_edge_keys, in the first radix pass's tiles with that pass's
+// digit table (bits [0, bits) of the keys; a dropped pair's key kInvalid has
+// every bit set): the canonical path sorts the keys next.
+__global__ __launch_bounds__(kOrientTileThreads) void k_edge_keys_hist(
+    const int32_t *__restrict__ src, const int32_t *__restrict__ dst, int64_t m_in,
+    const int64_t *__restrict__ edge_base, const int64_t *__restrict__ node_base, int k, int gb,
+    uint64_t *__restrict__ keys, uint32_t *__restrict__ err, int bits, int64_t tiles,
+    uint32_t *__restrict__ hist) {
+    constexpr int kRounds = kRadixTile / kOrientTileThreads;
+    __shared__ uint32_t hw[kOrientTileWaves][256];
+    for (int i = threadIdx.x; i < kOrientTileWaves * 256; i += kOrientTileThreads) (&hw[0][0])[i] = 0u;
     __syncthreads();
-    for (int i = threadIdx.x; i < 256; i += kOrientTileThreads) {
-        uint32_t c = 0;
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    const int64_t t = xcd_tile(blockIdx.x, tiles);
+    const int64_t base = t * kRadixTile + (int64_t)wave * (64 * kRounds) + lane;
+    const bool full = m_in - t * kRadixTile >= kRadixTile;
+    const int64_t b1 = k == 1 ? node_base[0] : 0, n1 = k == 1 ? node_base[1] - b1 : 0;  // the one graph
+    int32_t u[kRounds], v[kRounds];
 #pragma unroll
-        for (int w = 0; w < kOrientTileWaves; ++w) c += hw[w][i];
-        hist[(int64_t)i * tiles + t] = c;
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t e = base + r * 64;
+        u[r] = e < m_in ? __builtin_nontemporal_load(&src[e]) : 0;
+        v[r] = e < m_in ? __builtin_nontemporal_load(&dst[e]) : 0;
     }
+    uint32_t bad = 0;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int64_t e = base + r * 64;
+        int64_t nb = b1, ng = n1;
+        if (k != 1 && e < m_in) {
+            const int g = upper_bound_i64(edge_base, k + 1, e) - 1;
+            nb = node_base[g];
+            ng = node_base[g + 1] - nb;
+        }
+        uint64_t key = kInvalid;
+        if (e < m_in) {
+            if (u[r] < 0 || v[r] < 0 || u[r] >= ng || v[r] >= ng) {
+                bad |= 1u;
+            } else if (u[r] == v[r]) {
+                bad |= 2u;  // a loop: dropped
+            } else {
+                const int32_t lo = u[r] < v[r] ? u[r] : v[r], hi = u[r] < v[r] ? v[r] : u[r];
+                key = ((uint64_t)(nb + lo) << gb) | (uint64_t)(nb + hi);
+            }
+            keys[e] = key;
+        }
+        tile_digit_round(hw[wave], e < m_in ? (uint32_t)key & ((1u << bits) - 1u) : 256u, bits, full);
+    }
+    if (bad) atomicOr(err, bad);
+    tile_digit_flush<kOrientTileWaves>(hw, t, tiles, hist);
 }
 
 // Step 5b: rows sorted ascending.  The pair sort above orders by s only, so
@@ -1917,8 +1996,18 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
         runs_dst = (int64_t)bd * 4 <= M_in;
         M = M_in;
     } else if (M_in > 0) {
-        k_edge_keys<<<grid_for(M_in, 4 * kEdgeUnroll), kThreads, 0, s>>>(src, dst, M_in, edge_base.p,
-                                                                          out.node_base.p, k, gb, ka.p, err.p);
+        // the canonical path sorts the keys next: they come with the first
+        // radix pass's digit table
+        const int64_t tiles = ceil_div(M_in, (int64_t)kRadixTile);
+        const int bits0 = std::min(8, 2 * gb);
+        DevBuf<uint32_t> h0(tmp, simple ? 1 : (size_t)tiles * 256);
+        if (simple) {
+            k_edge_keys<<<grid_for(M_in, 4 * kEdgeUnroll), kThreads, 0, s>>>(src, dst, M_in, edge_base.p,
+                                                                              out.node_base.p, k, gb, ka.p, err.p);
+        } else {
+            k_edge_keys_hist<<<(unsigned)tiles, kOrientTileThreads, 0, s>>>(
+                src, dst, M_in, edge_base.p, out.node_base.p, k, gb, ka.p, err.p, bits0, tiles, h0.p);
+        }
         TC_LAUNCH_CHECK();
         uint32_t herr = 0;
         if (simple) {
@@ -1929,7 +2018,7 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
             M = M_in;
             ukeys = ka.p;
         } else {
-            uint64_t *sorted = radix_sort_u64(ka.p, kb.p, M_in, 0, 2 * gb, tmp, s);
+            uint64_t *sorted = radix_sort_u64_hist(ka.p, kb.p, M_in, 0, 2 * gb, h0.p, tmp, s);
             uint64_t *other = sorted == ka.p ? kb.p : ka.p;
             M = unique_sorted_keys(sorted, M_in, other, &ukeys, tmp, s);  // synchronises
             d2h(&herr, err.p, 1, s);
@@ -1964,14 +2053,18 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
     if (M > 0) {
         // order by s >> kGroupBits, then place each group of rows (in key
         // order inside a row: rows are sorted below)
-        if (pairs && gb > kGroupBits) {
+        if (gb > kGroupBits) {
             // the keys come out in the radix passes' tiles with the first
             // pass's digit table, so that pass does not read them to count
             const int64_t tiles = ceil_div(M, (int64_t)kRadixTile);
             const int shift = gb + kGroupBits, bits = std::min(8, 2 * gb - shift);
             DevBuf<uint32_t> h1(tmp, (size_t)tiles * 256);
-            k_orient_pairs_hist<<<(unsigned)tiles, kOrientTileThreads, 0, s>>>(src, dst, M, gb, rank.p, spare, shift,
-                                                                                bits, tiles, h1.p);
+            if (pairs)
+                k_orient_hist<false><<<(unsigned)tiles, kOrientTileThreads, 0, s>>>(
+                    src, dst, nullptr, M, gb, rank.p, spare, shift, bits, tiles, h1.p);
+            else
+                k_orient_hist<true><<<(unsigned)tiles, kOrientTileThreads, 0, s>>>(
+                    nullptr, nullptr, ukeys, M, gb, rank.p, spare, shift, bits, tiles, h1.p);
             TC_LAUNCH_CHECK();
             okeys = radix_sort_u64_hist(spare, ukeys, M, shift, 2 * gb, h1.p, tmp, s);
         } else {
@@ -1980,7 +2073,7 @@ static bool build_pass(const int32_t *src, const int32_t *dst, const Packing &pk
             else
                 k_orient_keys<<<grid_for(M, 4 * kOrientUnroll), kThreads, 0, s>>>(ukeys, M, gb, rank.p, spare);
             TC_LAUNCH_CHECK();
-            okeys = gb > kGroupBits ? radix_sort_u64(spare, ukeys, M, gb + kGroupBits, 2 * gb, tmp, s) : spare;
+            okeys = spare;  // one group: no sort
         }
         const int64_t ngroups = ceil_div(N, (int64_t)kGroupRows);
         DevBuf<int64_t> gstart(tmp, (size_t)ngroups + 1);
