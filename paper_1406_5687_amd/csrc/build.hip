@@ -1806,32 +1806,9 @@ __global__ __launch_bounds__(kThreads) void k_core_bits(const int64_t *__restric
     }
 }
 
-// The lower triangle as the mirror of the upper one, 32 x 32 bit blocks at a
-// time: block (b, c) holds rows 32 b .. 32 b + 31 (labels) and the word of
-// labels 32 c .. 32 c + 31.  Each half-wave takes one block b <= c: lane r
-// loads row 32 b + r's word c, the 32 words are transposed across the lanes in
-// five exchange rounds, and lane r writes word b of row 32 c + r (OR-ed into
-// the block itself when b == c).  Rows below lo do not exist and hold nothing.
-__global__ __launch_bounds__(kThreads) void k_core_mirror(int64_t lo, int64_t N, int64_t kw, int64_t nb,
-                                                          int64_t pairs, uint32_t *__restrict__ bm) {
-    const int r = (int)(__lane_id() & 31);
-    const int64_t t = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 5;  // block pair, b <= c
-    const bool live = t < pairs;
-    // pair t -> (b, c), row-major over the upper triangle of nb x nb blocks:
-    // counted from the end, index q lies in the row of k = nb - b pairs with
-    // k (k - 1) / 2 <= q < k (k + 1) / 2
-    const int64_t q = live ? pairs - 1 - t : 0;
-    int64_t k = (int64_t)((sqrt(8.0 * (double)q + 1.0) + 1.0) * 0.5);
-    while (k > 1 && k * (k - 1) / 2 > q) --k;
-    while (k * (k + 1) / 2 <= q) ++k;
-    const int64_t b = nb - k;
-    const int64_t c = nb - 1 - (q - k * (k - 1) / 2);
-    const int64_t b0 = lo >> 5;  // label block of word 0
-    const int64_t ru = (b0 + b) * 32 + r, rv = (b0 + c) * 32 + r;
-    const bool has_u = live && ru >= lo && ru < N, has_v = live && rv >= lo && rv < N;
-    uint32_t w = has_u ? bm[core_origin(ru, lo, kw) + b0 + c] : 0u;
-    const uint32_t orig = w;
-    // transpose: after the rounds lane r holds bit k of lane k's word at bit r
+// 32 x 32 bit transpose across the 32 lanes of a half-wave: lane r holds row
+// r; afterwards lane r holds bit r of every row k at bit k.
+__device__ __forceinline__ uint32_t transpose32(uint32_t w, int r) {
     constexpr uint32_t kHi[5] = {0xFFFF0000u, 0xFF00FF00u, 0xF0F0F0F0u, 0xCCCCCCCCu, 0xAAAAAAAAu};
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
@@ -1839,12 +1816,74 @@ __global__ __launch_bounds__(kThreads) void k_core_mirror(int64_t lo, int64_t N,
         const uint32_t o = __shfl_xor(w, j, 32);
         w = (r & j) ? (w & kHi[q]) | ((o & kHi[q]) >> j) : (w & ~kHi[q]) | ((o & ~kHi[q]) << j);
     }
-    if (!has_v) return;
-    const int64_t at = core_origin(rv, lo, kw) + b0 + b;
-    if (b == c)
-        bm[at] = w | orig;  // the diagonal block: rows and bits of one label block
-    else
-        bm[at] = w;
+    return w;
+}
+
+// Index t of the upper triangle (b <= c) of an n x n grid, row-major, as (b, c):
+// counted from the end, q = pairs - 1 - t lies in the row of k = n - b pairs
+// with k (k - 1) / 2 <= q < k (k + 1) / 2.
+__device__ __forceinline__ void upper_pair(int64_t t, int64_t n, int64_t *b, int64_t *c) {
+    const int64_t q = n * (n + 1) / 2 - 1 - t;
+    int64_t k = (int64_t)((sqrt(8.0 * (double)q + 1.0) + 1.0) * 0.5);
+    while (k > 1 && k * (k - 1) / 2 > q) --k;
+    while (k * (k + 1) / 2 <= q) ++k;
+    *b = n - k;
+    *c = n - 1 - (q - k * (k - 1) / 2);
+}
+
+// The lower triangle as the mirror of the upper one.  Block (b, c) holds the
+// rows of labels 32 (b0 + b) .. + 31 and their word of labels 32 (b0 + c) ..
+// + 31 (b0 = lo >> 5).  A workgroup takes a tile of kMirG x kMirG blocks, row
+// blocks B kMirG .. and word columns C kMirG .. with B <= C: it stages the tile
+// in LDS (each row's kMirG words read together), transposes every block in
+// place, half-wave by half-wave (blocks (i, j) and (j, i) swap their
+// transposes), and writes the result as the tile of row blocks C kMirG .. and
+// word columns B kMirG .. (a tile on the diagonal: OR-ed into itself, its
+// upper blocks then holding both halves).  Rows below lo do not exist.
+constexpr int kMirG = 16;
+constexpr int kMirRows = 32 * kMirG;
+constexpr int kMirPad = kMirG + 1;  // LDS row stride: the block reads hit distinct banks
+
+__global__ __launch_bounds__(kThreads) void k_core_mirror(int64_t lo, int64_t N, int64_t kw, int64_t nb,
+                                                          int64_t ng, uint32_t *__restrict__ bm) {
+    __shared__ uint32_t A[kMirRows * kMirPad];
+    int64_t B, C;
+    upper_pair(blockIdx.x, ng, &B, &C);
+    const bool diag = B == C;
+    const int64_t b0 = lo >> 5;
+    for (int idx = threadIdx.x; idx < kMirRows * kMirG; idx += kThreads) {
+        const int row = idx / kMirG, col = idx % kMirG;
+        const int64_t bi = B * kMirG + row / 32, cj = C * kMirG + col;
+        const int64_t ru = (b0 + bi) * 32 + (row & 31);
+        uint32_t w = 0u;
+        if (bi < nb && cj < nb && ru >= lo && ru < N) w = bm[core_origin(ru, lo, kw) + b0 + cj];
+        A[row * kMirPad + col] = w;
+    }
+    __syncthreads();
+    const int r = (int)(threadIdx.x & 31);
+    for (int p = (int)(threadIdx.x >> 5); p < kMirG * (kMirG + 1) / 2; p += kThreads / 32) {
+        int i = 0, rem = p;  // p -> (i, j), i <= j
+        while (rem >= kMirG - i) {
+            rem -= kMirG - i;
+            ++i;
+        }
+        const int j = i + rem;
+        const uint32_t x = A[(i * 32 + r) * kMirPad + j], y = A[(j * 32 + r) * kMirPad + i];
+        const uint32_t tx = transpose32(x, r), ty = transpose32(y, r);
+        if (i == j) {
+            A[(i * 32 + r) * kMirPad + j] = diag ? x | tx : tx;
+        } else {
+            A[(i * 32 + r) * kMirPad + j] = diag ? x | ty : ty;
+            A[(j * 32 + r) * kMirPad + i] = diag ? y | tx : tx;
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kMirRows * kMirG; idx += kThreads) {
+        const int row = idx / kMirG, col = idx % kMirG;
+        const int64_t bi = C * kMirG + row / 32, cj = B * kMirG + col;
+        const int64_t rv = (b0 + bi) * 32 + (row & 31);
+        if (bi < nb && cj < nb && rv >= lo && rv < N) bm[core_origin(rv, lo, kw) + b0 + cj] = A[row * kMirPad + col];
+    }
 }
 
 // Words of the core from label lo on.
@@ -1892,9 +1931,8 @@ void build_core(const Packing &pk, const BuildParams &bp, Allocator &al, hipStre
     k_core_bits<<<(unsigned)ceil_div((N - lo) * 64, (int64_t)kThreads), kThreads, 0, s>>>(
         out.off.p, out.col.p, lo, N, out.core.kw, out.bm.p, nlong.p);
     TC_LAUNCH_CHECK();
-    const int64_t nb = out.core.kw, pairs = nb * (nb + 1) / 2;
-    k_core_mirror<<<(unsigned)ceil_div(pairs * 32, (int64_t)kThreads), kThreads, 0, s>>>(lo, N, out.core.kw, nb,
-                                                                                       pairs, out.bm.p);
+    const int64_t nb = out.core.kw, ng = ceil_div(nb, (int64_t)kMirG);
+    k_core_mirror<<<(unsigned)(ng * (ng + 1) / 2), kThreads, 0, s>>>(lo, N, out.core.kw, nb, ng, out.bm.p);
     TC_LAUNCH_CHECK();
     unsigned int hl = 0;
     read_words(&hl, nlong.p, 1, s);
