@@ -124,7 +124,8 @@ typedef struct {
     int32_t bitmap_ratio; /* dense core (Fig. 1: the test w in N_u, turned around): a one-graph
                              handle built without a budget keeps the rows of its last nodes in
                              the degree order (those of highest degree, whose rows fill a good
-                             share of the few labels above them) as bitmaps too.  With
+                             share of the few labels above them) as bitmaps too, when one of
+                             those rows holds 128 entries or more.  With
                              TC_INTERSECT_AUTO, a target row of the core holding 64 entries or
                              more that is longer than bitmap_ratio times the entries of N_v
                              after u (the only candidates) is not read: each candidate is tested

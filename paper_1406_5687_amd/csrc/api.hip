@@ -314,7 +314,7 @@ void launch_batch(tc_graph *const *gs, int32_t ng, const tc_options *opt, const 
         large_base += g->o.nbig - g->o.nmed;
         workers = std::max(workers, g->workers);
         lds_max = std::min(lds_max, g->lds_max);
-        core = core || (g->o.core.long_rows > 0 && d.bitmap_ratio > 0);
+        core = core || d.bitmap_ratio > 0;
         rounds = std::min(rounds, count_rounds(g, opt));
     }
     if (descs_by_kernel) {
@@ -622,7 +622,7 @@ static tc_status count_one(tc_graph *g, const tc_options *opt, int64_t *per_node
             L.lds_max = opt && opt->lds_list_max > 0 ? opt->lds_list_max : g->lds_max;
             L.cuckoo_rounds = count_rounds(g, opt);
             L.per_node = want_tv;
-            L.core = g->o.core.long_rows > 0 && count_bitmap(g, opt) > 0;
+            L.core = g->o.bm.p && count_bitmap(g, opt) > 0;
             g->times_used = 0;
             if (opt && opt->time_kernels == 2) {
                 const int64_t cap = tc::max_timed_workers();

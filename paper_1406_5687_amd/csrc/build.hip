@@ -1762,17 +1762,21 @@ constexpr int64_t kCoreScan = (int64_t)1 << 17;
 constexpr int kCoreMinRow = 32;
 constexpr int64_t kCoreMaxWords = (int64_t)1 << 28;
 
-// far[0] = max of N - u over the qualifying rows u >= u0 (0: none)
+// far[0] = max of N - u over the qualifying rows u >= u0 (0: none); far[1] =
+// 1 + the last row u >= u0 of 2 kCoreMinProbe entries or more (0: none)
 __global__ void k_core_start(const int64_t *__restrict__ off, int64_t N, int64_t u0, int32_t *__restrict__ far) {
     const int64_t u = u0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool q = false;
+    bool q = false, lng = false;
     if (u < N) {
         const int64_t L = off[u + 1] - off[u];
         q = L >= kCoreMinRow && kCoreDensity * L >= N - 1 - u;
+        lng = L >= 2 * kCoreMinProbe;
     }
-    const uint64_t b = __ballot(q);
-    // the first qualifying lane of the wave holds its smallest row
-    if (q && (int)__lane_id() == __builtin_ctzll(b)) atomicMax(far, (int32_t)(N - u));
+    const uint64_t b = __ballot(q), bl = __ballot(lng);
+    // the first qualifying lane of the wave holds its smallest row, the last
+    // long one its largest
+    if (q && (int)__lane_id() == __builtin_ctzll(b)) atomicMax(&far[0], (int32_t)(N - u));
+    if (lng && (int)__lane_id() == 63 - __builtin_clzll(bl)) atomicMax(&far[1], (int32_t)(u + 1));
 }
 
 // One wave per core row u: each entry x sets bit x in row u (the upper
@@ -1781,14 +1785,12 @@ __global__ void k_core_start(const int64_t *__restrict__ off, int64_t N, int64_t
 // lanes first and each word takes one atomic OR per wave.
 __global__ __launch_bounds__(kThreads) void k_core_bits(const int64_t *__restrict__ off,
                                                         const int32_t *__restrict__ col, int64_t lo, int64_t N,
-                                                        int64_t kw, uint32_t *__restrict__ bm,
-                                                        unsigned int *__restrict__ nlong) {
+                                                        int64_t kw, uint32_t *__restrict__ bm) {
     const int lane = (int)__lane_id();
     const int64_t u = lo + ((int64_t)blockIdx.x * kThreads + threadIdx.x) / 64;
     if (u >= N) return;  // the whole wave
     const int64_t org = core_origin(u, lo, kw);
     const int64_t r1 = off[u + 1];
-    if (lane == 0 && r1 - off[u] >= 2 * kCoreMinProbe) atomicAdd(nlong, 1u);
     for (int64_t e0 = off[u]; e0 < r1; e0 += 64) {
         const int64_t e = e0 + lane;
         const bool ok = e < r1;
@@ -1892,20 +1894,23 @@ inline int64_t core_words(int64_t N, int64_t lo) {
 }
 
 // Builds the core of a one-graph handle without a device budget (else none).
+// A core none of whose rows holds 2 kCoreMinProbe entries is left out: its
+// rows are too short for the bit tests, and no list in it is long enough for
+// the workgroup kernels' AND.
 void build_core(const Packing &pk, const BuildParams &bp, Allocator &al, hipStream_t s, Oriented &out) {
     const int64_t N = pk.N;
     out.core = Oriented::CoreLayout{};
     out.core.lo = (int32_t)N;
     if (!bp.core || pk.k != 1 || al.budget || out.M == 0 || N < 2) return;
     const int64_t u0 = std::max<int64_t>(0, N - kCoreScan);
-    DevBuf<int32_t> far(al, 1);
-    fill_zero(far.p, 4, s);
+    DevBuf<int32_t> far(al, 2);
+    fill_zero(far.p, 8, s);
     k_core_start<<<grid_for(N - u0), kThreads, 0, s>>>(out.off.p, N, u0, far.p);
     TC_LAUNCH_CHECK();
-    int32_t hfar = 0;
-    read_words(&hfar, far.p, 1, s);
-    if (hfar <= 0) return;
-    int64_t lo = N - hfar;
+    int32_t hfar[2] = {0, 0};
+    read_words(hfar, far.p, 2, s);
+    if (hfar[0] <= 0) return;
+    int64_t lo = N - hfar[0];
     const int64_t cap = std::min<int64_t>(kCoreMaxWords, out.M / 2);
     if (core_words(N, lo) > cap) {
         int64_t a = lo, b = N;  // smallest first label whose core fits the cap
@@ -1919,24 +1924,19 @@ void build_core(const Packing &pk, const BuildParams &bp, Allocator &al, hipStre
         lo = a;
     }
     const int64_t words = core_words(N, lo);
-    if (lo >= N || words <= 0) return;
+    if (lo >= N || words <= 0 || (int64_t)hfar[1] - 1 < lo) return;
     out.bm = DevBuf<uint32_t>(al, (size_t)words);
     fill_zero(out.bm.p, (size_t)words * 4, s);
     out.core.lo = (int32_t)lo;
     out.core.wl = (int32_t)((N - 1) >> 5);
     out.core.kw = (int32_t)(out.core.wl - (lo >> 5) + 1);
     out.core.words = words;
-    DevBuf<unsigned int> nlong(al, 1);
-    fill_zero(nlong.p, 4, s);
     k_core_bits<<<(unsigned)ceil_div((N - lo) * 64, (int64_t)kThreads), kThreads, 0, s>>>(
-        out.off.p, out.col.p, lo, N, out.core.kw, out.bm.p, nlong.p);
+        out.off.p, out.col.p, lo, N, out.core.kw, out.bm.p);
     TC_LAUNCH_CHECK();
     const int64_t nb = out.core.kw, ng = ceil_div(nb, (int64_t)kMirG);
     k_core_mirror<<<(unsigned)(ng * (ng + 1) / 2), kThreads, 0, s>>>(lo, N, out.core.kw, nb, ng, out.bm.p);
     TC_LAUNCH_CHECK();
-    unsigned int hl = 0;
-    read_words(&hl, nlong.p, 1, s);
-    out.core.long_rows = hl;
 }
 
 void build_oriented_device(const int32_t *src, const int32_t *dst, const Packing &pk, const BuildParams &bp,

@@ -83,7 +83,6 @@ struct Oriented {
         int32_t wl = 0;   // (N - 1) >> 5: the last word of a row
         int32_t kw = 0;   // words per row: wl - (lo >> 5) + 1
         int64_t words = 0;
-        int64_t long_rows = 0;  // core rows of 2 * kCoreMinProbe entries or more
     } core;
 };
 
@@ -276,7 +275,7 @@ struct CountLaunch {
     int32_t cuckoo_rounds;  // two-choice table eviction limit; 0 = linear probing
     bool per_node;
     bool slice;  // descriptors are slice launches (32-bit row addressing)
-    bool core = false;  // some descriptor's core has rows for the one-wave kernel's bit tests
+    bool core = false;  // some descriptor has a core and asks for its bit tests
     // optional per-worker (start, finish) timestamps, wall-clock ticks: small-list
     // waves first, then the workgroups of each tier; capacity in pairs
     unsigned long long *times = nullptr;
